@@ -1,0 +1,186 @@
+/*
+ * esp.h -- long-range (k-space) electrostatics by Ewald summation with
+ * prolate spheroidal wave functions (ESP), on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Methods, "A general Ewald split", eq. task): N point charges q_i at
+ * r_i in a cubic periodic box of side L, sum q_i = 0, kernel 1/(4 pi r)
+ * (nondimensionalised; multiply by the Coulomb constant of your unit system).
+ * The library evaluates the spectral (smooth, long-range) part of the split
+ * 1/(4 pi r) = S(r) + L(r) (eq. kernelsplitting) with the PSWF splitting kernel
+ * (eq. pswf), using the five-step method (eqs. spread, FFT, diagonal scaling,
+ * IFFT, interp) with the influence function of eq. pk and analytic-derivative
+ * forces. For each particle it returns
+ *     phi_i = u~^s_i - q_i S(0)                  (self-corrected potential),
+ *     F_i   = -q_i grad u~^s(r_i)                (AD forces),
+ *     E     = (1/2) sum_i q_i phi_i              (computed in k-space, FP64).
+ * Adding the local part u^l_i (eq. localpart, kernel L(r) for r < rc, zero
+ * beyond; see esp_local_kernel) gives the full Coulomb potential of eq. task.
+ * The m = 0 Fourier mode is dropped (tin-foil boundary).
+ *
+ * Conventions shared by every entry point
+ *   - Status codes: every call returns ESP_OK or a negative esp_status and
+ *     never throws; esp_last_error() gives a thread-local message.
+ *   - Device pointers: pos, q, phi, F are device memory on the plan's device,
+ *     owned by the caller, valid for the duration of the call (and until the
+ *     plan's stream reaches the call for the _async variant). They must not
+ *     alias one another. Element type follows the plan precision: float for
+ *     precision 32, double for precision 64.
+ *   - Layouts: pos is N x 3 row-major (x, y, z per particle); q, phi are N;
+ *     F is N x 3 row-major. Positions may lie anywhere: they are wrapped into
+ *     [0, L). For a batch, the arrays of the systems are concatenated in system
+ *     order.
+ *   - The plan owns all scratch memory (grids, sorted particles, tables) and
+ *     its HIP stream; PyTorch or any other allocator only supplies the
+ *     caller's buffers.
+ *   - Thread safety: calls on different plans may run concurrently; calls on
+ *     one plan must be serialised by the caller.
+ */
+#ifndef ESP_H
+#define ESP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ESP_OK = 0,
+    ESP_E_INVALID = -1,      /* bad argument (NULL, N < 1, box <= 0, tol out of range) */
+    ESP_E_UNSUPPORTED = -2,  /* non-cubic box, grid or window outside the built range */
+    ESP_E_NOT_NEUTRAL = -3,  /* |sum q| > 1e-6 sum |q|: results computed but meaningless */
+    ESP_E_NOMEM = -4,        /* device allocation failed */
+    ESP_E_DEVICE = -5,       /* HIP runtime error (message in esp_last_error) */
+    ESP_E_BUSY = -6          /* serving: queue full / budget exhausted for this request */
+} esp_status;
+
+/* Parameters. On input (esp_plan_create_ex, esp_plan_query) a zero field means
+ * "choose for me"; on output every field is resolved.
+ *
+ * Default rules (Methods, parameter selection; Table 2; eq. pswfparameters):
+ *   c      solves psi_0^c(1) = tol (psi L2-normalised on [-1,1]);
+ *   P      Table 2's P_esp for the largest tabulated eps not above tol
+ *          (5 above 1e-3; +3 per decade below 1e-5, at most 12);
+ *   nf     smallest even 2^a 3^b with L/nf <= h_max;
+ *   rc     kappa * c * h / pi;
+ *   c1     argmin over [0.9c, 1.4c] of the aliasing estimate (eq. errorformula);
+ *   degree smallest polynomial degree whose piecewise fit of the window is
+ *          within 0.05*tol of psi_0^{c1} (relative to its peak). */
+typedef struct {
+    int    nf;            /* grid points per side: even, 2^a 3^b, 8..144 */
+    int    P;             /* window width in grid points, 4..12 */
+    int    degree;        /* window polynomial degree, 4..16 */
+    int    precision;     /* 32 (default) or 64 */
+    int    tile;          /* particle bin edge in grid points, 4..16 (0: 8) */
+    int    deterministic; /* reserved: 1 requests a fixed reduction order */
+    double c;             /* splitting-kernel PSWF shape parameter */
+    double c1;            /* window PSWF shape parameter */
+    double rc;            /* cutoff radius of the local part */
+    double h_max;         /* default-grid spacing bound (0: 1.25, length units) */
+    double kappa;         /* default-cutoff margin (0: 1.2) */
+    /* outputs only */
+    double L;             /* box side */
+    double h;             /* grid spacing L/nf */
+    double tol;           /* requested tolerance */
+    double s0;            /* self constant S(0) = chi(0)/(4 pi rc) */
+} esp_params;
+
+typedef struct esp_plan esp_plan;
+
+/* ---- host-only queries (no device use; safe on machines without a GPU) ---- */
+
+/* Resolve parameters for a cubic box of side box[0] (box[1], box[2] must equal
+ * it), N particles and tolerance tol in [1e-8, 1e-2]. req may be NULL. */
+esp_status esp_plan_query(const double box[3], int64_t N, double tol,
+                          const esp_params* req, esp_params* out);
+
+/* Window polynomials used by the spread and gather kernels (eq. pswf, SI
+ * kernel approximated by piecewise polynomials on intervals of length h).
+ * For a particle at grid coordinate u, l0 = floor(u - P/2) + 1 and
+ * y = u - P/2 - floor(u - P/2) - 1/2 in [-1/2, 1/2); the weight of grid point
+ * l0 + j (j = 0..P-1) is sum_m coef[j*(degree+1) + m] y^m, approximating
+ * psi_0^{c1}(2 (u - l0 - j)/P). coef must hold P*(degree+1) doubles. */
+esp_status esp_window_coeffs(const esp_params* resolved, double* coef);
+
+/* Influence function in factored form (eq. pk): for Fourier index m in
+ * [-nf/2, nf/2)^3,  p_m = TS[mx^2+my^2+mz^2] * Tphi[|mx|] Tphi[|my|] Tphi[|mz|].
+ * TS holds 3*(nf/2)^2 + 1 doubles (TS[0] = 0), Tphi holds nf/2 + 1 doubles. */
+esp_status esp_influence_tables(const esp_params* resolved, double* TS, double* Tphi);
+
+/* Local kernel of the split (eq. kernelsplitting), for pairing with a
+ * short-range code: L(r) and dL/dr at the n radii r[] (r > 0). */
+esp_status esp_local_kernel(const esp_params* resolved, const double* r, int64_t n,
+                            double* Lr, double* dLr);
+
+/* ---- single-system plans ---- */
+
+esp_status esp_plan_create(const double box[3], int64_t N, double tol, esp_plan** out);
+esp_status esp_plan_create_ex(const double box[3], int64_t N, double tol,
+                              const esp_params* req, esp_plan** out);
+
+/* Batched plan: nsys independent cubic systems of sides L[s], N[s] particles and
+ * tolerances tol[s]; req (may be NULL) applies to every system, or reqs[s]
+ * (may be NULL) per system. One call evaluates all systems with one launch per
+ * pipeline phase (systems grouped by window width P). */
+esp_status esp_batch_create(int nsys, const double* L, const int64_t* N, const double* tol,
+                            const esp_params* reqs, esp_plan** out);
+
+esp_status esp_plan_get_params(const esp_plan* plan, int sys, esp_params* out);
+int        esp_plan_num_systems(const esp_plan* plan);
+/* Stream (hipStream_t) the plan enqueues on; created by the plan. */
+void*      esp_plan_stream(const esp_plan* plan);
+
+/* Evaluate potentials, forces and energy (Methods, five-step method; AD
+ * forces). phi and/or F may be NULL to skip writing them. E is a HOST array
+ * of nsys doubles (or NULL); when non-NULL the call waits for the stream and
+ * checks neutrality, otherwise it returns after enqueueing. */
+esp_status esp_longrange(esp_plan* plan, const void* pos, const void* q,
+                         void* phi, void* F, double* E);
+
+/* Same, never waiting: E_dev (device, nsys doubles, or NULL) receives the
+ * energies; call esp_plan_sync to wait and check neutrality. */
+esp_status esp_longrange_async(esp_plan* plan, const void* pos, const void* q,
+                               void* phi, void* F, double* E_dev);
+esp_status esp_plan_sync(esp_plan* plan);
+
+/* Capture the whole pipeline for fixed buffers into a HIP graph and replay it
+ * on every later esp_longrange call with the same pointers (0 disables). */
+esp_status esp_plan_set_graph(esp_plan* plan, int enable);
+
+void esp_plan_destroy(esp_plan* plan);
+
+/* ---- diagnostics ---- */
+
+/* Run the pipeline of a single-system plan up to one stage and copy the plan's
+ * grid buffer (device, caller-owned) out:
+ *   stage 1: b   real grid after spreading (eq. spread)
+ *   stage 2: b^  spectrum after the forward FFT
+ *   stage 3: c^  spectrum after diagonal scaling
+ *   stage 4: c   real grid after the inverse FFT
+ * Real grids are nf x nf x (nf+2) (last axis padded); spectra are
+ * nf x nf x (nf/2+1) complex (interleaved re, im), the half spectrum along the
+ * last axis, index k meaning mode k or k - nf. Element type follows the plan
+ * precision. If grid_in (nf x nf x (nf+2) real) is non-NULL it replaces the
+ * spread grid and pos/q are ignored (stages 2..4). */
+esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q,
+                           const void* grid_in, int stage, void* grid_out);
+
+/* Time each pipeline phase: runs the full pipeline `reps` times on the plan's
+ * stream with a HIP event between consecutive phases and writes the mean
+ * milliseconds of each phase to ms[0..ESP_NUM_PHASES-1] (names from
+ * esp_phase_name). Waits for the stream. */
+#define ESP_NUM_PHASES 10
+esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void* phi, void* F,
+                            int reps, double* ms);
+const char* esp_phase_name(int phase);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* esp_last_error(void);
+/* Library version string. */
+const char* esp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESP_H */

@@ -66,26 +66,38 @@ def cutoff_radius(c: float, h: float, kappa: float = 1.2) -> float:
     return kappa * c * h / math.pi
 
 
-def aliasing_error(n, L, c, rc, c1, P):
-    """E_A of eq. errorformula (up to its overall constant)."""
+def _aliasing_weights(n, L, c, rc):
+    """c1-independent factor of E_A: a(m_x) = sum_{m_y, m_z} |chi^(2 pi rc |m|/L)| / |m|^2."""
     split = PSWFSplit(c, rc)
-    h = L / n
-    m = np.arange(-(n // 2), n // 2).astype(np.float64)
+    m = np.arange(-(n // 2), n // 2)
     m2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
-    zero = (n // 2,) * 3
-    m2[zero] = 1.0
-    A = np.abs(split.chihat(2 * math.pi * rc * np.sqrt(m2) / L)) / m2
-    A[zero] = 0.0
-    a = A.sum(axis=(1, 2))
+    vals = np.arange(3 * (n // 2) ** 2 + 1, dtype=np.float64)
+    vals[0] = 1.0
+    table = np.abs(split.chihat(2 * math.pi * rc * np.sqrt(vals) / L)) / vals
+    table[0] = 0.0
+    return m.astype(np.float64), table[m2].sum(axis=(1, 2))
+
+
+def _aliasing_from_weights(m, a, n, L, c1, P):
+    h = L / n
     psi1 = pswf(c1)
     ft = lambda xi: psi1.ft(xi * P * h / 2.0)
     ratio = np.abs(ft(2 * math.pi * (m + n) / L) / ft(2 * math.pi * m / L))
     return 6.0 * float(np.dot(a, ratio))
 
 
+def aliasing_error(n, L, c, rc, c1, P):
+    """E_A of eq. errorformula (up to its overall constant):
+    6 sum_{m in I, m != 0} |chi^(2 pi rc|m|/L)/|m|^2 * phi^(k + 2 pi (n,0,0)/L)/phi^(k)|;
+    phi^ factorises per axis, so only the x factor of the ratio survives."""
+    m, a = _aliasing_weights(n, L, c, rc)
+    return _aliasing_from_weights(m, a, n, L, c1, P)
+
+
 def choose_c1(n, L, c, rc, P, lo=0.9, hi=1.4, num=51):
+    m, a = _aliasing_weights(n, L, c, rc)
     grid = np.linspace(lo * c, hi * c, num)
-    ea = [aliasing_error(n, L, c, rc, float(x), P) for x in grid]
+    ea = [_aliasing_from_weights(m, a, n, L, float(x), P) for x in grid]
     return float(grid[int(np.argmin(ea))])
 
 

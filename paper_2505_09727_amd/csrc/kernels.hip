@@ -1,0 +1,766 @@
+// HIP kernels of the ESP long-range pipeline for gfx950 (CDNA4, wave64).
+//
+// Pipeline (Methods, "Fast algorithm for the spectral part"):
+//   bin + counting sort -> spread (eq. spread) -> forward 3D FFT ->
+//   diagonal scaling by p_k (eq. pk) with the k-space energy ->
+//   inverse 3D FFT -> interpolation with analytic window derivatives (eq. interp,
+//   AD forces) -> energy finalisation.
+//
+// Every kernel walks a work-item list, so one launch serves a batch of systems
+// of different sizes. Real grids are stored n x n x (n+2) so that the half
+// spectrum n x n x (n/2+1) of each x-plane overwrites that plane in place.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace esp {
+
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <typename R> struct cplx { R x, y; };
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFT butterflies, sign s: y_k = sum_m v_m exp(s 2 pi i m k / RAD)
+template <typename R, int RAD> struct Bfly;
+
+template <typename R> struct Bfly<R, 2> {
+    __device__ __forceinline__ static void run(cplx<R>* v, int) {
+        const cplx<R> a = v[0], b = v[1];
+        v[0] = {a.x + b.x, a.y + b.y};
+        v[1] = {a.x - b.x, a.y - b.y};
+    }
+};
+
+template <typename R> struct Bfly<R, 3> {
+    __device__ __forceinline__ static void run(cplx<R>* v, int s) {
+        const R h = R(0.86602540378443864676) * R(s);
+        const cplx<R> a = v[0], b = v[1], c = v[2];
+        const cplx<R> t1 = {b.x + c.x, b.y + c.y};
+        const cplx<R> t2 = {a.x - R(0.5) * t1.x, a.y - R(0.5) * t1.y};
+        const cplx<R> t3 = {h * (b.x - c.x), h * (b.y - c.y)};
+        v[0] = {a.x + t1.x, a.y + t1.y};
+        v[1] = {t2.x - t3.y, t2.y + t3.x};
+        v[2] = {t2.x + t3.y, t2.y - t3.x};
+    }
+};
+
+template <typename R> struct Bfly<R, 4> {
+    __device__ __forceinline__ static void run(cplx<R>* v, int s) {
+        const cplx<R> a = v[0], b = v[1], c = v[2], d = v[3];
+        const cplx<R> t0 = {a.x + c.x, a.y + c.y}, t1 = {a.x - c.x, a.y - c.y};
+        const cplx<R> t2 = {b.x + d.x, b.y + d.y}, t3 = {b.x - d.x, b.y - d.y};
+        const cplx<R> it3 = s > 0 ? cplx<R>{-t3.y, t3.x} : cplx<R>{t3.y, -t3.x};
+        v[0] = {t0.x + t2.x, t0.y + t2.y};
+        v[2] = {t0.x - t2.x, t0.y - t2.y};
+        v[1] = {t1.x + it3.x, t1.y + it3.y};
+        v[3] = {t1.x - it3.x, t1.y - it3.y};
+    }
+};
+
+// One Stockham autosort stage on `nlines` lines held in LDS; element (line,
+// idx) lives at buf[line*lstride + idx*estride]. All threads of the block take
+// part: every thread first loads and transforms its butterflies into
+// registers, the block synchronises, then every thread stores, so the stage
+// runs in place. MAXIT bounds the number of radix-2 butterflies per thread.
+template <typename R, int RAD, int MAXIT>
+__device__ __forceinline__ void stockham_stage(cplx<R>* buf, int n, int nlines, int lstride, int estride,
+                                               int Ns, const cplx<R>* tw, int s, bool line_fast) {
+    constexpr int IT = (2 * MAXIT + RAD - 1) / RAD;
+    const int nb = n / RAD;
+    const int total = nlines * nb;
+    const int span = n / (Ns * RAD);
+    cplx<R> v[IT][RAD];
+    int dst[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int item = threadIdx.x + it * blockDim.x;
+        dst[it] = -1;
+        if (item < total) {
+            int line, j;
+            if (line_fast) {
+                j = item / nlines;
+                line = item - j * nlines;
+            } else {
+                line = item / nb;
+                j = item - line * nb;
+            }
+            const cplx<R>* src = buf + line * lstride + j * estride;
+            const int jm = j % Ns;
+            const int tstep = jm * span;
+#pragma unroll
+            for (int k = 0; k < RAD; ++k) {
+                cplx<R> a = src[k * nb * estride];
+                if (k > 0) {
+                    cplx<R> w = tw[k * tstep];
+                    if (s < 0) w.y = -w.y;
+                    a = cmul(a, w);
+                }
+                v[it][k] = a;
+            }
+            Bfly<R, RAD>::run(v[it], s);
+            dst[it] = line * lstride + ((j - jm) * RAD + jm) * estride;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        if (dst[it] >= 0) {
+#pragma unroll
+            for (int k = 0; k < RAD; ++k) buf[dst[it] + k * Ns * estride] = v[it][k];
+        }
+    }
+    __syncthreads();
+}
+
+// Unnormalised DFT of length n = 2^a 3^b on many lines in LDS:
+// y_k = sum_l exp(s 2 pi i k l / n) x_l, natural order in and out.
+// tw[t] = exp(2 pi i t / n), t in [0, n).
+template <typename R, int MAXIT>
+__device__ void fft_lines(cplx<R>* buf, int n, int nlines, int lstride, int estride, const cplx<R>* tw,
+                          int s, bool line_fast) {
+    int m = n, Ns = 1;
+    while (m % 4 == 0) {
+        stockham_stage<R, 4, MAXIT>(buf, n, nlines, lstride, estride, Ns, tw, s, line_fast);
+        Ns *= 4;
+        m /= 4;
+    }
+    while (m % 2 == 0) {
+        stockham_stage<R, 2, MAXIT>(buf, n, nlines, lstride, estride, Ns, tw, s, line_fast);
+        Ns *= 2;
+        m /= 2;
+    }
+    while (m % 3 == 0) {
+        stockham_stage<R, 3, MAXIT>(buf, n, nlines, lstride, estride, Ns, tw, s, line_fast);
+        Ns *= 3;
+        m /= 3;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block sum of a double (fixed tree; blockDim a power of two).
+__device__ double block_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) t += red[w];
+    return t;  // valid in thread 0
+}
+
+// Grid coordinate u in [0, n) of one position component.
+template <typename R>
+__device__ __forceinline__ R grid_coord(R x, R inv_L, int n) {
+    R t = x * inv_L;
+    t = t - floor(t);
+    R u = t * R(n);
+    if (u >= R(n)) u -= R(n);
+    if (u < R(0)) u = R(0);
+    return u;
+}
+
+template <typename R>
+__device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
+    const int nm1 = S.n - 1;
+    const int cx = min((int)ux, nm1), cy = min((int)uy, nm1), cz = min((int)uz, nm1);
+    return (cx / S.T * S.tiles1 + cy / S.T) * S.tiles1 + cz / S.T;
+}
+
+// ---------------------------------------------------------------------------
+// Zero a buffer of reals (graph-safe replacement for a memset).
+template <typename R>
+__global__ void k_zero(R* __restrict__ p, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = R(0);
+}
+
+// Bin: grid coordinates, bin id, rank within the bin (atomic counter), and per
+// chunk sums of q, |q|, q^2 (for the neutrality check and the self energy).
+template <typename R>
+__global__ void __launch_bounds__(256) k_bin(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                             const R* __restrict__ pos, const R* __restrict__ q,
+                                             int* __restrict__ bin_count, int* __restrict__ rank,
+                                             double* __restrict__ bpart) {
+    __shared__ double red[16];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int il = wi.y + threadIdx.x;
+    double sq = 0.0, sa = 0.0, s2 = 0.0;
+    if (il < S.N) {
+        const long long i = (long long)S.part_off + il;
+        const R inv_L = R(S.inv_L);
+        const R ux = grid_coord(pos[3 * i + 0], inv_L, S.n);
+        const R uy = grid_coord(pos[3 * i + 1], inv_L, S.n);
+        const R uz = grid_coord(pos[3 * i + 2], inv_L, S.n);
+        const int b = S.tile_off + bin_of(ux, uy, uz, S);
+        rank[i] = atomicAdd(&bin_count[b], 1);
+        const double qq = (double)q[i];
+        sq = qq;
+        sa = fabs(qq);
+        s2 = qq * qq;
+    }
+    const double t0 = block_sum(sq, red);
+    const double t1 = block_sum(sa, red);
+    const double t2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        bpart[3 * blockIdx.x + 0] = t0;
+        bpart[3 * blockIdx.x + 1] = t1;
+        bpart[3 * blockIdx.x + 2] = t2;
+    }
+}
+
+// Exclusive scan of the bin counts of one system (one block per system); the
+// counters are cleared for the next call.
+__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, int nsys, int* __restrict__ bin_count,
+                                               int* __restrict__ bin_start) {
+    __shared__ int warp_tot[16];
+    __shared__ int carry_s;
+    const SysDesc S = sys[blockIdx.x];
+    const int nb = S.tiles1 * S.tiles1 * S.tiles1;
+    if (threadIdx.x == 0) carry_s = S.part_off;
+    __syncthreads();
+    for (int base = 0; base < nb; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? bin_count[S.tile_off + i] : 0;
+        // inclusive scan inside the wavefront
+        int x = v;
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) warp_tot[wid] = x;
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wid; ++w) before += warp_tot[w];
+        const int carry = carry_s;
+        if (i < nb) {
+            bin_start[S.tile_off + i] = carry + before + x - v;
+            bin_count[S.tile_off + i] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry_s = carry + before + x;
+        __syncthreads();
+    }
+    if (blockIdx.x == nsys - 1 && threadIdx.x == 0) bin_start[S.tile_off + nb] = S.part_off + S.N;
+}
+
+// Scatter particles into bin order as (u_x, u_y, u_z, q) and record the
+// permutation back to the caller's order.
+template <typename R>
+__global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                 const R* __restrict__ pos, const R* __restrict__ q,
+                                                 const int* __restrict__ rank, const int* __restrict__ bin_start,
+                                                 typename Vec4<R>::type* __restrict__ sorted,
+                                                 int* __restrict__ perm) {
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int il = wi.y + threadIdx.x;
+    if (il >= S.N) return;
+    const long long i = (long long)S.part_off + il;
+    const R inv_L = R(S.inv_L);
+    const R ux = grid_coord(pos[3 * i + 0], inv_L, S.n);
+    const R uy = grid_coord(pos[3 * i + 1], inv_L, S.n);
+    const R uz = grid_coord(pos[3 * i + 2], inv_L, S.n);
+    const int b = S.tile_off + bin_of(ux, uy, uz, S);
+    const int dst = bin_start[b] + rank[i];
+    typename Vec4<R>::type v;
+    v.x = ux;
+    v.y = uy;
+    v.z = uz;
+    v.w = q[i];
+    sorted[dst] = v;
+    perm[dst] = (int)i;
+}
+
+// ---------------------------------------------------------------------------
+// Window weights of one axis by Horner in y in [-1/2, 1/2): the P polynomial
+// pieces of psi^{c1}(2 (u - l)/P) for l = l0 .. l0+P-1, l0 = floor(u - P/2) + 1.
+template <typename R, int P>
+__device__ __forceinline__ int window(R u, const R* __restrict__ coef, int deg, R* w) {
+    const R hp = R(0.5) * R(P);
+    const R f = floor(u - hp);
+    const R y = (u - hp) - f - R(0.5);
+    const int d1 = deg + 1;
+#pragma unroll
+    for (int j = 0; j < P; ++j) w[j] = coef[j * d1 + deg];
+    for (int m = deg - 1; m >= 0; --m) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) w[j] = w[j] * y + coef[j * d1 + m];
+    }
+    return (int)f + 1;
+}
+
+template <typename R, int P>
+__device__ __forceinline__ int window_d(R u, const R* __restrict__ coef, int deg, R* w, R* dw) {
+    const R hp = R(0.5) * R(P);
+    const R f = floor(u - hp);
+    const R y = (u - hp) - f - R(0.5);
+    const int d1 = deg + 1;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        w[j] = coef[j * d1 + deg];
+        dw[j] = R(0);
+    }
+    for (int m = deg - 1; m >= 0; --m) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            dw[j] = dw[j] * y + w[j];
+            w[j] = w[j] * y + coef[j * d1 + m];
+        }
+    }
+    return (int)f + 1;
+}
+
+__device__ __forceinline__ int wrapi(int g, int n) {
+    g %= n;
+    return g < 0 ? g + n : g;
+}
+
+// Spread (eq. spread): one block per bin of T^3 grid cells. The block
+// accumulates its particles' P^3 windows into an LDS tile of (T+P)^3 points
+// with LDS atomics, then adds the tile to the periodic grid with global atomics.
+template <typename R, int P>
+__global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                const typename Vec4<R>::type* __restrict__ sorted,
+                                                const int* __restrict__ bin_start, const R* __restrict__ poly_all,
+                                                R* __restrict__ grid) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R* lds = reinterpret_cast<R*>(smem_raw);
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
+    const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+    const int lo = -((P - 1) / 2);
+    const int E = T + P, E3 = E * E * E;
+    const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
+    const int beg = bin_start[S.tile_off + t], end = bin_start[S.tile_off + t + 1];
+    if (beg == end) return;  // uniform over the block
+    for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = R(0);
+    __syncthreads();
+    const R* coef = poly_all + S.poly_off;
+    for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
+        const typename Vec4<R>::type v = sorted[k];
+        R wx[P], wy[P], wz[P];
+        const int bx = window<R, P>(v.x, coef, S.degree, wx) - ox;
+        const int by = window<R, P>(v.y, coef, S.degree, wy) - oy;
+        const int bz = window<R, P>(v.z, coef, S.degree, wz) - oz;
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+            const R qa = v.w * wx[a];
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                const R qab = qa * wy[b];
+                R* row = lds + ((bx + a) * E + (by + b)) * E + bz;
+#pragma unroll
+                for (int c = 0; c < P; ++c) atomicAdd(row + c, qab * wz[c]);
+            }
+        }
+    }
+    __syncthreads();
+    R* g = grid + S.grid_off;
+    const int rl = n + 2;
+    for (int i = threadIdx.x; i < E3; i += blockDim.x) {
+        const R val = lds[i];
+        if (val != R(0)) {
+            const int a = i / (E * E), rem = i - a * E * E, b = rem / E, c = rem - b * E;
+            const int gx = wrapi(ox + a, n), gy = wrapi(oy + b, n), gz = wrapi(oz + c, n);
+            atomicAdd(g + ((long long)gx * n + gy) * rl + gz, val);
+        }
+    }
+}
+
+// Gather (eq. interp) with analytic window derivatives (AD forces):
+// phi_i = u~_i - q_i S(0), F_i = -q_i (n/L) grad_u u~_i, written in caller order.
+template <typename R, int P>
+__global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                const typename Vec4<R>::type* __restrict__ sorted,
+                                                const int* __restrict__ perm, const int* __restrict__ bin_start,
+                                                const R* __restrict__ poly_all, const R* __restrict__ grid,
+                                                R* __restrict__ phi, R* __restrict__ F) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R* lds = reinterpret_cast<R*>(smem_raw);
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
+    const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+    const int lo = -((P - 1) / 2);
+    const int E = T + P, E3 = E * E * E;
+    const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
+    const int beg = bin_start[S.tile_off + t], end = bin_start[S.tile_off + t + 1];
+    if (beg == end) return;
+    const R* g = grid + S.grid_off;
+    const int rl = n + 2;
+    for (int i = threadIdx.x; i < E3; i += blockDim.x) {
+        const int a = i / (E * E), rem = i - a * E * E, b = rem / E, c = rem - b * E;
+        const int gx = wrapi(ox + a, n), gy = wrapi(oy + b, n), gz = wrapi(oz + c, n);
+        lds[i] = g[((long long)gx * n + gy) * rl + gz];
+    }
+    __syncthreads();
+    const R* coef = poly_all + S.poly_off;
+    const R sc = R(S.n) * R(S.inv_L);
+    const R s0 = R(S.s0);
+    for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
+        const typename Vec4<R>::type v = sorted[k];
+        R wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
+        const int bx = window_d<R, P>(v.x, coef, S.degree, wx, dx) - ox;
+        const int by = window_d<R, P>(v.y, coef, S.degree, wy, dy) - oy;
+        const int bz = window_d<R, P>(v.z, coef, S.degree, wz, dz) - oz;
+        R u = 0, gxs = 0, gys = 0, gzs = 0;
+        // outer loop kept rolled: a is uniform across the wavefront, and
+        // unrolling all P^3 loads would exhaust the register file
+#pragma unroll 1
+        for (int a = 0; a < P; ++a) {
+            R su = 0, sdy = 0, sdz = 0;
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                const R* row = lds + ((bx + a) * E + (by + b)) * E + bz;
+                R s = 0, sd = 0;
+#pragma unroll
+                for (int c = 0; c < P; ++c) {
+                    const R gv = row[c];
+                    s += gv * wz[c];
+                    sd += gv * dz[c];
+                }
+                su += s * wy[b];
+                sdy += s * dy[b];
+                sdz += sd * wy[b];
+            }
+            u += su * wx[a];
+            gxs += su * dx[a];
+            gys += sdy * wx[a];
+            gzs += sdz * wx[a];
+        }
+        const int o = perm[k];
+        if (phi) phi[o] = u - v.w * s0;
+        if (F) {
+            const R f = -v.w * sc;
+            F[3LL * o + 0] = f * gxs;
+            F[3LL * o + 1] = f * gys;
+            F[3LL * o + 2] = f * gzs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward FFT along z (real-to-complex) and y for one x-plane. Pairs of real
+// rows (2r, 2r+1) are transformed as one complex row and split afterwards.
+template <typename R, int MAXIT>
+__global__ void __launch_bounds__(512) k_fft_fwd_zy(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                    R* __restrict__ grid, const cplx<R>* __restrict__ tw_all) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int n = S.n, hs = n / 2 + 1, rl = n + 2, half = n / 2;
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
+    R* plane = grid + S.grid_off + (long long)wi.y * n * rl;
+    for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
+        const int r = idx / n, z = idx - r * n;
+        buf[idx] = {plane[(2 * r) * rl + z], plane[(2 * r + 1) * rl + z]};
+    }
+    __syncthreads();
+    fft_lines<R, MAXIT>(buf, n, half, n, 1, tw, +1, false);
+    {
+        cplx<R> A[MAXIT], B[MAXIT];
+        int o[MAXIT];
+        const int total = half * hs;
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            const int item = threadIdx.x + it * blockDim.x;
+            o[it] = -1;
+            if (item < total) {
+                const int r = item / hs, k = item - r * hs;
+                const cplx<R> zk = buf[r * n + k];
+                const cplx<R> zn = buf[r * n + (k == 0 ? 0 : n - k)];
+                A[it] = {R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};
+                B[it] = {R(0.5) * (zk.y + zn.y), -R(0.5) * (zk.x - zn.x)};
+                o[it] = (2 * r) * hs + k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it)
+            if (o[it] >= 0) {
+                buf[o[it]] = A[it];
+                buf[o[it] + hs] = B[it];
+            }
+        __syncthreads();
+    }
+    fft_lines<R, MAXIT>(buf, n, hs, 1, hs, tw, +1, true);
+    cplx<R>* gp = reinterpret_cast<cplx<R>*>(plane);
+    for (int idx = threadIdx.x; idx < n * hs; idx += blockDim.x) gp[idx] = buf[idx];
+}
+
+// Inverse FFT along y, then complex-to-real along z, for one x-plane.
+template <typename R, int MAXIT>
+__global__ void __launch_bounds__(512) k_fft_inv_yz(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                    R* __restrict__ grid, const cplx<R>* __restrict__ tw_all) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int n = S.n, hs = n / 2 + 1, rl = n + 2, half = n / 2;
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
+    R* plane = grid + S.grid_off + (long long)wi.y * n * rl;
+    const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(plane);
+    for (int idx = threadIdx.x; idx < n * hs; idx += blockDim.x) buf[idx] = gp[idx];
+    __syncthreads();
+    fft_lines<R, MAXIT>(buf, n, hs, 1, hs, tw, -1, true);
+    {
+        // rows 2r and 2r+1 (half spectra A, B of two real rows) -> Z = A + iB
+        cplx<R> Z[MAXIT], Zc[MAXIT];
+        int o[MAXIT], k_[MAXIT];
+        const int total = half * hs;
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) {
+            const int item = threadIdx.x + it * blockDim.x;
+            o[it] = -1;
+            if (item < total) {
+                const int r = item / hs, k = item - r * hs;
+                const cplx<R> a = buf[(2 * r) * hs + k], b = buf[(2 * r + 1) * hs + k];
+                Z[it] = {a.x - b.y, a.y + b.x};
+                Zc[it] = {a.x + b.y, b.x - a.y};
+                o[it] = r * n;
+                k_[it] = k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it)
+            if (o[it] >= 0) {
+                const int k = k_[it];
+                buf[o[it] + k] = Z[it];
+                if (k > 0 && k < half) buf[o[it] + n - k] = Zc[it];
+            }
+        __syncthreads();
+    }
+    fft_lines<R, MAXIT>(buf, n, half, n, 1, tw, -1, false);
+    for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
+        const int r = idx / n, z = idx - r * n;
+        const cplx<R> v = buf[idx];
+        plane[(2 * r) * rl + z] = v.x;
+        plane[(2 * r + 1) * rl + z] = v.y;
+    }
+}
+
+// FFT along x for a block of kz columns at fixed ky, diagonal scaling by the
+// influence function (eq. pk) with the k-space energy
+//   E_k = 1/2 sum_k p_k |b^_k|^2   (half spectrum, weight 2 off the kz = 0, n/2 planes),
+// then the inverse FFT along x. mode 1 stops after the forward FFT, mode 2
+// after the scaling (diagnostics).
+template <typename R, int MAXIT>
+__global__ void __launch_bounds__(256) k_fft_x(const SysDesc* __restrict__ sys, const int4* __restrict__ items,
+                                               R* __restrict__ grid, const cplx<R>* __restrict__ tw_all,
+                                               const R* __restrict__ TS_all, const R* __restrict__ Tphi_all,
+                                               double* __restrict__ epart, int mode) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    const int4 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int n = S.n, hs = n / 2 + 1, half = n / 2;
+    const int ky = wi.y, kz0 = wi.z, KB = wi.w;
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
+    cplx<R>* gp = reinterpret_cast<cplx<R>*>(grid + S.grid_off);
+    const int cnt = n * KB;
+    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+        const int x = idx / KB, l = idx - x * KB;
+        buf[idx] = gp[((long long)x * n + ky) * hs + kz0 + l];
+    }
+    __syncthreads();
+    fft_lines<R, MAXIT>(buf, n, KB, 1, KB, tw, +1, true);
+    double e = 0.0;
+    if (mode != 1) {
+        const R* TS = TS_all + S.ts_off;
+        const R* Tp = Tphi_all + S.tphi_off;
+        const int my = ky <= half ? ky : n - ky;
+        const R py = Tp[my];
+        for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+            const int x = idx / KB, l = idx - x * KB, kz = kz0 + l;
+            const int mx = x <= half ? x : n - x;
+            const R p = TS[mx * mx + my * my + kz * kz] * Tp[mx] * py * Tp[kz];
+            const cplx<R> b = buf[idx];
+            const double wgt = (kz == 0 || kz == half) ? 1.0 : 2.0;
+            e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);
+            buf[idx] = {b.x * p, b.y * p};
+        }
+        __syncthreads();
+        if (mode == 0) fft_lines<R, MAXIT>(buf, n, KB, 1, KB, tw, -1, true);
+    }
+    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+        const int x = idx / KB, l = idx - x * KB;
+        gp[((long long)x * n + ky) * hs + kz0 + l] = buf[idx];
+    }
+    const double tot = block_sum(e, red);
+    if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
+}
+
+// Energy per system: E = E_k - S(0)/2 sum q^2, plus the charge sums.
+__global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
+                                                  const double* __restrict__ bpart, double* __restrict__ eout,
+                                                  double* __restrict__ E_dev) {
+    __shared__ double red[16];
+    const SysDesc S = sys[blockIdx.x];
+    double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < S.ncol; i += blockDim.x) ek += epart[S.col_off + i];
+    for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) {
+        sq += bpart[3 * (S.pitem_off + i) + 0];
+        sa += bpart[3 * (S.pitem_off + i) + 1];
+        s2 += bpart[3 * (S.pitem_off + i) + 2];
+    }
+    ek = block_sum(ek, red);
+    sq = block_sum(sq, red);
+    sa = block_sum(sa, red);
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        const double E = ek - 0.5 * S.s0 * s2;
+        eout[4 * blockIdx.x + 0] = E;
+        eout[4 * blockIdx.x + 1] = sq;
+        eout[4 * blockIdx.x + 2] = sa;
+        eout[4 * blockIdx.x + 3] = s2;
+        if (E_dev) E_dev[blockIdx.x] = E;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <typename K>
+static hipError_t allow_lds(K kernel, int bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <typename R>
+static hipError_t prepare_t(const Launch& L, int phase, const void* pos, const void* q) {
+    switch (phase) {
+        case 0: {
+            const long long cnt = L.grid_reals;
+            const int blocks = (int)std::min<long long>((cnt + 255) / 256, 4096);
+            k_zero<R><<<blocks, 256, 0, L.stream>>>(reinterpret_cast<R*>(L.grid), cnt);
+            break;
+        }
+        case 1:
+            k_bin<R><<<L.n_pitems, 256, 0, L.stream>>>(L.sys, L.pitems, reinterpret_cast<const R*>(pos),
+                                                       reinterpret_cast<const R*>(q), L.bin_count, L.rank, L.bpart);
+            break;
+        case 2:
+            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.nsys, L.bin_count, L.bin_start);
+            break;
+        case 3:
+            k_scatter<R><<<L.n_pitems, 256, 0, L.stream>>>(
+                L.sys, L.pitems, reinterpret_cast<const R*>(pos), reinterpret_cast<const R*>(q), L.rank,
+                L.bin_start, reinterpret_cast<typename Vec4<R>::type*>(L.sorted), L.perm);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Launch& L, int phase, const void* pos, const void* q) {
+    return L.prec == 64 ? prepare_t<double>(L, phase, pos, q) : prepare_t<float>(L, phase, pos, q);
+}
+
+template <typename R, int P>
+static hipError_t spread_p(const Launch& L, const Group& G) {
+    hipError_t e = allow_lds(k_spread<R, P>, G.lds);
+    if (e != hipSuccess) return e;
+    k_spread<R, P><<<G.count, 256, G.lds, L.stream>>>(
+        L.sys, L.titems + G.off, reinterpret_cast<const typename Vec4<R>::type*>(L.sorted), L.bin_start,
+        reinterpret_cast<const R*>(L.poly), reinterpret_cast<R*>(L.grid));
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+static hipError_t gather_p(const Launch& L, const Group& G, void* phi, void* F) {
+    hipError_t e = allow_lds(k_gather<R, P>, G.lds);
+    if (e != hipSuccess) return e;
+    k_gather<R, P><<<G.count, 256, G.lds, L.stream>>>(
+        L.sys, L.titems + G.off, reinterpret_cast<const typename Vec4<R>::type*>(L.sorted), L.perm,
+        L.bin_start, reinterpret_cast<const R*>(L.poly), reinterpret_cast<const R*>(L.grid),
+        reinterpret_cast<R*>(phi), reinterpret_cast<R*>(F));
+    return hipGetLastError();
+}
+
+#define ESP_P_SWITCH(FN, R, ...)                        \
+    switch (G.P) {                                      \
+        case 4: return FN<R, 4>(__VA_ARGS__);           \
+        case 5: return FN<R, 5>(__VA_ARGS__);           \
+        case 6: return FN<R, 6>(__VA_ARGS__);           \
+        case 7: return FN<R, 7>(__VA_ARGS__);           \
+        case 8: return FN<R, 8>(__VA_ARGS__);           \
+        case 9: return FN<R, 9>(__VA_ARGS__);           \
+        case 10: return FN<R, 10>(__VA_ARGS__);         \
+        case 11: return FN<R, 11>(__VA_ARGS__);         \
+        case 12: return FN<R, 12>(__VA_ARGS__);         \
+        default: return hipErrorInvalidValue;           \
+    }
+
+hipError_t launch_spread(const Launch& L, const Group& G) {
+    if (L.prec == 64) { ESP_P_SWITCH(spread_p, double, L, G) }
+    ESP_P_SWITCH(spread_p, float, L, G)
+}
+
+hipError_t launch_gather(const Launch& L, const Group& G, void* phi, void* F) {
+    if (L.prec == 64) { ESP_P_SWITCH(gather_p, double, L, G, phi, F) }
+    ESP_P_SWITCH(gather_p, float, L, G, phi, F)
+}
+
+template <typename R, int MAXIT>
+static hipError_t fft_t(const Launch& L, int which, int mode) {
+    const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(L.tw);
+    R* grid = reinterpret_cast<R*>(L.grid);
+    hipError_t e;
+    if (which == 0) {
+        if ((e = allow_lds(k_fft_fwd_zy<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
+        k_fft_fwd_zy<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes, grid, tw);
+    } else if (which == 1) {
+        if ((e = allow_lds(k_fft_x<R, MAXIT>, L.col_lds)) != hipSuccess) return e;
+        k_fft_x<R, MAXIT><<<L.n_cols, 256, L.col_lds, L.stream>>>(L.sys, L.cols, grid, tw,
+                                                                  reinterpret_cast<const R*>(L.TS),
+                                                                  reinterpret_cast<const R*>(L.Tphi), L.epart, mode);
+    } else {
+        if ((e = allow_lds(k_fft_inv_yz<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
+        k_fft_inv_yz<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes, grid, tw);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t fft_r(const Launch& L, int which, int mode) {
+    const int m = which == 1 ? L.col_maxit : L.plane_maxit;
+    if (m <= 2) return fft_t<R, 2>(L, which, mode);
+    if (m <= 4) return fft_t<R, 4>(L, which, mode);
+    if (m <= 8) return fft_t<R, 8>(L, which, mode);
+    if (m <= 12) return fft_t<R, 12>(L, which, mode);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fft(const Launch& L, int which, int mode) {
+    return L.prec == 64 ? fft_r<double>(L, which, mode) : fft_r<float>(L, which, mode);
+}
+
+hipError_t launch_finalize(const Launch& L, double* E_dev) {
+    k_finalize<<<L.nsys, 256, 0, L.stream>>>(L.sys, L.epart, L.bpart, L.eout, E_dev);
+    return hipGetLastError();
+}
+
+}  // namespace esp

@@ -1,0 +1,58 @@
+// Launch descriptors and launchers of the pipeline kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace esp {
+
+// Systems sharing one window width P: one spread and one gather launch.
+struct Group {
+    int P;
+    int off;    // first bin work item of the group
+    int count;  // bin work items
+    int lds;    // LDS bytes per block, (T+P)^3 reals
+};
+
+// Everything a pipeline launch needs (device pointers owned by the plan).
+struct Launch {
+    int prec;             // 32 or 64
+    int nsys;
+    hipStream_t stream;
+    const SysDesc* sys;
+    const int2* pitems;   // particle chunks
+    int n_pitems;
+    const int2* titems;   // bins, grouped by P
+    const int2* planes;   // (sys, x)
+    int n_planes;
+    const int4* cols;     // (sys, ky, kz0, width)
+    int n_cols;
+    int plane_bd, plane_maxit, plane_lds;
+    int col_maxit, col_lds;
+    void* grid;
+    long long grid_reals;
+    void* sorted;
+    int* perm;
+    int* rank;
+    int* bin_count;
+    int* bin_start;
+    double* bpart;
+    double* epart;
+    double* eout;
+    const void* TS;
+    const void* Tphi;
+    const void* poly;
+    const void* tw;
+};
+
+// Preparation phases: 0 zero the grid, 1 bin, 2 scan the bin counts,
+// 3 scatter into bin order.
+hipError_t launch_prepare(const Launch& L, int phase, const void* pos, const void* q);
+hipError_t launch_spread(const Launch& L, const Group& G);
+// which: 0 forward z/y planes, 1 x-columns with scaling (mode 0 full,
+// 1 forward only, 2 forward + scaling), 2 inverse y/z planes.
+hipError_t launch_fft(const Launch& L, int which, int mode);
+hipError_t launch_gather(const Launch& L, const Group& G, void* phi, void* F);
+hipError_t launch_finalize(const Launch& L, double* E_dev);
+
+}  // namespace esp

@@ -1,0 +1,410 @@
+// Host-side parameter selection and tables (FP64).
+//
+// Paper passages implemented here:
+//  * PSWF psi_0^c and its use as splitting kernel chi = psi/int_0^1 psi and as
+//    window phi(x) = psi^{c1}(2x/(P h)) (Methods, PSWF section, eq. pswf).
+//  * c from psi_0^c(1) = eps; P from Table 2; n from the Fourier truncation
+//    rule (eq. pswfparameters) and rc = kappa c h / pi.
+//  * c1 by minimising the aliasing estimate E_A (eq. errorformula).
+//  * Influence function p_m = h^6 S^(2 pi m/L) / (L^3 phi^(2 pi m/L)^2) with
+//    S^(k) = chi^(rc k)/k^2 (eqs. hS, pk), factored into a radial table over
+//    |m|^2 and a per-axis table of 1/phi^_1^2.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <limits>
+
+namespace esp {
+
+static constexpr double kPi = 3.14159265358979323846;
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Solve (T - s I) v = b for symmetric tridiagonal T (diag d, off e) by
+// Gaussian elimination with partial pivoting.
+static void tridiag_solve(const std::vector<double>& d, const std::vector<double>& e, double s,
+                          std::vector<double>& b) {
+    const int n = (int)d.size();
+    std::vector<double> dl(n > 1 ? n - 1 : 0), dd(n), du(n > 1 ? n - 1 : 0), du2(n > 2 ? n - 2 : 0, 0.0);
+    for (int i = 0; i < n; ++i) dd[i] = d[i] - s;
+    for (int i = 0; i + 1 < n; ++i) dl[i] = du[i] = e[i];
+    const double tiny = 1e-300;
+    for (int i = 0; i + 1 < n; ++i) {
+        if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+            if (dd[i] == 0.0) dd[i] = tiny;
+            double f = dl[i] / dd[i];
+            dd[i + 1] -= f * du[i];
+            b[i + 1] -= f * b[i];
+            if (i + 2 < n) du2[i] = 0.0;
+        } else {
+            double f = dd[i] / dl[i];
+            dd[i] = dl[i];
+            double t = dd[i + 1];
+            dd[i + 1] = du[i] - f * t;
+            du[i] = t;
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du2[i];
+            }
+            std::swap(b[i], b[i + 1]);
+            b[i + 1] -= f * b[i];
+        }
+    }
+    if (dd[n - 1] == 0.0) dd[n - 1] = tiny;
+    b[n - 1] /= dd[n - 1];
+    if (n > 1) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / (dd[n - 2] == 0.0 ? tiny : dd[n - 2]);
+    for (int i = n - 3; i >= 0; --i)
+        b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / (dd[i] == 0.0 ? tiny : dd[i]);
+}
+
+Prolate::Prolate(double c) : c_(c) {
+    const int K = (int)(c + 40.0);  // even Legendre degrees 0, 2, ..., 2(K-1)
+    std::vector<double> d(K), e(K - 1);
+    for (int i = 0; i < K; ++i) {
+        const double k = 2.0 * i;
+        double t = (k + 1) * (k + 1) / ((2 * k + 1) * (2 * k + 3));
+        if (i > 0) t += k * k / ((2 * k + 1) * (2 * k - 1));
+        d[i] = k * (k + 1) + c * c * t;
+        if (i + 1 < K)
+            e[i] = c * c * (k + 1) * (k + 2) / ((2 * k + 1) * (2 * k + 3)) *
+                   std::sqrt((2 * k + 1) / (2 * k + 5));
+    }
+    // smallest eigenvalue by bisection on the Sturm count
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = d[0] - x;
+        if (q < 0) ++cnt;
+        for (int i = 1; i < K; ++i) {
+            if (q == 0.0) q = 1e-300;
+            q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    double lo = d[0] - std::fabs(e[0]) - 1.0, hi = d[0] + std::fabs(e[0]) + 1.0;
+    for (int i = 1; i < K; ++i) {
+        const double r = std::fabs(e[i - 1]) + (i + 1 < K ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= 1) hi = mid; else lo = mid;
+    }
+    const double lam = 0.5 * (lo + hi);
+    // inverse iteration
+    std::vector<double> v(K, 1.0);
+    for (int it = 0; it < 4; ++it) {
+        tridiag_solve(d, e, lam, v);
+        double nrm = 0.0;
+        for (double t : v) nrm += t * t;
+        nrm = std::sqrt(nrm);
+        for (double& t : v) t /= nrm;
+    }
+    if (v[0] < 0) for (double& t : v) t = -t;
+    a_.resize(K);
+    for (int i = 0; i < K; ++i) a_[i] = v[i] * std::sqrt(2.0 * i + 0.5);
+    std::vector<double> w;
+    gauss_legendre(256, qx_, w);
+    qw_psi_.resize(qx_.size());
+    for (size_t q = 0; q < qx_.size(); ++q) qw_psi_[q] = w[q] * (*this)(qx_[q]);
+}
+
+double Prolate::operator()(double x) const {
+    // sum_i a_i P_{2i}(x) with the Legendre three-term recurrence
+    double p0 = 1.0, p1 = x, s = a_[0];
+    const int deg = 2 * ((int)a_.size() - 1);
+    for (int k = 1; k < deg; ++k) {
+        const double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+        if ((k + 1) % 2 == 0) s += a_[(k + 1) / 2] * p1;
+    }
+    return s;
+}
+
+double Prolate::deriv(double x) const {
+    double p0 = 1.0, p1 = x, dp0 = 0.0, dp1 = 1.0, s = 0.0;
+    const int deg = 2 * ((int)a_.size() - 1);
+    for (int k = 1; k < deg; ++k) {
+        const double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        const double dp2 = ((2.0 * k + 1.0) * (p1 + x * dp1) - k * dp0) / (k + 1.0);
+        p0 = p1; p1 = p2; dp0 = dp1; dp1 = dp2;
+        if ((k + 1) % 2 == 0) s += a_[(k + 1) / 2] * dp1;
+    }
+    return s;
+}
+
+double Prolate::integral(double x) const {
+    // int_0^x P_0 = x; int_0^x P_k = (P_{k+1}(x) - P_{k-1}(x))/(2k+1) for even k >= 2
+    const int deg = 2 * ((int)a_.size() - 1) + 1;
+    std::vector<double> P(deg + 1);
+    P[0] = 1.0;
+    P[1] = x;
+    for (int k = 1; k < deg; ++k) P[k + 1] = ((2.0 * k + 1.0) * x * P[k] - k * P[k - 1]) / (k + 1.0);
+    double s = a_[0] * x;
+    for (size_t i = 1; i < a_.size(); ++i) {
+        const int k = 2 * (int)i;
+        s += a_[i] * (P[k + 1] - P[k - 1]) / (2.0 * k + 1.0);
+    }
+    return s;
+}
+
+double Prolate::ft(double w) const {
+    double s = 0.0;
+    for (size_t q = 0; q < qx_.size(); ++q) s += qw_psi_[q] * std::cos(w * qx_[q]);
+    return s;
+}
+
+double c_for_tolerance(double eps) {
+    // psi_0^c(1) decreases monotonically in c; bisection on log psi(1)
+    double lo = std::max(0.5, std::log(1.0 / eps) - 3.0), hi = std::log(1.0 / eps) + 10.0;
+    const double target = std::log(eps);
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double v = Prolate(mid)(1.0);
+        if (v > 0 && std::log(v) > target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+int order_for_tol(double tol) {
+    // Table 2: P_esp = 5, 5, 6, 7, 8 at eps = 1e-3, 5e-4, 1e-4, 5e-5, 1e-5
+    static const double eps[5] = {1e-5, 5e-5, 1e-4, 5e-4, 1e-3};
+    static const int P[5] = {8, 7, 6, 5, 5};
+    if (tol >= 1e-3) return 5;
+    if (tol < 1e-5) {
+        const int p = 8 + (int)std::ceil(3.0 * std::log10(1e-5 / tol) - 1e-9);
+        return std::min(p, 12);
+    }
+    int best = 0;
+    for (int i = 0; i < 5; ++i)
+        if (eps[i] <= tol * (1 + 1e-12)) best = i;
+    return P[best];
+}
+
+bool is_smooth(int n) {
+    if (n < 2 || n % 2) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+int grid_size(double L, double h_max) {
+    int n = std::max(8, (int)std::ceil(L / h_max - 1e-12));
+    while (!is_smooth(n)) ++n;
+    return n;
+}
+
+double aliasing_error(int n, double L, const Prolate& chi, double rc, double c1, int P) {
+    // E_A = 6 sum_{m in I\0} | chi^(2 pi rc|m|/L)/|m|^2 * phi^(k + 2 pi (n,0,0)/L)/phi^(k) |
+    const double I1 = chi.integral(1.0);
+    const double h = L / n;
+    const int h2 = n / 2;
+    std::vector<double> ax(n, 0.0);  // sum over (my, mz) for each mx
+    std::vector<double> chat(3 * h2 * h2 + 1);
+    for (int m2 = 1; m2 <= 3 * h2 * h2; ++m2)
+        chat[m2] = std::fabs(0.5 * chi.ft(2 * kPi * rc * std::sqrt((double)m2) / L) / I1) / m2;
+    for (int mx = -h2; mx < h2; ++mx)
+        for (int my = -h2; my < h2; ++my)
+            for (int mz = -h2; mz < h2; ++mz) {
+                const int m2 = mx * mx + my * my + mz * mz;
+                if (m2) ax[mx + h2] += chat[m2];
+            }
+    Prolate win(c1);
+    double s = 0.0;
+    for (int mx = -h2; mx < h2; ++mx) {
+        const double a = win.ft(2 * kPi * (mx + n) / L * P * h / 2);
+        const double b = win.ft(2 * kPi * mx / L * P * h / 2);
+        s += ax[mx + h2] * std::fabs(a / b);
+    }
+    return 6.0 * s;
+}
+
+esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req, esp_params* out,
+                          std::string& msg) {
+    esp_params r{};
+    if (req) r = *req;
+    if (!(L > 0) || !std::isfinite(L)) { msg = "box side must be positive and finite"; return ESP_E_INVALID; }
+    if (N < 1) { msg = "N must be >= 1"; return ESP_E_INVALID; }
+    if (!(tol >= 1e-8 && tol <= 1e-2)) { msg = "tol must lie in [1e-8, 1e-2]"; return ESP_E_INVALID; }
+    r.L = L;
+    r.tol = tol;
+    if (r.c <= 0) r.c = c_for_tolerance(tol);
+    if (r.P <= 0) r.P = order_for_tol(tol);
+    if (r.P < 4 || r.P > 12) { msg = "window width P must lie in [4, 12]"; return ESP_E_UNSUPPORTED; }
+    if (r.h_max <= 0) r.h_max = 1.25;
+    if (r.kappa <= 0) r.kappa = 1.2;
+    if (r.nf <= 0) r.nf = grid_size(L, r.h_max);
+    if (!is_smooth(r.nf) || r.nf < 8 || r.nf > 144) {
+        msg = "grid size must be even, of the form 2^a 3^b, within [8, 144]";
+        return ESP_E_UNSUPPORTED;
+    }
+    if (r.nf < r.P) { msg = "grid size must be at least P"; return ESP_E_UNSUPPORTED; }
+    r.h = L / r.nf;
+    if (r.rc <= 0) r.rc = r.kappa * r.c * r.h / kPi;
+    if (r.precision == 0) r.precision = 32;
+    if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
+    if (r.tile == 0) r.tile = 8;
+    if (r.tile < 4 || r.tile > 16) { msg = "tile must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
+    Prolate chi(r.c);
+    if (r.c1 <= 0) {
+        double best = std::numeric_limits<double>::infinity(), bc1 = r.c;
+        for (int i = 0; i <= 50; ++i) {
+            const double c1 = r.c * (0.9 + 0.5 * i / 50.0);
+            const double ea = aliasing_error(r.nf, L, chi, r.rc, c1, r.P);
+            if (ea < best) { best = ea; bc1 = c1; }
+        }
+        r.c1 = bc1;
+    }
+    r.s0 = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * r.rc);
+    if (r.degree != 0 && (r.degree < 4 || r.degree > 16)) { msg = "degree must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
+    if (r.degree == 0) {
+        std::vector<double> coef;
+        window_polynomials(r, coef);
+    }
+    *out = r;
+    return ESP_OK;
+}
+
+// Chebyshev interpolation of f on [-1/2, 1/2] at degree d, returned as
+// monomial coefficients in y.
+template <class F>
+static std::vector<double> cheb_fit(F f, int d) {
+    const int m = d + 1;
+    std::vector<double> fv(m), s(m);
+    for (int i = 0; i < m; ++i) {
+        s[i] = std::cos(kPi * (i + 0.5) / m);
+        fv[i] = f(0.5 * s[i]);
+    }
+    std::vector<double> ck(m, 0.0);
+    for (int k = 0; k < m; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < m; ++i) acc += fv[i] * std::cos(k * kPi * (i + 0.5) / m);
+        ck[k] = acc * 2.0 / m;
+    }
+    ck[0] *= 0.5;
+    // sum ck T_k(s) -> monomials in s, T_{k+1} = 2 s T_k - T_{k-1}
+    std::vector<double> mono(m, 0.0), Tkm1(m, 0.0), Tk(m, 0.0), Tkp1(m, 0.0);
+    Tkm1[0] = 1.0;
+    mono[0] += ck[0];
+    if (m > 1) {
+        Tk[1] = 1.0;
+        mono[1] += ck[1];
+    }
+    for (int k = 1; k + 1 < m; ++k) {
+        std::fill(Tkp1.begin(), Tkp1.end(), 0.0);
+        for (int j = 0; j + 1 < m; ++j) Tkp1[j + 1] += 2.0 * Tk[j];
+        for (int j = 0; j < m; ++j) Tkp1[j] -= Tkm1[j];
+        for (int j = 0; j < m; ++j) mono[j] += ck[k + 1] * Tkp1[j];
+        Tkm1 = Tk;
+        Tk = Tkp1;
+    }
+    // s = 2y
+    double sc = 1.0;
+    for (int j = 0; j < m; ++j, sc *= 2.0) mono[j] *= sc;
+    return mono;
+}
+
+void window_polynomials(esp_params& p, std::vector<double>& coef) {
+    Prolate win(p.c1);
+    const int P = p.P;
+    const double peak = win(0.0);
+    auto piece = [&](int j) {
+        // weight of point l0 + j as a function of y = z - 1/2, z = frac(u - P/2):
+        // psi(2 (u - l0 - j)/P) with u - l0 = P/2 - 1 + z
+        return [&win, j, P](double y) { return win(2.0 * (y + 0.5 + 0.5 * P - 1.0 - j) / P); };
+    };
+    auto eval = [](const std::vector<double>& a, double y) {
+        double s = 0.0;
+        for (int m = (int)a.size() - 1; m >= 0; --m) s = s * y + a[m];
+        return s;
+    };
+    int d0 = p.degree, d1 = p.degree;
+    if (p.degree == 0) { d0 = 4; d1 = 16; }
+    for (int d = d0; d <= d1; ++d) {
+        coef.assign((size_t)P * (d + 1), 0.0);
+        double err = 0.0;
+        for (int j = 0; j < P; ++j) {
+            auto f = piece(j);
+            std::vector<double> a = cheb_fit(f, d);
+            for (int m = 0; m <= d; ++m) coef[(size_t)j * (d + 1) + m] = a[m];
+            for (int t = 0; t <= 64; ++t) {
+                const double y = -0.5 + t / 64.0;
+                err = std::max(err, std::fabs(eval(a, y) - f(y)));
+            }
+        }
+        if (p.degree != 0 || err <= 0.05 * p.tol * peak || d == d1) {
+            p.degree = d;
+            return;
+        }
+    }
+}
+
+void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<double>& Tphi) {
+    Prolate chi(p.c), win(p.c1);
+    const int n = p.nf, h2 = n / 2, P = p.P;
+    const double L = p.L, h = p.h, I1 = chi.integral(1.0);
+    TS.assign(3 * h2 * h2 + 1, 0.0);
+    const double pref = std::pow(h, 6) / (L * L * L);
+    for (int m2 = 1; m2 <= 3 * h2 * h2; ++m2) {
+        const double k = 2 * kPi * std::sqrt((double)m2) / L;
+        const double chat = 0.5 * chi.ft(p.rc * k) / I1;
+        TS[m2] = pref * chat / (k * k);
+    }
+    Tphi.assign(h2 + 1, 0.0);
+    for (int m = 0; m <= h2; ++m) {
+        const double xi = 2 * kPi * m / L;
+        const double ph = 0.5 * P * h * win.ft(xi * P * h / 2);
+        Tphi[m] = 1.0 / (ph * ph);
+    }
+}
+
+void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, double* dLr) {
+    Prolate chi(p.c);
+    const double I1 = chi.integral(1.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const double t = r[i] / p.rc;
+        if (t >= 1.0) {
+            Lr[i] = 0.0;
+            dLr[i] = 0.0;
+            continue;
+        }
+        const double G = chi.integral(t) / I1;
+        const double ch = chi(t) / I1;
+        Lr[i] = (1.0 - G) / (4 * kPi * r[i]);
+        dLr[i] = -(1.0 - G) / (4 * kPi * r[i] * r[i]) - ch / (p.rc * 4 * kPi * r[i]);
+    }
+}
+
+}  // namespace esp

@@ -1,0 +1,56 @@
+// Host-side (FP64) parameter selection and table generation for the ESP
+// long-range pipeline. No device code here.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "esp.h"
+
+namespace esp {
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// psi_0^c, L2-normalised on [-1, 1], psi(0) > 0: eigenvector of the prolate
+// differential operator -(d/dx)(1-x^2)(d/dx) + c^2 x^2 with the smallest
+// eigenvalue, expanded in the orthonormal even Legendre functions
+// (Slepian & Pollak 1961). Eigenvalue by Sturm-sequence bisection, vector by
+// inverse iteration on the tridiagonal matrix.
+class Prolate {
+  public:
+    explicit Prolate(double c);
+    double c() const { return c_; }
+    double operator()(double x) const;     // psi(x), |x| <= 1
+    double deriv(double x) const;          // psi'(x)
+    double integral(double x) const;       // int_0^x psi
+    double ft(double w) const;             // int_{-1}^{1} psi(t) cos(w t) dt
+  private:
+    double c_;
+    std::vector<double> a_;                // psi = sum_k a_k P_{2k}(x)
+    std::vector<double> qx_, qw_psi_;      // quadrature nodes, w * psi(nodes)
+};
+
+double c_for_tolerance(double eps);
+int order_for_tol(double tol);
+bool is_smooth(int n);
+int grid_size(double L, double h_max);
+double aliasing_error(int n, double L, const Prolate& chi, double rc, double c1, int P);
+
+struct Resolved {
+    esp_params p;                // fully resolved parameters
+    std::vector<double> poly;    // P * (degree + 1)
+    std::vector<double> TS;      // 3 (n/2)^2 + 1
+    std::vector<double> Tphi;    // n/2 + 1
+};
+
+// Resolve parameters; returns ESP_OK or an error with msg filled in.
+esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req,
+                          esp_params* out, std::string& msg);
+// Window polynomials for resolved params (fits degree if p.degree == 0 and
+// writes it back).
+void window_polynomials(esp_params& p, std::vector<double>& coef);
+void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<double>& Tphi);
+void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, double* dLr);
+
+}  // namespace esp

@@ -1,0 +1,211 @@
+"""Thin ctypes binding of libesp.so with the C ABI's names.
+
+Argument marshalling only: every step of the pipeline runs in the HIP
+library. Device buffers are torch tensors on the plan's GPU; their data
+pointers are handed to the library, and the plan's HIP stream is ordered
+after torch's current stream before each call (and torch's stream after it).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libesp.so")
+_lib = None
+
+STATUS = {0: "ESP_OK", -1: "ESP_E_INVALID", -2: "ESP_E_UNSUPPORTED", -3: "ESP_E_NOT_NEUTRAL",
+          -4: "ESP_E_NOMEM", -5: "ESP_E_DEVICE", -6: "ESP_E_BUSY"}
+
+
+class EspError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class esp_params(C.Structure):
+    _fields_ = [("nf", C.c_int), ("P", C.c_int), ("degree", C.c_int), ("precision", C.c_int),
+                ("tile", C.c_int), ("deterministic", C.c_int),
+                ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
+                ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
+                ("s0", C.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.POINTER
+_vp = C.c_void_p
+_SIGS = {
+    "esp_plan_query": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(esp_params), _P(esp_params)]),
+    "esp_window_coeffs": (C.c_int, [_P(esp_params), _P(C.c_double)]),
+    "esp_influence_tables": (C.c_int, [_P(esp_params), _P(C.c_double), _P(C.c_double)]),
+    "esp_local_kernel": (C.c_int, [_P(esp_params), _P(C.c_double), C.c_int64, _P(C.c_double), _P(C.c_double)]),
+    "esp_plan_create": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(_vp)]),
+    "esp_plan_create_ex": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(esp_params), _P(_vp)]),
+    "esp_batch_create": (C.c_int, [C.c_int, _P(C.c_double), _P(C.c_int64), _P(C.c_double), _P(esp_params),
+                                   _P(_vp)]),
+    "esp_plan_get_params": (C.c_int, [_vp, C.c_int, _P(esp_params)]),
+    "esp_plan_num_systems": (C.c_int, [_vp]),
+    "esp_plan_stream": (_vp, [_vp]),
+    "esp_longrange": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(C.c_double)]),
+    "esp_longrange_async": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "esp_plan_sync": (C.c_int, [_vp]),
+    "esp_plan_set_graph": (C.c_int, [_vp, C.c_int]),
+    "esp_plan_destroy": (None, [_vp]),
+    "esp_debug_stage": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
+    "esp_last_error": (C.c_char_p, []),
+    "esp_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libesp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with python -m paper_2505_09727_amd.build")
+        L = C.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise EspError(status, lib().esp_last_error().decode())
+
+
+def _req(**kw) -> esp_params:
+    p = esp_params()
+    for k, v in kw.items():
+        if v is not None:
+            setattr(p, k, v)
+    return p
+
+
+def _box(L):
+    return (C.c_double * 3)(L, L, L)
+
+
+def esp_version() -> str:
+    return lib().esp_version().decode()
+
+
+def esp_plan_query(box, N, tol, **req):
+    """Resolved parameters (dict) for a cubic box; host only."""
+    b = (C.c_double * 3)(*box) if np.ndim(box) else _box(float(box))
+    out = esp_params()
+    _check(lib().esp_plan_query(b, int(N), float(tol), C.byref(_req(**req)), C.byref(out)))
+    return out
+
+
+def esp_window_coeffs(params: esp_params) -> np.ndarray:
+    c = np.zeros(params.P * (params.degree + 1))
+    _check(lib().esp_window_coeffs(C.byref(params), c.ctypes.data_as(_P(C.c_double))))
+    return c.reshape(params.P, params.degree + 1)
+
+
+def esp_influence_tables(params: esp_params):
+    h2 = params.nf // 2
+    TS = np.zeros(3 * h2 * h2 + 1)
+    Tphi = np.zeros(h2 + 1)
+    _check(lib().esp_influence_tables(C.byref(params), TS.ctypes.data_as(_P(C.c_double)),
+                                      Tphi.ctypes.data_as(_P(C.c_double))))
+    return TS, Tphi
+
+
+def esp_local_kernel(params: esp_params, r):
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    Lr, dLr = np.zeros_like(r), np.zeros_like(r)
+    dp = _P(C.c_double)
+    _check(lib().esp_local_kernel(C.byref(params), r.ctypes.data_as(dp), len(r), Lr.ctypes.data_as(dp),
+                                  dLr.ctypes.data_as(dp)))
+    return Lr, dLr
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A single-system or batched plan (esp_plan_create_ex / esp_batch_create)."""
+
+    def __init__(self, L, N, tol, **req):
+        self._h = C.c_void_p()
+        if np.ndim(L) == 0:
+            _check(lib().esp_plan_create_ex(_box(float(L)), int(N), float(tol), C.byref(_req(**req)),
+                                            C.byref(self._h)))
+        else:
+            Ls = np.ascontiguousarray(L, dtype=np.float64)
+            Ns = np.ascontiguousarray(N, dtype=np.int64)
+            tols = np.ascontiguousarray(np.broadcast_to(tol, Ls.shape), dtype=np.float64)
+            reqs = (esp_params * len(Ls))(*[_req(**req) for _ in range(len(Ls))])
+            _check(lib().esp_batch_create(len(Ls), Ls.ctypes.data_as(_P(C.c_double)),
+                                          Ns.ctypes.data_as(_P(C.c_int64)), tols.ctypes.data_as(_P(C.c_double)),
+                                          reqs, C.byref(self._h)))
+        self.nsys = lib().esp_plan_num_systems(self._h)
+        self.params = [self.get_params(s) for s in range(self.nsys)]
+        self.precision = self.params[0].precision
+
+    def get_params(self, sys: int = 0) -> esp_params:
+        out = esp_params()
+        _check(lib().esp_plan_get_params(self._h, sys, C.byref(out)))
+        return out
+
+    @property
+    def stream(self):
+        return lib().esp_plan_stream(self._h)
+
+    def _order_after_torch(self):
+        import torch
+        ext = torch.cuda.ExternalStream(self.stream)
+        ext.wait_stream(torch.cuda.current_stream())
+        return ext
+
+    def longrange(self, pos, q, phi=None, F=None, energy=True):
+        """Enqueue esp_longrange; returns the energies (numpy, one per system) or None."""
+        import torch
+        ext = self._order_after_torch()
+        E = (C.c_double * self.nsys)() if energy else None
+        st = lib().esp_longrange(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), E)
+        torch.cuda.current_stream().wait_stream(ext)
+        _check(st)
+        return np.array(E[:]) if energy else None
+
+    def longrange_async(self, pos, q, phi=None, F=None, E_dev=None):
+        import torch
+        ext = self._order_after_torch()
+        st = lib().esp_longrange_async(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), _ptr(E_dev))
+        torch.cuda.current_stream().wait_stream(ext)
+        _check(st)
+
+    def sync(self):
+        _check(lib().esp_plan_sync(self._h))
+
+    def set_graph(self, enable: bool = True):
+        _check(lib().esp_plan_set_graph(self._h, int(bool(enable))))
+
+    def debug_stage(self, pos, q, stage, out, grid_in=None):
+        import torch
+        ext = self._order_after_torch()
+        st = lib().esp_debug_stage(self._h, _ptr(pos), _ptr(q), _ptr(grid_in), int(stage), _ptr(out))
+        torch.cuda.current_stream().wait_stream(ext)
+        _check(st)
+
+    def close(self):
+        if self._h:
+            lib().esp_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,126 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol esp.h declares, and its parameter rules and tables agree with the
+independent CPU reference."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+esp = pytest.importorskip("paper_2505_09727_amd.esp")
+
+from oracle.fivestep import influence, phi_hat_1d          # noqa: E402
+from oracle.params import aliasing_error, esp_parameters    # noqa: E402
+from oracle.pswf import c_for_tolerance, pswf              # noqa: E402
+from oracle.split import PSWFSplit, L_and_dL               # noqa: E402
+
+
+def _lib_or_skip():
+    try:
+        return esp.lib()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "esp.h")).read()
+    names = set(re.findall(r"\b(esp_[a-z_0-9]+)\s*\(", hdr))
+    assert len(names) >= 18
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert "gfx950" in esp.esp_version()
+
+
+@pytest.mark.parametrize("L,N,tol,n,P", [(31.0, 9000, 1e-4, 32, 6), (100.0, 300000, 1e-5, 96, 8),
+                                         (22.56, 512, 1e-3, 24, 5)])
+def test_default_parameters_match_reference_rules(L, N, tol, n, P):
+    _lib_or_skip()
+    p = esp.esp_plan_query(L, N, tol)
+    ref = esp_parameters(L, tol)
+    assert (p.nf, p.P) == (n, P) == (ref["n"], ref["P"])
+    assert abs(p.c - c_for_tolerance(tol)) < 1e-9
+    assert abs(p.rc - ref["rc"]) < 1e-9
+    assert p.precision == 32 and p.tile == 8
+    # c1: the library's choice is (near-)optimal for the reference's E_A
+    ea = aliasing_error(p.nf, L, p.c, p.rc, p.c1, p.P)
+    ea_ref = aliasing_error(p.nf, L, p.c, p.rc, ref["c1"], p.P)
+    assert ea <= 1.01 * ea_ref
+    s0 = PSWFSplit(p.c, p.rc).S0()
+    assert abs(p.s0 - s0) < 1e-12 * s0
+
+
+@pytest.mark.parametrize("tol,P", [(1e-3, 5), (1e-4, 6), (1e-5, 8)])
+def test_window_polynomials_fit_pswf(tol, P):
+    _lib_or_skip()
+    p = esp.esp_plan_query(31.0, 9000, tol)
+    coef = esp.esp_window_coeffs(p)
+    assert coef.shape == (P, p.degree + 1)
+    psi = pswf(p.c1)
+    y = np.linspace(-0.5, 0.5, 101)
+    err = 0.0
+    for j in range(P):
+        fit = np.polynomial.polynomial.polyval(y, coef[j])
+        exact = psi(2 * (y + 0.5 + P / 2 - 1 - j) / P)
+        err = max(err, np.max(np.abs(fit - exact)))
+    assert err <= 0.05 * tol * psi(0.0)
+    # high-degree fit reproduces the window to rounding
+    p16 = esp.esp_plan_query(31.0, 9000, tol, degree=16)
+    c16 = esp.esp_window_coeffs(p16)
+    for j in range(P):
+        fit = np.polynomial.polynomial.polyval(y, c16[j])
+        assert np.max(np.abs(fit - psi(2 * (y + 0.5 + P / 2 - 1 - j) / P))) < 1e-10
+
+
+def test_influence_tables_match_reference():
+    _lib_or_skip()
+    p = esp.esp_plan_query(17.0, 1500, 1e-4, nf=18)
+    TS, Tphi = esp.esp_influence_tables(p)
+    pref = influence(p.nf, p.L, p.P, p.c, p.rc, p.c1)
+    n = p.nf
+    k = np.arange(n)
+    m = np.abs(np.where(k < n // 2, k, k - n))
+    m2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
+    plib = TS[m2] * Tphi[m][:, None, None] * Tphi[m][None, :, None] * Tphi[m][None, None, :]
+    assert plib[0, 0, 0] == 0.0
+    assert np.max(np.abs(plib - pref)) < 1e-10 * np.max(np.abs(pref))
+    ph = phi_hat_1d(2 * math.pi * np.arange(n // 2 + 1) / p.L, p.P, p.h, p.c1)
+    assert np.max(np.abs(Tphi * ph ** 2 - 1)) < 1e-10
+
+
+def test_local_kernel_matches_reference():
+    _lib_or_skip()
+    p = esp.esp_plan_query(31.0, 9000, 1e-4)
+    r = np.linspace(0.3, p.rc * 1.2, 50)
+    Lr, dLr = esp.esp_local_kernel(p, r)
+    Lo, dLo = L_and_dL(PSWFSplit(p.c, p.rc), r)
+    assert np.max(np.abs(Lr - Lo)) < 1e-11 * np.max(np.abs(Lo))
+    assert np.max(np.abs(dLr - dLo)) < 1e-11 * np.max(np.abs(dLo))
+    assert np.all(Lr[r >= p.rc] == 0)
+
+
+def test_table2_through_the_library():
+    _lib_or_skip()
+    for eps, c_tab, P_tab in [(1e-3, 9.5392, 5), (5e-4, 10.290, 5), (1e-4, 12.024, 6), (5e-5, 12.762, 7),
+                              (1e-5, 14.471, 8)]:
+        p = esp.esp_plan_query(31.0, 9000, eps)
+        assert abs(p.c - c_tab) < 3e-3 and p.P == P_tab
+
+
+@pytest.mark.parametrize("kw,box,tol,status", [
+    ({}, (10.0, 10.0, 11.0), 1e-4, -2),        # non-cubic
+    ({}, 10.0, 0.5, -1),                        # tolerance out of range
+    ({"nf": 10}, 10.0, 1e-4, -2),               # 10 is not 2^a 3^b
+    ({"nf": 192}, 10.0, 1e-4, -2),              # beyond the built FFT range
+    ({"P": 13}, 10.0, 1e-4, -2),
+    ({"precision": 16}, 10.0, 1e-4, -1),
+])
+def test_invalid_arguments_return_status(kw, box, tol, status):
+    _lib_or_skip()
+    with pytest.raises(esp.EspError) as ei:
+        esp.esp_plan_query(box, 100, tol, **kw)
+    assert ei.value.status == status
+    assert esp.lib().esp_last_error().decode() != ""
