@@ -72,7 +72,9 @@ typedef struct {
     int    P;             /* window width in grid points, 4..12 */
     int    degree;        /* window polynomial degree, 4..16 */
     int    precision;     /* 32 (default) or 64 */
-    int    tile;          /* particle bin edge in grid points, 4..16 (0: 8) */
+    int    tile;          /* particle bin edge in grid points, 4..16, rounded down to a
+                             divisor of nf (0: chosen per plan; reported by
+                             esp_plan_get_params, 0 from esp_plan_query) */
     int    deterministic; /* reserved: 1 requests a fixed reduction order */
     double c;             /* splitting-kernel PSWF shape parameter */
     double c1;            /* window PSWF shape parameter */
@@ -170,7 +172,7 @@ esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q,
  * stream with a HIP event between consecutive phases and writes the mean
  * milliseconds of each phase to ms[0..ESP_NUM_PHASES-1] (names from
  * esp_phase_name). Waits for the stream. */
-#define ESP_NUM_PHASES 10
+#define ESP_NUM_PHASES 9
 esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void* phi, void* F,
                             int reps, double* ms);
 const char* esp_phase_name(int phase);

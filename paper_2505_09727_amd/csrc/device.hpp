@@ -26,8 +26,12 @@ struct SysDesc {
     int ncol;         // number of x-column work items
     int pitem_off;    // first particle work item
     int npitem;       // number of particle work items
+    int E;            // edge of a bin's window tile, T + P - 1 + (P odd)
+    int hist_off;     // bin-major histogram / offset matrix, nbins x npitem
+    long long tb_off; // first real of this system's bin tiles, nbins x E^3
     double inv_L;     // 1/L
     double s0;        // self constant S(0)
+    double wmax3;     // cube of the window's peak value (fixed-point range)
 };
 
 // Work items: .x = system, .y (.z) = item coordinates inside the system.

@@ -11,6 +11,8 @@
 // spectrum n x n x (n/2+1) of each x-plane overwrites that plane in place.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -159,6 +161,19 @@ __device__ double block_sum(double v, double* red) {
     return t;  // valid in thread 0
 }
 
+__device__ double block_max(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+    return t;  // valid in thread 0
+}
+
 // Grid coordinate u in [0, n) of one position component.
 template <typename R>
 __device__ __forceinline__ R grid_coord(R x, R inv_L, int n) {
@@ -170,6 +185,7 @@ __device__ __forceinline__ R grid_coord(R x, R inv_L, int n) {
     return u;
 }
 
+// Bin of a particle: cells floor(u) grouped into T^3 blocks (T divides n).
 template <typename R>
 __device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
     const int nm1 = S.n - 1;
@@ -178,23 +194,26 @@ __device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
 }
 
 // ---------------------------------------------------------------------------
-// Zero a buffer of reals (graph-safe replacement for a memset).
+// Binning without global atomics.
+//
+// k_hist: one block per chunk of 256 particles of one system. Grid
+// coordinates, bin id, and the rank of the particle among the chunk's
+// particles of the same bin (LDS atomics); the chunk's bin counts go to column
+// `item` of the system's bin-major count matrix (plain stores). Also the chunk
+// sums of q, |q|, q^2 (neutrality check, self energy).
 template <typename R>
-__global__ void k_zero(R* __restrict__ p, long long count) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = R(0);
-}
-
-// Bin: grid coordinates, bin id, rank within the bin (atomic counter), and per
-// chunk sums of q, |q|, q^2 (for the neutrality check and the self energy).
-template <typename R>
-__global__ void __launch_bounds__(256) k_bin(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                             const R* __restrict__ pos, const R* __restrict__ q,
-                                             int* __restrict__ bin_count, int* __restrict__ rank,
-                                             double* __restrict__ bpart) {
+__global__ void __launch_bounds__(256) k_hist(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                              const R* __restrict__ pos, const R* __restrict__ q,
+                                              int* __restrict__ hist, int* __restrict__ rank,
+                                              double* __restrict__ bpart) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int* cnt = reinterpret_cast<int*>(smem_raw);
     __shared__ double red[16];
     const int2 wi = items[blockIdx.x];
     const SysDesc S = sys[wi.x];
+    const int t1 = S.n / S.T, nb = t1 * t1 * t1;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
     const int il = wi.y + threadIdx.x;
     double sq = 0.0, sa = 0.0, s2 = 0.0;
     if (il < S.N) {
@@ -203,37 +222,56 @@ __global__ void __launch_bounds__(256) k_bin(const SysDesc* __restrict__ sys, co
         const R ux = grid_coord(pos[3 * i + 0], inv_L, S.n);
         const R uy = grid_coord(pos[3 * i + 1], inv_L, S.n);
         const R uz = grid_coord(pos[3 * i + 2], inv_L, S.n);
-        const int b = S.tile_off + bin_of(ux, uy, uz, S);
-        rank[i] = atomicAdd(&bin_count[b], 1);
+        rank[i] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
         const double qq = (double)q[i];
         sq = qq;
         sa = fabs(qq);
         s2 = qq * qq;
     }
+    __syncthreads();
+    const int it = blockIdx.x - S.pitem_off;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[S.hist_off + b * S.npitem + it] = cnt[b];
+    const double qm = block_max(sa, red);
     const double t0 = block_sum(sq, red);
-    const double t1 = block_sum(sa, red);
+    const double t1s = block_sum(sa, red);
     const double t2 = block_sum(s2, red);
     if (threadIdx.x == 0) {
-        bpart[3 * blockIdx.x + 0] = t0;
-        bpart[3 * blockIdx.x + 1] = t1;
-        bpart[3 * blockIdx.x + 2] = t2;
+        bpart[4 * blockIdx.x + 0] = t0;
+        bpart[4 * blockIdx.x + 1] = t1s;
+        bpart[4 * blockIdx.x + 2] = t2;
+        bpart[4 * blockIdx.x + 3] = qm;
     }
 }
 
-// Exclusive scan of the bin counts of one system (one block per system); the
-// counters are cleared for the next call.
-__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, int nsys, int* __restrict__ bin_count,
-                                               int* __restrict__ bin_start) {
+// Exclusive scan of a system's bin-major count matrix (one block per system):
+// the entry (bin, item) becomes the first sorted slot of that chunk's
+// particles in that bin; bin_start[bin] is the first slot of the bin.
+__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, int nsys, int* __restrict__ hist,
+                                               int* __restrict__ bin_start, const double* __restrict__ bpart,
+                                               float* __restrict__ fx_scale) {
     __shared__ int warp_tot[16];
     __shared__ int carry_s;
+    __shared__ double red[16];
     const SysDesc S = sys[blockIdx.x];
-    const int nb = S.tiles1 * S.tiles1 * S.tiles1;
+    {
+        // fixed-point scale of the FP32 spread: 2^F with every single
+        // contribution |q w_x w_y w_z| 2^F <= 2^30 (exact through int32)
+        double qm = 0.0;
+        for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) qm = fmax(qm, bpart[4 * (S.pitem_off + i) + 3]);
+        qm = block_max(qm, red);
+        if (threadIdx.x == 0) {
+            const double bound = qm * S.wmax3;
+            const int F = bound > 0.0 ? 30 - (int)ceil(log2(bound)) : 30;
+            fx_scale[blockIdx.x] = ldexpf(1.0f, max(-100, min(100, F)));
+        }
+    }
+    const int t1 = S.n / S.T, nb = t1 * t1 * t1;
+    const int total = nb * S.npitem;
     if (threadIdx.x == 0) carry_s = S.part_off;
     __syncthreads();
-    for (int base = 0; base < nb; base += blockDim.x) {
-        const int i = base + threadIdx.x;
-        const int v = i < nb ? bin_count[S.tile_off + i] : 0;
-        // inclusive scan inside the wavefront
+    for (int base = 0; base < total; base += blockDim.x) {
+        const int l = base + threadIdx.x;
+        const int v = l < total ? hist[S.hist_off + l] : 0;
         int x = v;
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         for (int off = 1; off < 64; off <<= 1) {
@@ -245,9 +283,10 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
         int before = 0;
         for (int w = 0; w < wid; ++w) before += warp_tot[w];
         const int carry = carry_s;
-        if (i < nb) {
-            bin_start[S.tile_off + i] = carry + before + x - v;
-            bin_count[S.tile_off + i] = 0;
+        if (l < total) {
+            const int off = carry + before + x - v;
+            hist[S.hist_off + l] = off;
+            if (l % S.npitem == 0) bin_start[S.tile_off + l / S.npitem] = off;
         }
         __syncthreads();
         if (threadIdx.x == blockDim.x - 1) carry_s = carry + before + x;
@@ -261,7 +300,7 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
 template <typename R>
 __global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
                                                  const R* __restrict__ pos, const R* __restrict__ q,
-                                                 const int* __restrict__ rank, const int* __restrict__ bin_start,
+                                                 const int* __restrict__ rank, const int* __restrict__ offs,
                                                  typename Vec4<R>::type* __restrict__ sorted,
                                                  int* __restrict__ perm) {
     const int2 wi = items[blockIdx.x];
@@ -273,8 +312,8 @@ __global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys
     const R ux = grid_coord(pos[3 * i + 0], inv_L, S.n);
     const R uy = grid_coord(pos[3 * i + 1], inv_L, S.n);
     const R uz = grid_coord(pos[3 * i + 2], inv_L, S.n);
-    const int b = S.tile_off + bin_of(ux, uy, uz, S);
-    const int dst = bin_start[b] + rank[i];
+    const int b = bin_of(ux, uy, uz, S);
+    const int dst = offs[S.hist_off + b * S.npitem + (blockIdx.x - S.pitem_off)] + rank[i];
     typename Vec4<R>::type v;
     v.x = ux;
     v.y = uy;
@@ -329,55 +368,150 @@ __device__ __forceinline__ int wrapi(int g, int n) {
 }
 
 // Spread (eq. spread): one block per bin of T^3 grid cells. The block
-// accumulates its particles' P^3 windows into an LDS tile of (T+P)^3 points
-// with LDS atomics, then adds the tile to the periodic grid with global atomics.
+// accumulates its particles' P^3 windows into an LDS tile of E^3 points
+// (E = T + P - 1 + (P odd)) with LDS atomics and stores the whole tile, halo
+// included, to the bin's slot of the tile buffer with plain stores. The halos
+// of neighbouring bins are summed when the forward FFT loads its planes
+// (fold_point), so no global atomics are needed.
+//
+// LDS accumulator: FP32 plans accumulate in 64-bit fixed point (ds_add_u64;
+// LDS float atomics are ~20x slower than 64-bit integer ones on gfx950, and
+// integer sums are order-independent, so the spread is deterministic). Each
+// contribution q w_x w_y w_z is scaled by the system's 2^F and rounded to an
+// int32 (|value| <= 2^30 by the choice of F), the tile is converted back to
+// float when stored. FP64 plans accumulate with ds_add_f64.
+template <typename R> struct SpreadAcc {
+    using type = R;
+};
+template <> struct SpreadAcc<float> {
+    using type = unsigned long long;
+};
+
 template <typename R, int P>
 __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
                                                 const typename Vec4<R>::type* __restrict__ sorted,
                                                 const int* __restrict__ bin_start, const R* __restrict__ poly_all,
-                                                R* __restrict__ grid) {
+                                                const float* __restrict__ fx_scale, R* __restrict__ tiles) {
+    using A = typename SpreadAcc<R>::type;
+    constexpr bool kFixed = sizeof(A) != sizeof(R) || !std::is_floating_point<A>::value;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R* lds = reinterpret_cast<R*>(smem_raw);
+    A* lds = reinterpret_cast<A*>(smem_raw);
     const int2 wi = items[blockIdx.x];
     const SysDesc S = sys[wi.x];
-    const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
+    const int t = wi.y, T = S.T, t1 = S.tiles1;
     const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
     const int lo = -((P - 1) / 2);
-    const int E = T + P, E3 = E * E * E;
+    const int E = S.E, E3 = E * E * E;
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const int beg = bin_start[S.tile_off + t], end = bin_start[S.tile_off + t + 1];
-    if (beg == end) return;  // uniform over the block
-    for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = R(0);
+    R* out = tiles + S.tb_off + (long long)t * E3;
+    if (beg == end) {  // uniform over the block
+        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R(0);
+        return;
+    }
+    for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
     __syncthreads();
     const R* coef = poly_all + S.poly_off;
+    const R scale = kFixed ? R(fx_scale[wi.x]) : R(1);
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = sorted[k];
         R wx[P], wy[P], wz[P];
         const int bx = window<R, P>(v.x, coef, S.degree, wx) - ox;
         const int by = window<R, P>(v.y, coef, S.degree, wy) - oy;
         const int bz = window<R, P>(v.z, coef, S.degree, wz) - oz;
+        const R qs = v.w * scale;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
-            const R qa = v.w * wx[a];
+            const R qa = qs * wx[a];
 #pragma unroll
             for (int b = 0; b < P; ++b) {
                 const R qab = qa * wy[b];
-                R* row = lds + ((bx + a) * E + (by + b)) * E + bz;
+                A* row = lds + ((bx + a) * E + (by + b)) * E + bz;
 #pragma unroll
-                for (int c = 0; c < P; ++c) atomicAdd(row + c, qab * wz[c]);
+                for (int c = 0; c < P; ++c) {
+                    if constexpr (kFixed)
+                        atomicAdd(row + c, (A)(long long)__float2int_rn(qab * wz[c]));
+                    else
+                        atomicAdd(row + c, qab * wz[c]);
+                }
             }
         }
     }
     __syncthreads();
-    R* g = grid + S.grid_off;
-    const int rl = n + 2;
-    for (int i = threadIdx.x; i < E3; i += blockDim.x) {
-        const R val = lds[i];
-        if (val != R(0)) {
-            const int a = i / (E * E), rem = i - a * E * E, b = rem / E, c = rem - b * E;
-            const int gx = wrapi(ox + a, n), gy = wrapi(oy + b, n), gz = wrapi(oz + c, n);
-            atomicAdd(g + ((long long)gx * n + gy) * rl + gz, val);
+    if constexpr (kFixed) {
+        const R inv = R(1) / scale;
+        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((long long)lds[i]) * inv;
+    } else {
+        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = lds[i];
+    }
+}
+
+// The (bin, offset) pairs of one axis whose tiles cover grid index g: bin t's
+// tile starts at t*T + lo (mod n) and spans E points, so g lies at offset
+// o = (g - lo - t*T) mod n (and o + n, o + 2n, ... while below E).
+__device__ __forceinline__ int covering(int g, int lo, int T, int t1, int n, int E, int* tb, int* off) {
+    int gm = (g - lo) % n;
+    if (gm < 0) gm += n;
+    const int tf = gm / T;
+    const int o1 = gm - tf * T;
+    int c = 0;
+    for (int k = 0; o1 + k * T < E && c < 4; ++k) {
+        int tt = (tf - k) % t1;
+        if (tt < 0) tt += t1;
+        tb[c] = tt;
+        off[c] = o1 + k * T;
+        ++c;
+    }
+    return c;
+}
+
+// Covering lists of all n indices of an axis, built once per block in LDS:
+// cov[g] = count, then up to 4 (bin, offset) pairs.
+struct CoverTab {
+    int cnt;
+    int bin[4];
+    int off[4];
+};
+
+__device__ __forceinline__ void build_cover(CoverTab* tab, const SysDesc& S, int lo) {
+    for (int g = threadIdx.x; g < S.n; g += blockDim.x) {
+        CoverTab c;
+        c.cnt = covering(g, lo, S.T, S.tiles1, S.n, S.E, c.bin, c.off);
+        tab[g] = c;
+    }
+}
+
+// b_l for one grid point, summed over every bin tile that covers it.
+template <typename R>
+__device__ __forceinline__ R fold_point(const R* __restrict__ tiles, const SysDesc& S, const CoverTab& cx,
+                                        const CoverTab& cy, const CoverTab& cz) {
+    const int t1 = S.tiles1, E = S.E;
+    const long long E3 = (long long)E * E * E;
+    R acc = R(0);
+    for (int a = 0; a < cx.cnt; ++a)
+        for (int b = 0; b < cy.cnt; ++b) {
+            const long long base = S.tb_off + ((long long)cx.bin[a] * t1 + cy.bin[b]) * t1 * E3 +
+                                   ((long long)cx.off[a] * E + cy.off[b]) * E;
+            for (int c = 0; c < cz.cnt; ++c) acc += tiles[base + (long long)cz.bin[c] * E3 + cz.off[c]];
         }
+    return acc;
+}
+
+// Diagnostics: fold the bin tiles into the padded real grid (b_l of eq. spread).
+template <typename R>
+__global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                              const R* __restrict__ tiles, R* __restrict__ grid) {
+    __shared__ CoverTab tab[145];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc S = sys[wi.x];
+    const int n = S.n, lo = -((S.P - 1) / 2);
+    build_cover(tab, S, lo);
+    __syncthreads();
+    const CoverTab cx = tab[wi.y];
+    R* plane = grid + S.grid_off + (long long)wi.y * n * (n + 2);
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int y = idx / n, z = idx - y * n;
+        plane[y * (n + 2) + z] = fold_point(tiles, S, cx, tab[y], tab[z]);
     }
 }
 
@@ -396,7 +530,7 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
     const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
     const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
     const int lo = -((P - 1) / 2);
-    const int E = T + P, E3 = E * E * E;
+    const int E = S.E, E3 = E * E * E;
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const int beg = bin_start[S.tile_off + t], end = bin_start[S.tile_off + t + 1];
     if (beg == end) return;
@@ -456,9 +590,12 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
 // ---------------------------------------------------------------------------
 // Forward FFT along z (real-to-complex) and y for one x-plane. Pairs of real
 // rows (2r, 2r+1) are transformed as one complex row and split afterwards.
+// With tiles != nullptr the plane is assembled from the spread's bin tiles
+// (fold_point); otherwise it is read from the real grid.
 template <typename R, int MAXIT>
 __global__ void __launch_bounds__(512) k_fft_fwd_zy(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                    R* __restrict__ grid, const cplx<R>* __restrict__ tw_all) {
+                                                    R* __restrict__ grid, const cplx<R>* __restrict__ tw_all,
+                                                    const R* __restrict__ tiles) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wi = items[blockIdx.x];
     const SysDesc S = sys[wi.x];
@@ -467,9 +604,22 @@ __global__ void __launch_bounds__(512) k_fft_fwd_zy(const SysDesc* __restrict__ 
     cplx<R>* buf = tw + n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
     R* plane = grid + S.grid_off + (long long)wi.y * n * rl;
-    for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
-        const int r = idx / n, z = idx - r * n;
-        buf[idx] = {plane[(2 * r) * rl + z], plane[(2 * r + 1) * rl + z]};
+    if (tiles) {
+        CoverTab* tab = reinterpret_cast<CoverTab*>(buf + n * hs);
+        build_cover(tab, S, -((S.P - 1) / 2));
+        __syncthreads();
+        const CoverTab cx = tab[wi.y];
+        R* bufr = reinterpret_cast<R*>(buf);
+        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+            const int y = idx / n, z = idx - y * n;
+            // rows 2r and 2r+1 are the real and imaginary parts of pair-row r
+            bufr[2 * ((y >> 1) * n + z) + (y & 1)] = fold_point(tiles, S, cx, tab[y], tab[z]);
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
+            const int r = idx / n, z = idx - r * n;
+            buf[idx] = {plane[(2 * r) * rl + z], plane[(2 * r + 1) * rl + z]};
+        }
     }
     __syncthreads();
     fft_lines<R, MAXIT>(buf, n, half, n, 1, tw, +1, false);
@@ -619,9 +769,9 @@ __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sy
     double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < S.ncol; i += blockDim.x) ek += epart[S.col_off + i];
     for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) {
-        sq += bpart[3 * (S.pitem_off + i) + 0];
-        sa += bpart[3 * (S.pitem_off + i) + 1];
-        s2 += bpart[3 * (S.pitem_off + i) + 2];
+        sq += bpart[4 * (S.pitem_off + i) + 0];
+        sa += bpart[4 * (S.pitem_off + i) + 1];
+        s2 += bpart[4 * (S.pitem_off + i) + 2];
     }
     ek = block_sum(ek, red);
     sq = block_sum(sq, red);
@@ -650,24 +800,21 @@ static hipError_t allow_lds(K kernel, int bytes) {
 
 template <typename R>
 static hipError_t prepare_t(const Launch& L, int phase, const void* pos, const void* q) {
+    hipError_t e;
     switch (phase) {
-        case 0: {
-            const long long cnt = L.grid_reals;
-            const int blocks = (int)std::min<long long>((cnt + 255) / 256, 4096);
-            k_zero<R><<<blocks, 256, 0, L.stream>>>(reinterpret_cast<R*>(L.grid), cnt);
+        case 0:
+            if ((e = allow_lds(k_hist<R>, L.hist_lds)) != hipSuccess) return e;
+            k_hist<R><<<L.n_pitems, 256, L.hist_lds, L.stream>>>(L.sys, L.pitems, reinterpret_cast<const R*>(pos),
+                                                                 reinterpret_cast<const R*>(q), L.hist, L.rank,
+                                                                 L.bpart);
             break;
-        }
         case 1:
-            k_bin<R><<<L.n_pitems, 256, 0, L.stream>>>(L.sys, L.pitems, reinterpret_cast<const R*>(pos),
-                                                       reinterpret_cast<const R*>(q), L.bin_count, L.rank, L.bpart);
+            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.nsys, L.hist, L.bin_start, L.bpart, L.fx_scale);
             break;
         case 2:
-            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.nsys, L.bin_count, L.bin_start);
-            break;
-        case 3:
             k_scatter<R><<<L.n_pitems, 256, 0, L.stream>>>(
-                L.sys, L.pitems, reinterpret_cast<const R*>(pos), reinterpret_cast<const R*>(q), L.rank,
-                L.bin_start, reinterpret_cast<typename Vec4<R>::type*>(L.sorted), L.perm);
+                L.sys, L.pitems, reinterpret_cast<const R*>(pos), reinterpret_cast<const R*>(q), L.rank, L.hist,
+                reinterpret_cast<typename Vec4<R>::type*>(L.sorted), L.perm);
             break;
         default:
             return hipErrorInvalidValue;
@@ -685,7 +832,17 @@ static hipError_t spread_p(const Launch& L, const Group& G) {
     if (e != hipSuccess) return e;
     k_spread<R, P><<<G.count, 256, G.lds, L.stream>>>(
         L.sys, L.titems + G.off, reinterpret_cast<const typename Vec4<R>::type*>(L.sorted), L.bin_start,
-        reinterpret_cast<const R*>(L.poly), reinterpret_cast<R*>(L.grid));
+        reinterpret_cast<const R*>(L.poly), L.fx_scale, reinterpret_cast<R*>(L.tiles));
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const Launch& L) {
+    if (L.prec == 64)
+        k_fold<double><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes, reinterpret_cast<const double*>(L.tiles),
+                                                         reinterpret_cast<double*>(L.grid));
+    else
+        k_fold<float><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes, reinterpret_cast<const float*>(L.tiles),
+                                                        reinterpret_cast<float*>(L.grid));
     return hipGetLastError();
 }
 
@@ -731,7 +888,8 @@ static hipError_t fft_t(const Launch& L, int which, int mode) {
     hipError_t e;
     if (which == 0) {
         if ((e = allow_lds(k_fft_fwd_zy<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
-        k_fft_fwd_zy<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes, grid, tw);
+        k_fft_fwd_zy<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(
+            L.sys, L.planes, grid, tw, mode == 3 ? nullptr : reinterpret_cast<const R*>(L.tiles));
     } else if (which == 1) {
         if ((e = allow_lds(k_fft_x<R, MAXIT>, L.col_lds)) != hipSuccess) return e;
         k_fft_x<R, MAXIT><<<L.n_cols, 256, L.col_lds, L.stream>>>(L.sys, L.cols, grid, tw,

@@ -34,9 +34,12 @@ struct Launch {
     void* sorted;
     int* perm;
     int* rank;
-    int* bin_count;
+    int* hist;            // bin-major count / offset matrices
+    int hist_lds;         // LDS bytes of the per-chunk histogram
     int* bin_start;
-    double* bpart;
+    void* tiles;          // spread tiles, nbins x E^3 reals per system
+    double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
+    float* fx_scale;      // per system: fixed-point scale 2^F of the FP32 spread
     double* epart;
     double* eout;
     const void* TS;
@@ -45,12 +48,15 @@ struct Launch {
     const void* tw;
 };
 
-// Preparation phases: 0 zero the grid, 1 bin, 2 scan the bin counts,
-// 3 scatter into bin order.
+// Preparation phases: 0 per-chunk bin histograms, 1 scan, 2 scatter into
+// bin order.
 hipError_t launch_prepare(const Launch& L, int phase, const void* pos, const void* q);
 hipError_t launch_spread(const Launch& L, const Group& G);
-// which: 0 forward z/y planes, 1 x-columns with scaling (mode 0 full,
-// 1 forward only, 2 forward + scaling), 2 inverse y/z planes.
+// Diagnostics: fold the spread tiles into the real grid.
+hipError_t launch_fold(const Launch& L);
+// which: 0 forward z/y planes (mode 3: read the real grid instead of the
+// spread tiles), 1 x-columns with scaling (mode 0 full, 1 forward only,
+// 2 forward + scaling), 2 inverse y/z planes.
 hipError_t launch_fft(const Launch& L, int which, int mode);
 hipError_t launch_gather(const Launch& L, const Group& G, void* phi, void* F);
 hipError_t launch_finalize(const Launch& L, double* E_dev);

@@ -275,8 +275,7 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.rc <= 0) r.rc = r.kappa * r.c * r.h / kPi;
     if (r.precision == 0) r.precision = 32;
     if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
-    if (r.tile == 0) r.tile = 8;
-    if (r.tile < 4 || r.tile > 16) { msg = "tile must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
+    if (r.tile != 0 && (r.tile < 4 || r.tile > 16)) { msg = "tile must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
     Prolate chi(r.c);
     if (r.c1 <= 0) {
         double best = std::numeric_limits<double>::infinity(), bc1 = r.c;

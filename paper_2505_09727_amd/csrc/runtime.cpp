@@ -105,6 +105,27 @@ esp_status upload(esp_plan* p, void** dst, const void* src, size_t bytes) {
     return ESP_OK;
 }
 
+// Bin edge T for a system: a divisor of n so bins tile the periodic grid
+// exactly. A requested edge is rounded down to a divisor; otherwise the
+// largest divisor in [8, 16] that still gives the system its share
+// (`target` bins) of a few hundred spread blocks, else the smallest one.
+int choose_tile(int n, int requested, long long target) {
+    if (requested > 0) {
+        for (int d = std::min(requested, n); d >= 4; --d)
+            if (n % d == 0) return d;
+        return n;
+    }
+    int best = 0, smallest = 0;
+    for (int d = 16; d >= 8; --d) {
+        if (n % d) continue;
+        smallest = d;
+        const long long nb = (long long)(n / d) * (n / d) * (n / d);
+        if (!best && nb >= target) best = d;
+    }
+    if (best) return best;
+    return smallest ? smallest : n;
+}
+
 esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const double* tols, const esp_params* reqs,
                       bool per_system_req, esp_plan** out) {
     if (!out) return fail(ESP_E_INVALID, "out is NULL");
@@ -126,6 +147,11 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
         Ntot += Ns[s];
     }
     if (Ntot > (int64_t)1 << 30) return bail(fail(ESP_E_UNSUPPORTED, "more than 2^30 particles in one plan"));
+    for (int s = 0; s < nsys; ++s) {
+        const esp_params* req = reqs ? (per_system_req ? &reqs[s] : reqs) : nullptr;
+        const long long target = (512LL * Ns[s] + Ntot - 1) / Ntot;
+        p->prm[s].tile = choose_tile(p->prm[s].nf, req ? req->tile : 0, target);
+    }
     p->prec = p->prm[0].precision;
     for (int s = 1; s < nsys; ++s)
         if (p->prm[s].precision != p->prec)
@@ -138,8 +164,8 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
     std::vector<int4> cols;
     std::vector<std::vector<int2>> titems_by_P(13);
     p->hsys.resize(nsys);
-    long long grid_off = 0;
-    int part_off = 0, tile_off = 0;
+    long long grid_off = 0, hist_total = 0, tiles_total = 0;
+    int part_off = 0, tile_off = 0, nb_max = 1;
     int nmax = 0, KBmax = 1;
     for (int s = 0; s < nsys; ++s) {
         esp_params& r = p->prm[s];
@@ -149,12 +175,29 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
         d.N = (int)Ns[s];
         d.part_off = part_off;
         d.T = r.tile;
-        d.tiles1 = (r.nf + r.tile - 1) / r.tile;
+        d.tiles1 = r.nf / r.tile;
+        d.E = r.tile + r.P - 1 + (r.P & 1);
         d.tile_off = tile_off;
         d.degree = r.degree;
         d.grid_off = grid_off;
         d.inv_L = 1.0 / r.L;
         d.s0 = r.s0;
+        {
+            // peak of the window polynomials (slightly above psi(0) at most)
+            double wm = 0.0;
+            std::vector<double> pc0;
+            esp_params rr = r;
+            window_polynomials(rr, pc0);
+            for (int j = 0; j < r.P; ++j)
+                for (int t = 0; t <= 64; ++t) {
+                    const double y = -0.5 + t / 64.0;
+                    double v = 0.0;
+                    for (int m = r.degree; m >= 0; --m) v = v * y + pc0[(size_t)j * (r.degree + 1) + m];
+                    wm = std::max(wm, std::fabs(v));
+                }
+            wm *= 1.001;
+            d.wmax3 = wm * wm * wm;
+        }
         std::vector<double> ts, tp, pc;
         influence_tables(r, ts, tp);
         window_polynomials(r, pc);
@@ -174,6 +217,11 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
         for (int c = 0; c < d.N; c += kParticleChunk) pitems.push_back(make_int2(s, c));
         d.npitem = (int)pitems.size() - d.pitem_off;
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
+        d.hist_off = (int)hist_total;
+        hist_total += (long long)nb * d.npitem;
+        d.tb_off = tiles_total;
+        tiles_total += (long long)nb * d.E * d.E * d.E;
+        nb_max = std::max(nb_max, nb);
         for (int t = 0; t < nb; ++t) titems_by_P[r.P].push_back(make_int2(s, t));
         for (int x = 0; x < r.nf; ++x) planes.push_back(make_int2(s, x));
         const int hs = r.nf / 2 + 1;
@@ -199,8 +247,8 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
         g.count = (int)titems_by_P[P].size();
         int lds = 0;
         for (const int2& it : titems_by_P[P]) {
-            const int E = p->hsys[it.x].T + P;
-            lds = std::max(lds, E * E * E * rb);
+            const int E = p->hsys[it.x].E;
+            lds = std::max(lds, E * E * E * 8);  // 64-bit accumulators (fixed point or double)
         }
         g.lds = lds;
         if (lds > kMaxLds) return bail(fail(ESP_E_UNSUPPORTED, "bin tile (T+P)^3 exceeds LDS; reduce tile"));
@@ -219,7 +267,7 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
     int need = 1;
     for (const SysDesc& d : p->hsys) need = std::max(need, ((d.n / 2 + 1) * (d.n / 2) + L.plane_bd - 1) / L.plane_bd);
     L.plane_maxit = need;
-    L.plane_lds = (nmax + nmax * (nmax / 2 + 1)) * 2 * rb;
+    L.plane_lds = (nmax + nmax * (nmax / 2 + 1)) * 2 * rb + (nmax + 1) * 9 * 4;  // + covering tables
     int needc = 1;
     for (const SysDesc& d : p->hsys) needc = std::max(needc, (KBmax * d.n / 2 + 255) / 256);
     L.col_maxit = needc;
@@ -270,12 +318,18 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
     L.sorted = so;
     if ((st = p->alloc(&L.perm, (size_t)Ntot)) != ESP_OK) return bail(st);
     if ((st = p->alloc(&L.rank, (size_t)Ntot)) != ESP_OK) return bail(st);
-    if ((st = p->alloc(&L.bin_count, (size_t)tile_off)) != ESP_OK) return bail(st);
+    if (hist_total > (1LL << 31) - 1) return bail(fail(ESP_E_UNSUPPORTED, "bin histogram too large"));
+    if ((st = p->alloc(&L.hist, (size_t)hist_total)) != ESP_OK) return bail(st);
+    L.hist_lds = nb_max * 4;
+    if (L.hist_lds > kMaxLds) return bail(fail(ESP_E_UNSUPPORTED, "too many bins per system; raise tile"));
+    unsigned char* tb = nullptr;
+    if ((st = p->alloc(&tb, (size_t)tiles_total * rb)) != ESP_OK) return bail(st);
+    L.tiles = tb;
     if ((st = p->alloc(&L.bin_start, (size_t)tile_off + 1)) != ESP_OK) return bail(st);
-    if ((st = p->alloc(&L.bpart, (size_t)3 * pitems.size())) != ESP_OK) return bail(st);
+    if ((st = p->alloc(&L.bpart, (size_t)4 * pitems.size())) != ESP_OK) return bail(st);
+    if ((st = p->alloc(&L.fx_scale, (size_t)nsys)) != ESP_OK) return bail(st);
     if ((st = p->alloc(&L.epart, cols.size())) != ESP_OK) return bail(st);
     if ((st = p->alloc(&L.eout, (size_t)4 * nsys)) != ESP_OK) return bail(st);
-    HIP_TRY(hipMemset(L.bin_count, 0, sizeof(int) * (size_t)tile_off));
     HIP_TRY(hipHostMalloc((void**)&p->h_eout, sizeof(double) * 4 * nsys, hipHostMallocDefault));
     HIP_TRY(hipStreamCreate(&p->stream));
     p->own_stream = true;
@@ -286,25 +340,24 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
 }
 
 // Pipeline phases (one kernel launch each, or one per window-width group).
-enum Phase { kZero, kBin, kScan, kScatter, kSpread, kFftZY, kFftX, kFftYZ, kGather, kFinalize, kNumPhases };
-const char* const kPhaseNames[kNumPhases] = {"zero", "bin", "scan", "scatter", "spread",
-                                             "fft_zy", "fft_x_scale", "fft_yz", "gather", "finalize"};
+enum Phase { kHist, kScan, kScatter, kSpread, kFftZY, kFftX, kFftYZ, kGather, kFinalize, kNumPhases };
+const char* const kPhaseNames[kNumPhases] = {"hist", "scan", "scatter", "spread", "fft_zy",
+                                             "fft_x_scale", "fft_yz", "gather", "finalize"};
 
 esp_status run_phase(esp_plan* p, int ph, const void* pos, const void* q, void* phi, void* F, double* E_dev,
                      int fft_mode) {
     Launch& L = p->L;
     switch (ph) {
-        case kZero:
-        case kBin:
+        case kHist:
         case kScan:
         case kScatter:
-            HIP_TRY(launch_prepare(L, ph - kZero, pos, q));
+            HIP_TRY(launch_prepare(L, ph - kHist, pos, q));
             break;
         case kSpread:
             for (const Group& G : p->groups) HIP_TRY(launch_spread(L, G));
             break;
         case kFftZY:
-            HIP_TRY(launch_fft(L, 0, 0));
+            HIP_TRY(launch_fft(L, 0, fft_mode));
             break;
         case kFftX:
             HIP_TRY(launch_fft(L, 1, fft_mode));
@@ -322,21 +375,32 @@ esp_status run_phase(esp_plan* p, int ph, const void* pos, const void* q, void* 
     return ESP_OK;
 }
 
-// Enqueue the pipeline up to `upto` (0 = everything).
+// Enqueue the pipeline; upto = 0 runs everything, 1..4 stop after a stage
+// (diagnostics; see esp_debug_stage). With grid_in the spread is replaced by a
+// copy of the caller's real grid.
 esp_status enqueue(esp_plan* p, const void* pos, const void* q, void* phi, void* F, double* E_dev, int upto,
                    const void* grid_in) {
     Launch& L = p->L;
     esp_status s;
-    int first = kZero;
     if (grid_in) {
         HIP_TRY(hipMemcpyAsync(L.grid, grid_in, (size_t)L.grid_reals * (p->prec == 64 ? 8 : 4),
                                hipMemcpyDeviceToDevice, L.stream));
-        first = kFftZY;
+    } else {
+        for (int ph = kHist; ph <= kSpread; ++ph)
+            if ((s = run_phase(p, ph, pos, q, phi, F, E_dev, 0)) != ESP_OK) return s;
+        if (upto == 1) {
+            HIP_TRY(launch_fold(L));
+            return ESP_OK;
+        }
     }
-    const int last = upto == 1 ? kSpread : (upto == 2 || upto == 3) ? kFftX : upto == 4 ? kFftYZ : kFinalize;
-    const int mode = upto == 2 ? 1 : upto == 3 ? 2 : 0;
-    for (int ph = first; ph <= last; ++ph)
-        if ((s = run_phase(p, ph, pos, q, phi, F, E_dev, mode)) != ESP_OK) return s;
+    const int xmode = upto == 2 ? 1 : upto == 3 ? 2 : 0;
+    if ((s = run_phase(p, kFftZY, pos, q, phi, F, E_dev, grid_in ? 3 : 0)) != ESP_OK) return s;
+    if ((s = run_phase(p, kFftX, pos, q, phi, F, E_dev, xmode)) != ESP_OK) return s;
+    if (upto == 2 || upto == 3) return ESP_OK;
+    if ((s = run_phase(p, kFftYZ, pos, q, phi, F, E_dev, 0)) != ESP_OK) return s;
+    if (upto == 4) return ESP_OK;
+    for (int ph = kGather; ph <= kFinalize; ++ph)
+        if ((s = run_phase(p, ph, pos, q, phi, F, E_dev, 0)) != ESP_OK) return s;
     return ESP_OK;
 }
 

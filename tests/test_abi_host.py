@@ -44,7 +44,7 @@ def test_default_parameters_match_reference_rules(L, N, tol, n, P):
     assert (p.nf, p.P) == (n, P) == (ref["n"], ref["P"])
     assert abs(p.c - c_for_tolerance(tol)) < 1e-9
     assert abs(p.rc - ref["rc"]) < 1e-9
-    assert p.precision == 32 and p.tile == 8
+    assert p.precision == 32 and p.tile == 0
     # c1: the library's choice is (near-)optimal for the reference's E_A
     ea = aliasing_error(p.nf, L, p.c, p.rc, p.c1, p.P)
     ea_ref = aliasing_error(p.nf, L, p.c, p.rc, ref["c1"], p.P)
