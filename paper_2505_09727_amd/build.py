@@ -39,6 +39,7 @@ def build(verbose: bool = False) -> str:
     jobs = [
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(OUT_DIR, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "runtime.cpp"), "-o", os.path.join(OUT_DIR, "runtime.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "assembly.cpp"), "-o", os.path.join(OUT_DIR, "assembly.o")],
         ["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "plan.cpp"), "-o", os.path.join(OUT_DIR, "plan.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:

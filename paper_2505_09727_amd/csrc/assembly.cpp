@@ -1,0 +1,302 @@
+// Launch-set assembly (see assembly.hpp).
+#include "assembly.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace esp {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+std::vector<unsigned char> to_prec(const std::vector<double>& v, int prec) {
+    std::vector<unsigned char> out(v.size() * (prec == 64 ? 8 : 4));
+    if (prec == 64) {
+        std::memcpy(out.data(), v.data(), out.size());
+    } else {
+        float* f = reinterpret_cast<float*>(out.data());
+        for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+    }
+    return out;
+}
+
+int nbins(const esp_params& p) {
+    const int t1 = p.nf / p.tile;
+    return t1 * t1 * t1;
+}
+
+int tile_edge(const esp_params& p) { return p.tile + p.P - 1 + (p.P & 1); }
+
+int npitems(int64_t N) { return (int)((N + kParticleChunk - 1) / kParticleChunk); }
+
+}  // namespace
+
+TableStore::~TableStore() {
+    for (void* p : allocs_) (void)hipFree(p);
+}
+
+esp_status TableStore::get(const esp_params& p, const DeviceClass** out, std::string& msg) {
+    std::shared_ptr<const ClassTables> t = class_tables(p);
+    const auto key = std::make_pair(t.get(), p.precision);
+    auto it = dev_.find(key);
+    if (it != dev_.end()) {
+        *out = &it->second;
+        return ESP_OK;
+    }
+    DeviceClass d;
+    d.host = t.get();
+    const std::vector<double>* src[4] = {&t->TS, &t->Tphi, &t->poly, &t->tw};
+    void** dst[4] = {&d.TS, &d.Tphi, &d.poly, &d.tw};
+    for (int i = 0; i < 4; ++i) {
+        auto b = to_prec(*src[i], p.precision);
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(b.size(), 16));
+        if (e != hipSuccess) {
+            msg = std::string("hipMalloc: ") + hipGetErrorString(e);
+            return ESP_E_NOMEM;
+        }
+        allocs_.push_back(q);
+        e = hipMemcpy(q, b.data(), b.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            msg = std::string("hipMemcpy: ") + hipGetErrorString(e);
+            return ESP_E_DEVICE;
+        }
+        *dst[i] = q;
+    }
+    keep_.push_back(t);
+    auto res = dev_.emplace(key, d);
+    *out = &res.first->second;
+    return ESP_OK;
+}
+
+int choose_tile(int n, int requested, long long target) {
+    if (requested > 0) {
+        for (int d = std::min(requested, n); d >= 4; --d)
+            if (n % d == 0) return d;
+        return n;
+    }
+    int best = 0, smallest = 0;
+    for (int d = 16; d >= 8; --d) {
+        if (n % d) continue;
+        smallest = d;
+        const long long nb = (long long)(n / d) * (n / d) * (n / d);
+        if (!best && nb >= target) best = d;
+    }
+    if (best) return best;
+    return smallest ? smallest : n;
+}
+
+size_t scratch_bytes(const esp_params& p, int64_t N) {
+    const size_t rb = p.precision == 64 ? 8 : 4;
+    const size_t nb = nbins(p), E = tile_edge(p), n = p.nf;
+    size_t s = 0;
+    s += align256(N * 4 * rb);                   // sorted
+    s += align256(N * 4);                        // perm
+    s += align256(N * 4);                        // rank
+    s += align256(nb * npitems(N) * 4);          // hist
+    s += align256((nb + 1) * 4);                 // bin_start
+    s += align256(n * n * (n + 2) * rb);         // grid
+    s += align256(nb * E * E * E * rb);          // tiles
+    s += align256(kOutDoubles * 8);              // out
+    return s;
+}
+
+SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
+    const size_t rb = p.precision == 64 ? 8 : 4;
+    const size_t nb = nbins(p), E = tile_edge(p), n = p.nf;
+    SysScratch s;
+    size_t o = 0;
+    s.sorted = base + o;
+    o += align256(N * 4 * rb);
+    s.perm = reinterpret_cast<int*>(base + o);
+    o += align256(N * 4);
+    s.rank = reinterpret_cast<int*>(base + o);
+    o += align256(N * 4);
+    s.hist = reinterpret_cast<int*>(base + o);
+    o += align256(nb * npitems(N) * 4);
+    s.bin_start = reinterpret_cast<int*>(base + o);
+    o += align256((nb + 1) * 4);
+    s.grid = base + o;
+    o += align256(n * n * (n + 2) * rb);
+    s.tiles = base + o;
+    o += align256(nb * E * E * E * rb);
+    s.out = reinterpret_cast<double*>(base + o);
+    return s;
+}
+
+LaunchSet::~LaunchSet() {
+    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_cols_, d_bpart_, d_epart_};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+}
+
+template <class T>
+esp_status LaunchSet::put(T** dev, size_t* cap, const std::vector<T>& v, std::string& msg) {
+    if (v.size() > *cap || !*dev) {
+        if (*dev) (void)hipFree(*dev);
+        *dev = nullptr;
+        const size_t c = std::max<size_t>(v.size() + v.size() / 2, 16);
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(dev), c * sizeof(T));
+        if (e != hipSuccess) {
+            msg = std::string("hipMalloc: ") + hipGetErrorString(e);
+            return ESP_E_NOMEM;
+        }
+        *cap = c;
+    }
+    if (!v.empty()) {
+        hipError_t e = hipMemcpyAsync(*dev, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, L_.stream);
+        if (e != hipSuccess) {
+            msg = std::string("hipMemcpyAsync: ") + hipGetErrorString(e);
+            return ESP_E_DEVICE;
+        }
+    }
+    return ESP_OK;
+}
+
+esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hipStream_t stream,
+                            std::string& msg) {
+    const int rb = prec == 64 ? 8 : 4;
+    const int nsys = (int)systems.size();
+    hsys_.assign(nsys, SysDesc{});
+    pitems_.clear();
+    titems_.clear();
+    planes_.clear();
+    cols_.clear();
+    groups_.clear();
+    std::vector<std::vector<int2>> titems_by_P(13);
+    int nmax = 0, KBmax = 1, nb_max = 1;
+    for (int s = 0; s < nsys; ++s) {
+        const SystemSlot& sl = systems[s];
+        const esp_params& r = sl.prm;
+        const ClassTables& ct = *sl.cls->host;
+        SysDesc& d = hsys_[s];
+        d.n = r.nf;
+        d.P = r.P;
+        d.N = (int)sl.N;
+        d.T = r.tile;
+        d.tiles1 = r.nf / r.tile;
+        d.E = tile_edge(r);
+        d.degree = r.degree;
+        d.inv_L = 1.0 / r.L;
+        d.pscale = r.nf / r.L;
+        d.s0 = ct.s0_ref * r.nf / r.L;
+        d.wmax3 = ct.wmax3;
+        d.TS = sl.cls->TS;
+        d.Tphi = sl.cls->Tphi;
+        d.poly = sl.cls->poly;
+        d.tw = sl.cls->tw;
+        d.pos = sl.pos;
+        d.q = sl.q;
+        d.phi = sl.phi;
+        d.F = sl.F;
+        d.sorted = sl.scr.sorted;
+        d.perm = sl.scr.perm;
+        d.rank = sl.scr.rank;
+        d.hist = sl.scr.hist;
+        d.bin_start = sl.scr.bin_start;
+        d.grid = sl.scr.grid;
+        d.tiles = sl.scr.tiles;
+        d.out = sl.scr.out;
+        d.pitem_off = (int)pitems_.size();
+        for (int c = 0; c < d.N; c += kParticleChunk) pitems_.push_back(make_int2(s, c));
+        d.npitem = (int)pitems_.size() - d.pitem_off;
+        const int nb = d.tiles1 * d.tiles1 * d.tiles1;
+        nb_max = std::max(nb_max, nb);
+        for (int t = 0; t < nb; ++t) titems_by_P[r.P].push_back(make_int2(s, t));
+        for (int x = 0; x < r.nf; ++x) planes_.push_back(make_int2(s, x));
+        const int hs = r.nf / 2 + 1;
+        const int nch = (hs + kMaxColumns - 1) / kMaxColumns;
+        const int KB = (hs + nch - 1) / nch;
+        KBmax = std::max(KBmax, KB);
+        d.col_off = (int)cols_.size();
+        for (int ky = 0; ky < r.nf; ++ky)
+            for (int kz0 = 0; kz0 < hs; kz0 += KB) cols_.push_back(make_int4(s, ky, kz0, std::min(KB, hs - kz0)));
+        d.ncol = (int)cols_.size() - d.col_off;
+        nmax = std::max(nmax, r.nf);
+    }
+    for (int P = 4; P <= 12; ++P) {
+        if (titems_by_P[P].empty()) continue;
+        Group g;
+        g.P = P;
+        g.off = (int)titems_.size();
+        g.count = (int)titems_by_P[P].size();
+        int E = 0;
+        for (const int2& it : titems_by_P[P]) E = std::max(E, hsys_[it.x].E);
+        g.lds_spread = E * E * E * 8;  // 64-bit accumulators (fixed point or double)
+        g.lds_gather = E * E * E * rb;
+        if (g.lds_spread > kMaxLds) {
+            msg = "bin tile (T+P)^3 exceeds LDS; reduce tile";
+            return ESP_E_UNSUPPORTED;
+        }
+        titems_.insert(titems_.end(), titems_by_P[P].begin(), titems_by_P[P].end());
+        groups_.push_back(g);
+    }
+    L_.prec = prec;
+    L_.nsys = nsys;
+    L_.stream = stream;
+    L_.n_pitems = (int)pitems_.size();
+    L_.n_planes = (int)planes_.size();
+    L_.n_cols = (int)cols_.size();
+    L_.plane_bd = nmax <= 96 ? 256 : 512;
+    int need = 1;
+    for (const SysDesc& d : hsys_) need = std::max(need, ((d.n / 2 + 1) * (d.n / 2) + L_.plane_bd - 1) / L_.plane_bd);
+    L_.plane_maxit = need;
+    L_.plane_lds = (nmax + nmax * (nmax / 2 + 1)) * 2 * rb + (nmax + 1) * 9 * 4;  // + covering tables
+    int needc = 1;
+    for (const SysDesc& d : hsys_) needc = std::max(needc, (KBmax * d.n / 2 + 255) / 256);
+    L_.col_maxit = needc;
+    L_.col_lds = (nmax + nmax * KBmax) * 2 * rb;
+    L_.hist_lds = nb_max * 4;
+    if (L_.plane_maxit > 12 || L_.plane_lds > kMaxLds) {
+        msg = "grid too large for the LDS-resident plane FFT at this precision";
+        return ESP_E_UNSUPPORTED;
+    }
+    if (L_.hist_lds > kMaxLds) {
+        msg = "too many bins per system; raise tile";
+        return ESP_E_UNSUPPORTED;
+    }
+    esp_status st;
+    if ((st = put(&d_sys_, &cap_sys_, hsys_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_pitems_, &cap_pitems_, pitems_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_titems_, &cap_titems_, titems_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_planes_, &cap_planes_, planes_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_cols_, &cap_cols_, cols_, msg)) != ESP_OK) return st;
+    // partial sums are written before they are read: capacity only
+    auto reserve = [&](double** dev, size_t* cap, size_t need) {
+        if (need <= *cap && *dev) return ESP_OK;
+        if (*dev) (void)hipFree(*dev);
+        *dev = nullptr;
+        const size_t c = std::max<size_t>(need + need / 2, 16);
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(dev), c * sizeof(double));
+        if (e != hipSuccess) {
+            msg = std::string("hipMalloc: ") + hipGetErrorString(e);
+            return ESP_E_NOMEM;
+        }
+        *cap = c;
+        return ESP_OK;
+    };
+    if ((st = reserve(&d_bpart_, &cap_bpart_, 4 * pitems_.size())) != ESP_OK) return st;
+    if ((st = reserve(&d_epart_, &cap_epart_, cols_.size())) != ESP_OK) return st;
+    L_.sys = d_sys_;
+    L_.pitems = d_pitems_;
+    L_.titems = d_titems_;
+    L_.planes = d_planes_;
+    L_.cols = d_cols_;
+    L_.bpart = d_bpart_;
+    L_.epart = d_epart_;
+    return ESP_OK;
+}
+
+void LaunchSet::set_io(int s, const void* pos, const void* q, void* phi, void* F) {
+    SysDesc& d = hsys_[s];
+    d.pos = pos;
+    d.q = q;
+    d.phi = phi;
+    d.F = F;
+}
+
+esp_status LaunchSet::upload_descriptors(std::string& msg) { return put(&d_sys_, &cap_sys_, hsys_, msg); }
+
+}  // namespace esp

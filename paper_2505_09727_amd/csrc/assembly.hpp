@@ -1,0 +1,105 @@
+// Assembly of launch sets: per-system scratch layout, device copies of the
+// table classes, and the descriptor / work-item lists of a set of systems.
+// Shared by static plans (one set built once) and the server (rebuilt when
+// the active set changes).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "esp.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace esp {
+
+// Device copy of one table class (owned by a TableStore).
+struct DeviceClass {
+    const ClassTables* host = nullptr;
+    void* TS = nullptr;
+    void* Tphi = nullptr;
+    void* poly = nullptr;
+    void* tw = nullptr;
+};
+
+// Uploads each table class once per precision and keeps it until destroyed.
+class TableStore {
+  public:
+    ~TableStore();
+    // Device tables for resolved params (uploads on first use).
+    esp_status get(const esp_params& p, const DeviceClass** out, std::string& msg);
+
+  private:
+    std::map<std::pair<const ClassTables*, int>, DeviceClass> dev_;
+    std::vector<std::shared_ptr<const ClassTables>> keep_;
+    std::vector<void*> allocs_;
+};
+
+// Bin edge: a divisor of n in [8, 16] giving at least `target` bins when
+// possible (requested > 0 rounds a caller's choice down to a divisor).
+int choose_tile(int n, int requested, long long target);
+
+// Scratch of one system, carved from one block of device memory.
+struct SysScratch {
+    void* sorted;
+    int* perm;
+    int* rank;
+    int* hist;
+    int* bin_start;
+    void* grid;
+    void* tiles;
+    double* out;
+};
+size_t scratch_bytes(const esp_params& p, int64_t N);
+SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N);
+
+// One system placed in a launch set.
+struct SystemSlot {
+    esp_params prm;
+    int64_t N = 0;
+    const DeviceClass* cls = nullptr;
+    SysScratch scr{};
+    const void* pos = nullptr;
+    const void* q = nullptr;
+    void* phi = nullptr;
+    void* F = nullptr;
+};
+
+// Host and device copies of a launch set.
+class LaunchSet {
+  public:
+    ~LaunchSet();
+    // Build descriptors and work lists for `systems` (same precision) and
+    // upload them on `stream`. Device arrays grow as needed.
+    esp_status build(const std::vector<SystemSlot>& systems, int prec, hipStream_t stream, std::string& msg);
+    // Re-point the particle arrays of system s (no upload).
+    void set_io(int s, const void* pos, const void* q, void* phi, void* F);
+    // Upload the descriptors after set_io.
+    esp_status upload_descriptors(std::string& msg);
+    const Launch& launch() const { return L_; }
+    const std::vector<Group>& groups() const { return groups_; }
+    int nsys() const { return (int)hsys_.size(); }
+    const SysDesc& desc(int s) const { return hsys_[s]; }
+
+  private:
+    template <class T>
+    esp_status put(T** dev, size_t* cap, const std::vector<T>& v, std::string& msg);
+    Launch L_{};
+    std::vector<Group> groups_;
+    std::vector<SysDesc> hsys_;
+    std::vector<int2> pitems_, titems_, planes_;
+    std::vector<int4> cols_;
+    SysDesc* d_sys_ = nullptr;
+    int2 *d_pitems_ = nullptr, *d_titems_ = nullptr, *d_planes_ = nullptr;
+    int4* d_cols_ = nullptr;
+    double *d_bpart_ = nullptr, *d_epart_ = nullptr;
+    size_t cap_sys_ = 0, cap_pitems_ = 0, cap_titems_ = 0, cap_planes_ = 0, cap_cols_ = 0, cap_bpart_ = 0,
+           cap_epart_ = 0;
+};
+
+constexpr int kMaxLds = 160 * 1024;
+
+}  // namespace esp

@@ -6,35 +6,48 @@
 
 namespace esp {
 
-// One system of a (possibly batched) plan. Every kernel reads the descriptor of
-// its work item's system, so systems of different sizes share one launch.
+// One system of a launch. Every kernel reads the descriptor of its work
+// item's system, so systems of different sizes, whose buffers may live
+// anywhere in device memory, share one launch per pipeline phase.
 struct SysDesc {
     int n;            // grid points per side
     int P;            // window width
     int N;            // particles
-    int part_off;     // first particle in the concatenated arrays
-    int tile_off;     // first bin in the bin arrays
-    int tiles1;       // bins per side = ceil(n / T)
-    int T;            // bin edge in grid points
-    int degree;       // window polynomial degree
-    long long grid_off;  // first real of the grid, n * n * (n + 2) reals
-    int ts_off;       // radial influence table (3 (n/2)^2 + 1 entries)
-    int tphi_off;     // per-axis influence table (n/2 + 1 entries)
-    int poly_off;     // window polynomials, P * (degree + 1)
-    int tw_off;       // twiddles exp(2 pi i t/n), n complex
-    int col_off;      // first x-column work item of this system
-    int ncol;         // number of x-column work items
-    int pitem_off;    // first particle work item
-    int npitem;       // number of particle work items
+    int T;            // bin edge in grid points (divides n)
+    int tiles1;       // bins per side, n / T
     int E;            // edge of a bin's window tile, T + P - 1 + (P odd)
-    int hist_off;     // bin-major histogram / offset matrix, nbins x npitem
-    long long tb_off; // first real of this system's bin tiles, nbins x E^3
+    int degree;       // window polynomial degree
+    int npitem;       // particle-chunk work items of this system ...
+    int pitem_off;    // ... starting at this index of the launch's list
+    int ncol;         // x-column work items ...
+    int col_off;      // ... starting here
+    int pad0;
     double inv_L;     // 1/L
-    double s0;        // self constant S(0)
+    double s0;        // self constant S(0) of this box
+    double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
     double wmax3;     // cube of the window's peak value (fixed-point range)
+    // tables shared by the systems of one parameter class
+    const void* TS;   // radial influence table, 3 (n/2)^2 + 1 entries
+    const void* Tphi; // per-axis influence table, n/2 + 1 entries
+    const void* poly; // window polynomials, P * (degree + 1)
+    const void* tw;   // twiddles exp(2 pi i t/n), n complex
+    // particles in the caller's order (this system's slice) and outputs
+    const void* pos;  // N x 3
+    const void* q;    // N
+    void* phi;        // N or null
+    void* F;          // N x 3 or null
+    // scratch owned by the plan or server
+    void* sorted;     // N x (u_x, u_y, u_z, q) in bin order
+    int* perm;        // N: caller index of each sorted particle
+    int* rank;        // N: rank within (chunk, bin)
+    int* hist;        // nbins x npitem counts, then offsets
+    int* bin_start;   // nbins + 1
+    void* grid;       // n x n x (n + 2) reals (half spectrum in place)
+    void* tiles;      // nbins x E^3 reals
+    double* out;      // 8 doubles: E, sum q, sum |q|, sum q^2, fixed-point scale
 };
 
-// Work items: .x = system, .y (.z) = item coordinates inside the system.
+// Work items: .x = system index in the launch, .y (.z, .w) = position inside it.
 //   particle chunk: (sys, first particle of a 256-chunk)
 //   bin:            (sys, bin index within the system)
 //   plane:          (sys, x)
@@ -42,5 +55,6 @@ struct SysDesc {
 
 constexpr int kParticleChunk = 256;
 constexpr int kMaxColumns = 16;
+constexpr int kOutDoubles = 8;
 
 }  // namespace esp

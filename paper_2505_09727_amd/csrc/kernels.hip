@@ -200,37 +200,36 @@ __device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
 // coordinates, bin id, and the rank of the particle among the chunk's
 // particles of the same bin (LDS atomics); the chunk's bin counts go to column
 // `item` of the system's bin-major count matrix (plain stores). Also the chunk
-// sums of q, |q|, q^2 (neutrality check, self energy).
+// sums of q, |q|, q^2 and max |q| (neutrality check, self energy, fixed-point
+// range of the spread).
 template <typename R>
 __global__ void __launch_bounds__(256) k_hist(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                              const R* __restrict__ pos, const R* __restrict__ q,
-                                              int* __restrict__ hist, int* __restrict__ rank,
                                               double* __restrict__ bpart) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int* cnt = reinterpret_cast<int*>(smem_raw);
     __shared__ double red[16];
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
-    const int t1 = S.n / S.T, nb = t1 * t1 * t1;
+    const SysDesc& S = sys[wi.x];
+    const int n = S.n, t1 = S.tiles1, nb = t1 * t1 * t1;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[b] = 0;
     __syncthreads();
     const int il = wi.y + threadIdx.x;
     double sq = 0.0, sa = 0.0, s2 = 0.0;
     if (il < S.N) {
-        const long long i = (long long)S.part_off + il;
+        const R* pos = reinterpret_cast<const R*>(S.pos);
         const R inv_L = R(S.inv_L);
-        const R ux = grid_coord(pos[3 * i + 0], inv_L, S.n);
-        const R uy = grid_coord(pos[3 * i + 1], inv_L, S.n);
-        const R uz = grid_coord(pos[3 * i + 2], inv_L, S.n);
-        rank[i] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
-        const double qq = (double)q[i];
+        const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
+        const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
+        const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
+        S.rank[il] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
+        const double qq = (double)reinterpret_cast<const R*>(S.q)[il];
         sq = qq;
         sa = fabs(qq);
         s2 = qq * qq;
     }
     __syncthreads();
     const int it = blockIdx.x - S.pitem_off;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[S.hist_off + b * S.npitem + it] = cnt[b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) S.hist[b * S.npitem + it] = cnt[b];
     const double qm = block_max(sa, red);
     const double t0 = block_sum(sq, red);
     const double t1s = block_sum(sa, red);
@@ -245,33 +244,32 @@ __global__ void __launch_bounds__(256) k_hist(const SysDesc* __restrict__ sys, c
 
 // Exclusive scan of a system's bin-major count matrix (one block per system):
 // the entry (bin, item) becomes the first sorted slot of that chunk's
-// particles in that bin; bin_start[bin] is the first slot of the bin.
-__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, int nsys, int* __restrict__ hist,
-                                               int* __restrict__ bin_start, const double* __restrict__ bpart,
-                                               float* __restrict__ fx_scale) {
+// particles in that bin; bin_start[bin] is the first slot of the bin. Also
+// the fixed-point scale of the FP32 spread: 2^F with every single
+// contribution |q w_x w_y w_z| 2^F <= 2^30, so it is exact through int32.
+__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, const double* __restrict__ bpart) {
     __shared__ int warp_tot[16];
     __shared__ int carry_s;
     __shared__ double red[16];
-    const SysDesc S = sys[blockIdx.x];
+    const SysDesc& S = sys[blockIdx.x];
     {
-        // fixed-point scale of the FP32 spread: 2^F with every single
-        // contribution |q w_x w_y w_z| 2^F <= 2^30 (exact through int32)
         double qm = 0.0;
         for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) qm = fmax(qm, bpart[4 * (S.pitem_off + i) + 3]);
         qm = block_max(qm, red);
         if (threadIdx.x == 0) {
             const double bound = qm * S.wmax3;
             const int F = bound > 0.0 ? 30 - (int)ceil(log2(bound)) : 30;
-            fx_scale[blockIdx.x] = ldexpf(1.0f, max(-100, min(100, F)));
+            S.out[4] = ldexp(1.0, max(-100, min(100, F)));
         }
     }
-    const int t1 = S.n / S.T, nb = t1 * t1 * t1;
+    const int t1 = S.tiles1, nb = t1 * t1 * t1;
     const int total = nb * S.npitem;
-    if (threadIdx.x == 0) carry_s = S.part_off;
+    int* hist = S.hist;
+    if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     for (int base = 0; base < total; base += blockDim.x) {
         const int l = base + threadIdx.x;
-        const int v = l < total ? hist[S.hist_off + l] : 0;
+        const int v = l < total ? hist[l] : 0;
         int x = v;
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         for (int off = 1; off < 64; off <<= 1) {
@@ -285,42 +283,39 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
         const int carry = carry_s;
         if (l < total) {
             const int off = carry + before + x - v;
-            hist[S.hist_off + l] = off;
-            if (l % S.npitem == 0) bin_start[S.tile_off + l / S.npitem] = off;
+            hist[l] = off;
+            if (l % S.npitem == 0) S.bin_start[l / S.npitem] = off;
         }
         __syncthreads();
         if (threadIdx.x == blockDim.x - 1) carry_s = carry + before + x;
         __syncthreads();
     }
-    if (blockIdx.x == nsys - 1 && threadIdx.x == 0) bin_start[S.tile_off + nb] = S.part_off + S.N;
+    if (threadIdx.x == 0) S.bin_start[nb] = S.N;
 }
 
 // Scatter particles into bin order as (u_x, u_y, u_z, q) and record the
 // permutation back to the caller's order.
 template <typename R>
-__global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                 const R* __restrict__ pos, const R* __restrict__ q,
-                                                 const int* __restrict__ rank, const int* __restrict__ offs,
-                                                 typename Vec4<R>::type* __restrict__ sorted,
-                                                 int* __restrict__ perm) {
+__global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
+    const SysDesc& S = sys[wi.x];
     const int il = wi.y + threadIdx.x;
     if (il >= S.N) return;
-    const long long i = (long long)S.part_off + il;
+    const R* pos = reinterpret_cast<const R*>(S.pos);
     const R inv_L = R(S.inv_L);
-    const R ux = grid_coord(pos[3 * i + 0], inv_L, S.n);
-    const R uy = grid_coord(pos[3 * i + 1], inv_L, S.n);
-    const R uz = grid_coord(pos[3 * i + 2], inv_L, S.n);
+    const int n = S.n;
+    const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
+    const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
+    const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
     const int b = bin_of(ux, uy, uz, S);
-    const int dst = offs[S.hist_off + b * S.npitem + (blockIdx.x - S.pitem_off)] + rank[i];
+    const int dst = S.hist[b * S.npitem + (blockIdx.x - S.pitem_off)] + S.rank[il];
     typename Vec4<R>::type v;
     v.x = ux;
     v.y = uy;
     v.z = uz;
-    v.w = q[i];
-    sorted[dst] = v;
-    perm[dst] = (int)i;
+    v.w = reinterpret_cast<const R*>(S.q)[il];
+    reinterpret_cast<typename Vec4<R>::type*>(S.sorted)[dst] = v;
+    S.perm[dst] = il;
 }
 
 // ---------------------------------------------------------------------------
@@ -369,17 +364,17 @@ __device__ __forceinline__ int wrapi(int g, int n) {
 
 // Spread (eq. spread): one block per bin of T^3 grid cells. The block
 // accumulates its particles' P^3 windows into an LDS tile of E^3 points
-// (E = T + P - 1 + (P odd)) with LDS atomics and stores the whole tile, halo
-// included, to the bin's slot of the tile buffer with plain stores. The halos
-// of neighbouring bins are summed when the forward FFT loads its planes
-// (fold_point), so no global atomics are needed.
+// (E = T + P - 1 + (P odd)) and stores the whole tile, halo included, to the
+// bin's slot of the tile buffer with plain stores. The halos of neighbouring
+// bins are summed when the forward FFT loads its planes (fold_point), so no
+// global atomics are needed.
 //
-// LDS accumulator: FP32 plans accumulate in 64-bit fixed point (ds_add_u64;
+// LDS accumulator: FP32 systems accumulate in 64-bit fixed point (ds_add_u64;
 // LDS float atomics are ~20x slower than 64-bit integer ones on gfx950, and
 // integer sums are order-independent, so the spread is deterministic). Each
 // contribution q w_x w_y w_z is scaled by the system's 2^F and rounded to an
-// int32 (|value| <= 2^30 by the choice of F), the tile is converted back to
-// float when stored. FP64 plans accumulate with ds_add_f64.
+// int32; the tile is converted back to float when stored. FP64 systems
+// accumulate with ds_add_f64.
 template <typename R> struct SpreadAcc {
     using type = R;
 };
@@ -388,37 +383,36 @@ template <> struct SpreadAcc<float> {
 };
 
 template <typename R, int P>
-__global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                const typename Vec4<R>::type* __restrict__ sorted,
-                                                const int* __restrict__ bin_start, const R* __restrict__ poly_all,
-                                                const float* __restrict__ fx_scale, R* __restrict__ tiles) {
+__global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     using A = typename SpreadAcc<R>::type;
-    constexpr bool kFixed = sizeof(A) != sizeof(R) || !std::is_floating_point<A>::value;
+    constexpr bool kFixed = !std::is_floating_point<A>::value;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
+    const SysDesc& S = sys[wi.x];
     const int t = wi.y, T = S.T, t1 = S.tiles1;
     const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
     const int lo = -((P - 1) / 2);
     const int E = S.E, E3 = E * E * E;
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
-    const int beg = bin_start[S.tile_off + t], end = bin_start[S.tile_off + t + 1];
-    R* out = tiles + S.tb_off + (long long)t * E3;
+    const int beg = S.bin_start[t], end = S.bin_start[t + 1];
+    R* out = reinterpret_cast<R*>(S.tiles) + (long long)t * E3;
     if (beg == end) {  // uniform over the block
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R(0);
         return;
     }
     for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
     __syncthreads();
-    const R* coef = poly_all + S.poly_off;
-    const R scale = kFixed ? R(fx_scale[wi.x]) : R(1);
+    const R* coef = reinterpret_cast<const R*>(S.poly);
+    const int deg = S.degree;
+    const R scale = kFixed ? R(S.out[4]) : R(1);
+    const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = sorted[k];
         R wx[P], wy[P], wz[P];
-        const int bx = window<R, P>(v.x, coef, S.degree, wx) - ox;
-        const int by = window<R, P>(v.y, coef, S.degree, wy) - oy;
-        const int bz = window<R, P>(v.z, coef, S.degree, wz) - oz;
+        const int bx = window<R, P>(v.x, coef, deg, wx) - ox;
+        const int by = window<R, P>(v.y, coef, deg, wy) - oy;
+        const int bz = window<R, P>(v.z, coef, deg, wz) - oz;
         const R qs = v.w * scale;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
@@ -465,8 +459,7 @@ __device__ __forceinline__ int covering(int g, int lo, int T, int t1, int n, int
     return c;
 }
 
-// Covering lists of all n indices of an axis, built once per block in LDS:
-// cov[g] = count, then up to 4 (bin, offset) pairs.
+// Covering lists of all n indices of an axis, built once per block in LDS.
 struct CoverTab {
     int cnt;
     int bin[4];
@@ -490,7 +483,7 @@ __device__ __forceinline__ R fold_point(const R* __restrict__ tiles, const SysDe
     R acc = R(0);
     for (int a = 0; a < cx.cnt; ++a)
         for (int b = 0; b < cy.cnt; ++b) {
-            const long long base = S.tb_off + ((long long)cx.bin[a] * t1 + cy.bin[b]) * t1 * E3 +
+            const long long base = ((long long)cx.bin[a] * t1 + cy.bin[b]) * t1 * E3 +
                                    ((long long)cx.off[a] * E + cy.off[b]) * E;
             for (int c = 0; c < cz.cnt; ++c) acc += tiles[base + (long long)cz.bin[c] * E3 + cz.off[c]];
         }
@@ -499,16 +492,16 @@ __device__ __forceinline__ R fold_point(const R* __restrict__ tiles, const SysDe
 
 // Diagnostics: fold the bin tiles into the padded real grid (b_l of eq. spread).
 template <typename R>
-__global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                              const R* __restrict__ tiles, R* __restrict__ grid) {
+__global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     __shared__ CoverTab tab[145];
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
-    const int n = S.n, lo = -((S.P - 1) / 2);
-    build_cover(tab, S, lo);
+    const SysDesc& S = sys[wi.x];
+    const int n = S.n;
+    build_cover(tab, S, -((S.P - 1) / 2));
     __syncthreads();
     const CoverTab cx = tab[wi.y];
-    R* plane = grid + S.grid_off + (long long)wi.y * n * (n + 2);
+    const R* tiles = reinterpret_cast<const R*>(S.tiles);
+    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * n * (n + 2);
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int y = idx / n, z = idx - y * n;
         plane[y * (n + 2) + z] = fold_point(tiles, S, cx, tab[y], tab[z]);
@@ -518,23 +511,19 @@ __global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, c
 // Gather (eq. interp) with analytic window derivatives (AD forces):
 // phi_i = u~_i - q_i S(0), F_i = -q_i (n/L) grad_u u~_i, written in caller order.
 template <typename R, int P>
-__global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                const typename Vec4<R>::type* __restrict__ sorted,
-                                                const int* __restrict__ perm, const int* __restrict__ bin_start,
-                                                const R* __restrict__ poly_all, const R* __restrict__ grid,
-                                                R* __restrict__ phi, R* __restrict__ F) {
+__global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* lds = reinterpret_cast<R*>(smem_raw);
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
+    const SysDesc& S = sys[wi.x];
     const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
     const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
     const int lo = -((P - 1) / 2);
     const int E = S.E, E3 = E * E * E;
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
-    const int beg = bin_start[S.tile_off + t], end = bin_start[S.tile_off + t + 1];
+    const int beg = S.bin_start[t], end = S.bin_start[t + 1];
     if (beg == end) return;
-    const R* g = grid + S.grid_off;
+    const R* g = reinterpret_cast<const R*>(S.grid);
     const int rl = n + 2;
     for (int i = threadIdx.x; i < E3; i += blockDim.x) {
         const int a = i / (E * E), rem = i - a * E * E, b = rem / E, c = rem - b * E;
@@ -542,15 +531,19 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
         lds[i] = g[((long long)gx * n + gy) * rl + gz];
     }
     __syncthreads();
-    const R* coef = poly_all + S.poly_off;
+    const R* coef = reinterpret_cast<const R*>(S.poly);
+    const int deg = S.degree;
     const R sc = R(S.n) * R(S.inv_L);
     const R s0 = R(S.s0);
+    const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
+    R* phi = reinterpret_cast<R*>(S.phi);
+    R* F = reinterpret_cast<R*>(S.F);
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = sorted[k];
         R wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
-        const int bx = window_d<R, P>(v.x, coef, S.degree, wx, dx) - ox;
-        const int by = window_d<R, P>(v.y, coef, S.degree, wy, dy) - oy;
-        const int bz = window_d<R, P>(v.z, coef, S.degree, wz, dz) - oz;
+        const int bx = window_d<R, P>(v.x, coef, deg, wx, dx) - ox;
+        const int by = window_d<R, P>(v.y, coef, deg, wy, dy) - oy;
+        const int bz = window_d<R, P>(v.z, coef, deg, wz, dz) - oz;
         R u = 0, gxs = 0, gys = 0, gzs = 0;
         // outer loop kept rolled: a is uniform across the wavefront, and
         // unrolling all P^3 loads would exhaust the register file
@@ -576,7 +569,7 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
             gys += sdy * wx[a];
             gzs += sdz * wx[a];
         }
-        const int o = perm[k];
+        const int o = S.perm[k];
         if (phi) phi[o] = u - v.w * s0;
         if (F) {
             const R f = -v.w * sc;
@@ -590,25 +583,26 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
 // ---------------------------------------------------------------------------
 // Forward FFT along z (real-to-complex) and y for one x-plane. Pairs of real
 // rows (2r, 2r+1) are transformed as one complex row and split afterwards.
-// With tiles != nullptr the plane is assembled from the spread's bin tiles
+// With from_tiles the plane is assembled from the spread's bin tiles
 // (fold_point); otherwise it is read from the real grid.
 template <typename R, int MAXIT>
 __global__ void __launch_bounds__(512) k_fft_fwd_zy(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                    R* __restrict__ grid, const cplx<R>* __restrict__ tw_all,
-                                                    const R* __restrict__ tiles) {
+                                                    int from_tiles) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
+    const SysDesc& S = sys[wi.x];
     const int n = S.n, hs = n / 2 + 1, rl = n + 2, half = n / 2;
     cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
     cplx<R>* buf = tw + n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
-    R* plane = grid + S.grid_off + (long long)wi.y * n * rl;
-    if (tiles) {
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_g[i];
+    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * n * rl;
+    if (from_tiles) {
         CoverTab* tab = reinterpret_cast<CoverTab*>(buf + n * hs);
         build_cover(tab, S, -((S.P - 1) / 2));
         __syncthreads();
         const CoverTab cx = tab[wi.y];
+        const R* tiles = reinterpret_cast<const R*>(S.tiles);
         R* bufr = reinterpret_cast<R*>(buf);
         for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
             const int y = idx / n, z = idx - y * n;
@@ -656,16 +650,16 @@ __global__ void __launch_bounds__(512) k_fft_fwd_zy(const SysDesc* __restrict__ 
 
 // Inverse FFT along y, then complex-to-real along z, for one x-plane.
 template <typename R, int MAXIT>
-__global__ void __launch_bounds__(512) k_fft_inv_yz(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                    R* __restrict__ grid, const cplx<R>* __restrict__ tw_all) {
+__global__ void __launch_bounds__(512) k_fft_inv_yz(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
+    const SysDesc& S = sys[wi.x];
     const int n = S.n, hs = n / 2 + 1, rl = n + 2, half = n / 2;
     cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
     cplx<R>* buf = tw + n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
-    R* plane = grid + S.grid_off + (long long)wi.y * n * rl;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_g[i];
+    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * n * rl;
     const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(plane);
     for (int idx = threadIdx.x; idx < n * hs; idx += blockDim.x) buf[idx] = gp[idx];
     __syncthreads();
@@ -714,19 +708,18 @@ __global__ void __launch_bounds__(512) k_fft_inv_yz(const SysDesc* __restrict__ 
 // after the scaling (diagnostics).
 template <typename R, int MAXIT>
 __global__ void __launch_bounds__(256) k_fft_x(const SysDesc* __restrict__ sys, const int4* __restrict__ items,
-                                               R* __restrict__ grid, const cplx<R>* __restrict__ tw_all,
-                                               const R* __restrict__ TS_all, const R* __restrict__ Tphi_all,
                                                double* __restrict__ epart, int mode) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
     const int4 wi = items[blockIdx.x];
-    const SysDesc S = sys[wi.x];
+    const SysDesc& S = sys[wi.x];
     const int n = S.n, hs = n / 2 + 1, half = n / 2;
     const int ky = wi.y, kz0 = wi.z, KB = wi.w;
     cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
     cplx<R>* buf = tw + n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_all[S.tw_off + i];
-    cplx<R>* gp = reinterpret_cast<cplx<R>*>(grid + S.grid_off);
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_g[i];
+    cplx<R>* gp = reinterpret_cast<cplx<R>*>(S.grid);
     const int cnt = n * KB;
     for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
         const int x = idx / KB, l = idx - x * KB;
@@ -736,10 +729,10 @@ __global__ void __launch_bounds__(256) k_fft_x(const SysDesc* __restrict__ sys, 
     fft_lines<R, MAXIT>(buf, n, KB, 1, KB, tw, +1, true);
     double e = 0.0;
     if (mode != 1) {
-        const R* TS = TS_all + S.ts_off;
-        const R* Tp = Tphi_all + S.tphi_off;
+        const R* TS = reinterpret_cast<const R*>(S.TS);
+        const R* Tp = reinterpret_cast<const R*>(S.Tphi);
         const int my = ky <= half ? ky : n - ky;
-        const R py = Tp[my];
+        const R py = Tp[my] * R(S.pscale);
         for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
             const int x = idx / KB, l = idx - x * KB, kz = kz0 + l;
             const int mx = x <= half ? x : n - x;
@@ -762,10 +755,9 @@ __global__ void __launch_bounds__(256) k_fft_x(const SysDesc* __restrict__ sys, 
 
 // Energy per system: E = E_k - S(0)/2 sum q^2, plus the charge sums.
 __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
-                                                  const double* __restrict__ bpart, double* __restrict__ eout,
-                                                  double* __restrict__ E_dev) {
+                                                  const double* __restrict__ bpart, double* __restrict__ E_dev) {
     __shared__ double red[16];
-    const SysDesc S = sys[blockIdx.x];
+    const SysDesc& S = sys[blockIdx.x];
     double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < S.ncol; i += blockDim.x) ek += epart[S.col_off + i];
     for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) {
@@ -779,10 +771,10 @@ __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sy
     s2 = block_sum(s2, red);
     if (threadIdx.x == 0) {
         const double E = ek - 0.5 * S.s0 * s2;
-        eout[4 * blockIdx.x + 0] = E;
-        eout[4 * blockIdx.x + 1] = sq;
-        eout[4 * blockIdx.x + 2] = sa;
-        eout[4 * blockIdx.x + 3] = s2;
+        S.out[0] = E;
+        S.out[1] = sq;
+        S.out[2] = sa;
+        S.out[3] = s2;
         if (E_dev) E_dev[blockIdx.x] = E;
     }
 }
@@ -799,22 +791,18 @@ static hipError_t allow_lds(K kernel, int bytes) {
 }
 
 template <typename R>
-static hipError_t prepare_t(const Launch& L, int phase, const void* pos, const void* q) {
+static hipError_t prepare_t(const Launch& L, int phase) {
     hipError_t e;
     switch (phase) {
         case 0:
             if ((e = allow_lds(k_hist<R>, L.hist_lds)) != hipSuccess) return e;
-            k_hist<R><<<L.n_pitems, 256, L.hist_lds, L.stream>>>(L.sys, L.pitems, reinterpret_cast<const R*>(pos),
-                                                                 reinterpret_cast<const R*>(q), L.hist, L.rank,
-                                                                 L.bpart);
+            k_hist<R><<<L.n_pitems, 256, L.hist_lds, L.stream>>>(L.sys, L.pitems, L.bpart);
             break;
         case 1:
-            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.nsys, L.hist, L.bin_start, L.bpart, L.fx_scale);
+            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.bpart);
             break;
         case 2:
-            k_scatter<R><<<L.n_pitems, 256, 0, L.stream>>>(
-                L.sys, L.pitems, reinterpret_cast<const R*>(pos), reinterpret_cast<const R*>(q), L.rank, L.hist,
-                reinterpret_cast<typename Vec4<R>::type*>(L.sorted), L.perm);
+            k_scatter<R><<<L.n_pitems, 256, 0, L.stream>>>(L.sys, L.pitems);
             break;
         default:
             return hipErrorInvalidValue;
@@ -822,38 +810,23 @@ static hipError_t prepare_t(const Launch& L, int phase, const void* pos, const v
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Launch& L, int phase, const void* pos, const void* q) {
-    return L.prec == 64 ? prepare_t<double>(L, phase, pos, q) : prepare_t<float>(L, phase, pos, q);
+hipError_t launch_prepare(const Launch& L, int phase) {
+    return L.prec == 64 ? prepare_t<double>(L, phase) : prepare_t<float>(L, phase);
 }
 
 template <typename R, int P>
 static hipError_t spread_p(const Launch& L, const Group& G) {
-    hipError_t e = allow_lds(k_spread<R, P>, G.lds);
+    hipError_t e = allow_lds(k_spread<R, P>, G.lds_spread);
     if (e != hipSuccess) return e;
-    k_spread<R, P><<<G.count, 256, G.lds, L.stream>>>(
-        L.sys, L.titems + G.off, reinterpret_cast<const typename Vec4<R>::type*>(L.sorted), L.bin_start,
-        reinterpret_cast<const R*>(L.poly), L.fx_scale, reinterpret_cast<R*>(L.tiles));
-    return hipGetLastError();
-}
-
-hipError_t launch_fold(const Launch& L) {
-    if (L.prec == 64)
-        k_fold<double><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes, reinterpret_cast<const double*>(L.tiles),
-                                                         reinterpret_cast<double*>(L.grid));
-    else
-        k_fold<float><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes, reinterpret_cast<const float*>(L.tiles),
-                                                        reinterpret_cast<float*>(L.grid));
+    k_spread<R, P><<<G.count, 256, G.lds_spread, L.stream>>>(L.sys, L.titems + G.off);
     return hipGetLastError();
 }
 
 template <typename R, int P>
-static hipError_t gather_p(const Launch& L, const Group& G, void* phi, void* F) {
-    hipError_t e = allow_lds(k_gather<R, P>, G.lds);
+static hipError_t gather_p(const Launch& L, const Group& G) {
+    hipError_t e = allow_lds(k_gather<R, P>, G.lds_gather);
     if (e != hipSuccess) return e;
-    k_gather<R, P><<<G.count, 256, G.lds, L.stream>>>(
-        L.sys, L.titems + G.off, reinterpret_cast<const typename Vec4<R>::type*>(L.sorted), L.perm,
-        L.bin_start, reinterpret_cast<const R*>(L.poly), reinterpret_cast<const R*>(L.grid),
-        reinterpret_cast<R*>(phi), reinterpret_cast<R*>(F));
+    k_gather<R, P><<<G.count, 256, G.lds_gather, L.stream>>>(L.sys, L.titems + G.off);
     return hipGetLastError();
 }
 
@@ -876,28 +849,31 @@ hipError_t launch_spread(const Launch& L, const Group& G) {
     ESP_P_SWITCH(spread_p, float, L, G)
 }
 
-hipError_t launch_gather(const Launch& L, const Group& G, void* phi, void* F) {
-    if (L.prec == 64) { ESP_P_SWITCH(gather_p, double, L, G, phi, F) }
-    ESP_P_SWITCH(gather_p, float, L, G, phi, F)
+hipError_t launch_gather(const Launch& L, const Group& G) {
+    if (L.prec == 64) { ESP_P_SWITCH(gather_p, double, L, G) }
+    ESP_P_SWITCH(gather_p, float, L, G)
+}
+
+hipError_t launch_fold(const Launch& L) {
+    if (L.prec == 64)
+        k_fold<double><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes);
+    else
+        k_fold<float><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes);
+    return hipGetLastError();
 }
 
 template <typename R, int MAXIT>
 static hipError_t fft_t(const Launch& L, int which, int mode) {
-    const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(L.tw);
-    R* grid = reinterpret_cast<R*>(L.grid);
     hipError_t e;
     if (which == 0) {
         if ((e = allow_lds(k_fft_fwd_zy<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
-        k_fft_fwd_zy<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(
-            L.sys, L.planes, grid, tw, mode == 3 ? nullptr : reinterpret_cast<const R*>(L.tiles));
+        k_fft_fwd_zy<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes, mode == 3 ? 0 : 1);
     } else if (which == 1) {
         if ((e = allow_lds(k_fft_x<R, MAXIT>, L.col_lds)) != hipSuccess) return e;
-        k_fft_x<R, MAXIT><<<L.n_cols, 256, L.col_lds, L.stream>>>(L.sys, L.cols, grid, tw,
-                                                                  reinterpret_cast<const R*>(L.TS),
-                                                                  reinterpret_cast<const R*>(L.Tphi), L.epart, mode);
+        k_fft_x<R, MAXIT><<<L.n_cols, 256, L.col_lds, L.stream>>>(L.sys, L.cols, L.epart, mode);
     } else {
         if ((e = allow_lds(k_fft_inv_yz<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
-        k_fft_inv_yz<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes, grid, tw);
+        k_fft_inv_yz<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes);
     }
     return hipGetLastError();
 }
@@ -917,7 +893,7 @@ hipError_t launch_fft(const Launch& L, int which, int mode) {
 }
 
 hipError_t launch_finalize(const Launch& L, double* E_dev) {
-    k_finalize<<<L.nsys, 256, 0, L.stream>>>(L.sys, L.epart, L.bpart, L.eout, E_dev);
+    k_finalize<<<L.nsys, 256, 0, L.stream>>>(L.sys, L.epart, L.bpart, E_dev);
     return hipGetLastError();
 }
 

@@ -9,12 +9,15 @@ namespace esp {
 // Systems sharing one window width P: one spread and one gather launch.
 struct Group {
     int P;
-    int off;    // first bin work item of the group
-    int count;  // bin work items
-    int lds;    // LDS bytes per block, (T+P)^3 reals
+    int off;         // first bin work item of the group
+    int count;       // bin work items
+    int lds_spread;  // LDS bytes per spread block, E^3 64-bit accumulators
+    int lds_gather;  // LDS bytes per gather block, E^3 reals
 };
 
-// Everything a pipeline launch needs (device pointers owned by the plan).
+// One launch set: the device descriptor table of the active systems, the
+// work-item lists of every phase and the launch shapes. Buffers the systems
+// use are reached through their descriptors.
 struct Launch {
     int prec;             // 32 or 64
     int nsys;
@@ -29,28 +32,14 @@ struct Launch {
     int n_cols;
     int plane_bd, plane_maxit, plane_lds;
     int col_maxit, col_lds;
-    void* grid;
-    long long grid_reals;
-    void* sorted;
-    int* perm;
-    int* rank;
-    int* hist;            // bin-major count / offset matrices
     int hist_lds;         // LDS bytes of the per-chunk histogram
-    int* bin_start;
-    void* tiles;          // spread tiles, nbins x E^3 reals per system
     double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
-    float* fx_scale;      // per system: fixed-point scale 2^F of the FP32 spread
-    double* epart;
-    double* eout;
-    const void* TS;
-    const void* Tphi;
-    const void* poly;
-    const void* tw;
+    double* epart;        // per x-column item: k-space energy partial
 };
 
 // Preparation phases: 0 per-chunk bin histograms, 1 scan, 2 scatter into
 // bin order.
-hipError_t launch_prepare(const Launch& L, int phase, const void* pos, const void* q);
+hipError_t launch_prepare(const Launch& L, int phase);
 hipError_t launch_spread(const Launch& L, const Group& G);
 // Diagnostics: fold the spread tiles into the real grid.
 hipError_t launch_fold(const Launch& L);
@@ -58,7 +47,7 @@ hipError_t launch_fold(const Launch& L);
 // spread tiles), 1 x-columns with scaling (mode 0 full, 1 forward only,
 // 2 forward + scaling), 2 inverse y/z planes.
 hipError_t launch_fft(const Launch& L, int which, int mode);
-hipError_t launch_gather(const Launch& L, const Group& G, void* phi, void* F);
+hipError_t launch_gather(const Launch& L, const Group& G);
 hipError_t launch_finalize(const Launch& L, double* E_dev);
 
 }  // namespace esp

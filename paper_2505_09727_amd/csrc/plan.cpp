@@ -15,6 +15,9 @@
 #include <cmath>
 #include <cstdio>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace esp {
 
@@ -186,7 +189,23 @@ double Prolate::ft(double w) const {
     return s;
 }
 
+static double c_for_tolerance_uncached(double eps);
+
 double c_for_tolerance(double eps) {
+    static std::mutex mu;
+    static std::map<double, double> cache;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(eps);
+        if (it != cache.end()) return it->second;
+    }
+    const double c = c_for_tolerance_uncached(eps);
+    std::lock_guard<std::mutex> g(mu);
+    cache[eps] = c;
+    return c;
+}
+
+static double c_for_tolerance_uncached(double eps) {
     // psi_0^c(1) decreases monotonically in c; bisection on log psi(1)
     double lo = std::max(0.5, std::log(1.0 / eps) - 3.0), hi = std::log(1.0 / eps) + 10.0;
     const double target = std::log(eps);
@@ -278,13 +297,28 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.tile != 0 && (r.tile < 4 || r.tile > 16)) { msg = "tile must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
     Prolate chi(r.c);
     if (r.c1 <= 0) {
-        double best = std::numeric_limits<double>::infinity(), bc1 = r.c;
-        for (int i = 0; i <= 50; ++i) {
-            const double c1 = r.c * (0.9 + 0.5 * i / 50.0);
-            const double ea = aliasing_error(r.nf, L, chi, r.rc, c1, r.P);
-            if (ea < best) { best = ea; bc1 = c1; }
+        // E_A depends on L only through rc/h; memoise per (n, P, c, rc/h)
+        static std::mutex mu;
+        static std::map<std::tuple<int, int, double, double>, double> cache;
+        const double rho = std::round(r.rc / r.h * 1e12) / 1e12;
+        const auto key = std::make_tuple(r.nf, r.P, r.c, rho);
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) { r.c1 = it->second; hit = true; }
         }
-        r.c1 = bc1;
+        if (!hit) {
+            double best = std::numeric_limits<double>::infinity(), bc1 = r.c;
+            for (int i = 0; i <= 50; ++i) {
+                const double c1 = r.c * (0.9 + 0.5 * i / 50.0);
+                const double ea = aliasing_error(r.nf, L, chi, r.rc, c1, r.P);
+                if (ea < best) { best = ea; bc1 = c1; }
+            }
+            r.c1 = bc1;
+            std::lock_guard<std::mutex> g(mu);
+            cache[key] = bc1;
+        }
     }
     r.s0 = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * r.rc);
     if (r.degree != 0 && (r.degree < 4 || r.degree > 16)) { msg = "degree must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
@@ -404,6 +438,52 @@ void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, d
         Lr[i] = (1.0 - G) / (4 * kPi * r[i]);
         dLr[i] = -(1.0 - G) / (4 * kPi * r[i] * r[i]) - ch / (p.rc * 4 * kPi * r[i]);
     }
+}
+
+std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, double, double, double>, std::shared_ptr<const ClassTables>> cache;
+    const double rho = std::round(p.rc / p.h * 1e12) / 1e12;
+    const auto key = std::make_tuple(p.nf, p.P, p.degree, p.c, p.c1, rho);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    auto t = std::make_shared<ClassTables>();
+    t->n = p.nf;
+    t->P = p.P;
+    t->degree = p.degree;
+    t->c = p.c;
+    t->c1 = p.c1;
+    t->rho = rho;
+    esp_params ref = p;                 // the reference box L = n
+    ref.L = p.nf;
+    ref.h = 1.0;
+    ref.rc = rho;
+    influence_tables(ref, t->TS, t->Tphi);
+    window_polynomials(ref, t->poly);
+    for (int k = 0; k < p.nf; ++k) {
+        const double a = 2.0 * kPi * k / p.nf;
+        t->tw.push_back(std::cos(a));
+        t->tw.push_back(std::sin(a));
+    }
+    Prolate chi(p.c);
+    t->s0_ref = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * rho);
+    double wm = 0.0;
+    for (int j = 0; j < p.P; ++j)
+        for (int s = 0; s <= 64; ++s) {
+            const double y = -0.5 + s / 64.0;
+            double v = 0.0;
+            for (int m = p.degree; m >= 0; --m) v = v * y + t->poly[(size_t)j * (p.degree + 1) + m];
+            wm = std::max(wm, std::fabs(v));
+        }
+    wm *= 1.001;
+    t->wmax3 = wm * wm * wm;
+    std::lock_guard<std::mutex> g(mu);
+    auto& slot = cache[key];
+    if (!slot) slot = t;
+    return slot;
 }
 
 }  // namespace esp

@@ -2,6 +2,7 @@
 // long-range pipeline. No device code here.
 #pragma once
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -52,5 +53,19 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
 void window_polynomials(esp_params& p, std::vector<double>& coef);
 void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<double>& Tphi);
 void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, double* dLr);
+
+// Tables of one parameter class. With rc proportional to h (the default
+// rule), the influence tables, window polynomials and c1 depend on
+// (n, P, degree, c, c1, rc/h) only; a box of side L then needs just the
+// scalars pscale = n/L (p ~ 1/L), s0 = s0_ref n/L and 1/L. Tables are made for
+// the reference box L = n (h = 1) and cached process-wide.
+struct ClassTables {
+    int n, P, degree;
+    double c, c1, rho;            // rho = rc/h
+    std::vector<double> TS, Tphi, poly, tw;  // tw interleaved (cos, sin)
+    double s0_ref;                // S(0) for L = n
+    double wmax3;                 // cube of the window polynomials' peak
+};
+std::shared_ptr<const ClassTables> class_tables(const esp_params& p);
 
 }  // namespace esp
