@@ -115,6 +115,14 @@ esp_status esp_influence_tables(const esp_params* resolved, double* TS, double* 
 esp_status esp_local_kernel(const esp_params* resolved, const double* r, int64_t n,
                             double* Lr, double* dLr);
 
+/* Precompute (host, process-wide cache) the parameter classes of every grid
+ * size 8..nf_max (even 2^a 3^b) for the default rules at each tolerance in
+ * tols[ntol], using `threads` host threads (0: up to 16). A class holds the
+ * window polynomials, influence tables and c1 search of one (grid, tolerance)
+ * pair; the first plan or served request of a class otherwise pays for it
+ * (~0.1 s). */
+esp_status esp_warm_tables(const double* tols, int ntol, int nf_max, int threads);
+
 /* ---- single-system plans ---- */
 
 esp_status esp_plan_create(const double box[3], int64_t N, double tol, esp_plan** out);
@@ -176,6 +184,80 @@ esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q,
 esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void* phi, void* F,
                             int reps, double* ms);
 const char* esp_phase_name(int phase);
+
+/* ---- serving: continuous batching of independent long-range solves ----
+ *
+ * A server owns one HIP stream, one scheduler thread and a device arena of
+ * hbm_budget_bytes. Each request is a cubic system (FP32) that is evaluated
+ * for nsteps consecutive MD steps; its positions stay resident on the device
+ * and move between steps by a seeded drift (each coordinate by
+ * drift * (2u - 1), u the SplitMix64 variate of the counter
+ * (step << 40) + 3 i + c + 1 added to seed in multiples of 0x9E3779B97F4A7C15,
+ * wrapped into [0, L)), so a host can reproduce every step. Requests are
+ * admitted in arrival order while their state fits the arena and fewer than
+ * max_active run; every scheduler iteration evaluates one step of every
+ * admitted request with one launch per pipeline phase, so requests that
+ * arrive while others run join the next iteration and their work overlaps on
+ * the device. Results of one request do not depend on which others share
+ * its launches (the spread sums in fixed point). Requests larger than the
+ * whole budget are refused at submission with ESP_E_BUSY. All server calls
+ * are thread-safe. Errors of server calls are reported by
+ * esp_server_last_error. */
+typedef struct esp_server esp_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* device memory for request state (0: 16 GiB), allocated at creation */
+    int    max_active;        /* most requests admitted at once (0: 4096) */
+    int    keep_outputs;      /* 1: keep each request's last-step phi and F for esp_server_fetch */
+} esp_server_opts;
+
+typedef struct {
+    double       L;           /* cubic box side */
+    int64_t      N;           /* particles (>= 2) */
+    double       tol;         /* force tolerance, parameters as for esp_plan_create */
+    const float* pos;         /* HOST, N x 3, copied by esp_server_submit */
+    const float* q;           /* HOST, N, copied by esp_server_submit */
+    int          nsteps;      /* steps to evaluate (>= 1) */
+    double       drift;       /* drift amplitude per coordinate and step (0: static) */
+    uint64_t     seed;        /* drift stream */
+    uint64_t     tag;         /* returned in the result */
+} esp_request;
+
+typedef struct {
+    uint64_t id, tag;
+    int      status;          /* ESP_OK, ESP_E_NOT_NEUTRAL, or ESP_E_BUSY (never admitted) */
+    int      nsteps;
+    int64_t  N;
+    int      nf, P;
+    double   t_submit, t_admit, t_done;  /* seconds since the server was created */
+    double   E_first, E_last;            /* energies of the first and the last step */
+} esp_result;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, active, waiting, iterations;
+    double  particle_steps;   /* sum of N * nsteps over completed requests */
+    double  busy_s;           /* scheduler time spent on steps */
+    double  span_s;           /* first submission to last completion */
+    double  p50_latency_s, p99_latency_s, max_latency_s;  /* t_done - t_submit */
+    size_t  bytes_in_use, bytes_peak;
+    double  build_s;          /* scheduler host time assembling launch sets */
+    double  admit_s;          /* scheduler host time admitting (incl. uploads) */
+    double  step_s;           /* enqueue-to-completion time of the steps */
+} esp_server_stats;
+
+esp_status esp_server_create(const esp_server_opts* opts, esp_server** out);
+/* Enqueue a request (never waits for the device); *id identifies its result. */
+esp_status esp_server_submit(esp_server* server, const esp_request* req, uint64_t* id);
+/* Move up to max finished results into out[]; *n receives how many. */
+esp_status esp_server_poll(esp_server* server, esp_result* out, int max, int* n);
+/* Copy a finished request's last-step outputs (HOST phi[N], F[N x 3]) once;
+ * needs keep_outputs. */
+esp_status esp_server_fetch(esp_server* server, uint64_t id, float* phi, float* F);
+/* Wait until no request is queued or running (ESP_E_BUSY on timeout). */
+esp_status esp_server_wait(esp_server* server, double timeout_s);
+esp_status esp_server_get_stats(esp_server* server, esp_server_stats* out);
+void       esp_server_destroy(esp_server* server);
+const char* esp_server_last_error(void);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* esp_last_error(void);

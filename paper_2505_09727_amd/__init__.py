@@ -8,10 +8,12 @@ not been built (python -m paper_2505_09727_amd.build).
 from .esp import (  # noqa: F401
     EspError,
     Plan,
+    Server,
     esp_influence_tables,
     esp_local_kernel,
     esp_plan_query,
     esp_version,
+    esp_warm_tables,
     esp_window_coeffs,
     lib,
 )

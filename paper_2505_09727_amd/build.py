@@ -40,6 +40,7 @@ def build(verbose: bool = False) -> str:
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(OUT_DIR, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "runtime.cpp"), "-o", os.path.join(OUT_DIR, "runtime.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "assembly.cpp"), "-o", os.path.join(OUT_DIR, "assembly.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "server.cpp"), "-o", os.path.join(OUT_DIR, "server.o")],
         ["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "plan.cpp"), "-o", os.path.join(OUT_DIR, "plan.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
@@ -48,7 +49,7 @@ def build(verbose: bool = False) -> str:
                 print(r.stdout + r.stderr, file=sys.stderr)
     objs = [j[-1] for j in jobs]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     return LIB
 

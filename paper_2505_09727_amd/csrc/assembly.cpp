@@ -199,6 +199,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.grid = sl.scr.grid;
         d.tiles = sl.scr.tiles;
         d.out = sl.scr.out;
+        d.seed = sl.seed;
+        d.drift = sl.drift;
+        d.step = 0;
         d.pitem_off = (int)pitems_.size();
         for (int c = 0; c < d.N; c += kParticleChunk) pitems_.push_back(make_int2(s, c));
         d.npitem = (int)pitems_.size() - d.pitem_off;

@@ -66,6 +66,8 @@ struct SystemSlot {
     const void* q = nullptr;
     void* phi = nullptr;
     void* F = nullptr;
+    unsigned long long seed = 0;  // serving drift stream
+    float drift = 0.0f;
 };
 
 // Host and device copies of a launch set.
@@ -77,7 +79,9 @@ class LaunchSet {
     esp_status build(const std::vector<SystemSlot>& systems, int prec, hipStream_t stream, std::string& msg);
     // Re-point the particle arrays of system s (no upload).
     void set_io(int s, const void* pos, const void* q, void* phi, void* F);
-    // Upload the descriptors after set_io.
+    // Serving: drift step of system s for the next drift launch (0: none).
+    void set_step(int s, int step) { hsys_[s].step = step; }
+    // Upload the descriptors after set_io / set_step.
     esp_status upload_descriptors(std::string& msg);
     const Launch& launch() const { return L_; }
     const std::vector<Group>& groups() const { return groups_; }

@@ -45,6 +45,10 @@ struct SysDesc {
     void* grid;       // n x n x (n + 2) reals (half spectrum in place)
     void* tiles;      // nbins x E^3 reals
     double* out;      // 8 doubles: E, sum q, sum |q|, sum q^2, fixed-point scale
+    // serving: per-step drift of the resident positions (k_drift)
+    unsigned long long seed;  // drift stream of the request
+    int step;         // index of the drift to apply (0: none this iteration)
+    float drift;      // amplitude: each coordinate moves by U(-drift, drift)
 };
 
 // Work items: .x = system index in the launch, .y (.z, .w) = position inside it.

@@ -24,6 +24,13 @@ template <> struct Vec4<double> { using type = double4; };
 
 template <typename R> struct cplx { R x, y; };
 
+// FFT arithmetic is kept free of fused multiply-adds: the FFT kernels are
+// instantiated for several per-thread work bounds (chosen from the largest
+// grid of a launch), and unfused arithmetic rounds every butterfly the same
+// way in each instantiation, so a system's result does not depend on which
+// other systems share its launch.
+#pragma clang fp contract(off)
+
 template <typename R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -145,6 +152,8 @@ __device__ void fft_lines(cplx<R>* buf, int n, int nlines, int lstride, int estr
         m /= 3;
     }
 }
+
+#pragma clang fp contract(fast)
 
 // ---------------------------------------------------------------------------
 // Deterministic block sum of a double (fixed tree; blockDim a power of two).
@@ -580,6 +589,7 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
     }
 }
 
+#pragma clang fp contract(off)
 // ---------------------------------------------------------------------------
 // Forward FFT along z (real-to-complex) and y for one x-plane. Pairs of real
 // rows (2r, 2r+1) are transformed as one complex row and split afterwards.
@@ -753,6 +763,8 @@ __global__ void __launch_bounds__(256) k_fft_x(const SysDesc* __restrict__ sys, 
     if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
 }
 
+#pragma clang fp contract(fast)
+
 // Energy per system: E = E_k - S(0)/2 sum q^2, plus the charge sums.
 __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
                                                   const double* __restrict__ bpart, double* __restrict__ E_dev) {
@@ -776,6 +788,36 @@ __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sy
         S.out[2] = sa;
         S.out[3] = s2;
         if (E_dev) E_dev[blockIdx.x] = E;
+    }
+}
+
+// Serving: move the resident positions of every system with step > 0 by the
+// drift of that step. Counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA
+// 2014): the uniform variate of (step k, particle i, component c) is
+// mix(seed + (k * 2^40 + 3 i + c + 1) * 0x9E3779B97F4A7C15) / 2^64, so the
+// host reproduces every position exactly.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_drift(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+    const int2 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    const int il = wi.y + threadIdx.x;
+    if (S.step <= 0 || il >= S.N) return;
+    float* pos = reinterpret_cast<float*>(const_cast<void*>(S.pos));
+    const float L = (float)(1.0 / S.inv_L);
+    for (int c = 0; c < 3; ++c) {
+        const unsigned long long ctr = ((unsigned long long)S.step << 40) + 3ULL * il + c + 1ULL;
+        const unsigned long long z = splitmix64(S.seed + ctr * 0x9E3779B97F4A7C15ULL);
+        const double u = (double)(z >> 11) * 0x1.0p-53;
+        const float d = (float)((double)S.drift * (2.0 * u - 1.0));
+        float x = pos[3 * il + c] + d;
+        if (x >= L) x -= L;
+        if (x < 0.0f) x += L;
+        pos[3 * il + c] = x;
     }
 }
 
@@ -890,6 +932,11 @@ static hipError_t fft_r(const Launch& L, int which, int mode) {
 
 hipError_t launch_fft(const Launch& L, int which, int mode) {
     return L.prec == 64 ? fft_r<double>(L, which, mode) : fft_r<float>(L, which, mode);
+}
+
+hipError_t launch_drift(const Launch& L) {
+    k_drift<<<L.n_pitems, 256, 0, L.stream>>>(L.sys, L.pitems);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Launch& L, double* E_dev) {

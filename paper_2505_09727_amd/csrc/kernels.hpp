@@ -49,5 +49,7 @@ hipError_t launch_fold(const Launch& L);
 hipError_t launch_fft(const Launch& L, int which, int mode);
 hipError_t launch_gather(const Launch& L, const Group& G);
 hipError_t launch_finalize(const Launch& L, double* E_dev);
+// Serving: apply each system's drift step to its resident FP32 positions.
+hipError_t launch_drift(const Launch& L);
 
 }  // namespace esp

@@ -245,21 +245,27 @@ int grid_size(double L, double h_max) {
     return n;
 }
 
-double aliasing_error(int n, double L, const Prolate& chi, double rc, double c1, int P) {
-    // E_A = 6 sum_{m in I\0} | chi^(2 pi rc|m|/L)/|m|^2 * phi^(k + 2 pi (n,0,0)/L)/phi^(k) |
+// c1-independent factor of E_A: a(m_x) = sum_{m_y, m_z} |chi^(2 pi rc |m|/L)| / |m|^2
+// for m_x = -n/2 .. n/2-1 (only the x factor of the window ratio depends on c1).
+static std::vector<double> aliasing_weights(int n, double L, const Prolate& chi, double rc) {
     const double I1 = chi.integral(1.0);
-    const double h = L / n;
     const int h2 = n / 2;
-    std::vector<double> ax(n, 0.0);  // sum over (my, mz) for each mx
-    std::vector<double> chat(3 * h2 * h2 + 1);
+    std::vector<double> chat(3 * h2 * h2 + 1, 0.0);
     for (int m2 = 1; m2 <= 3 * h2 * h2; ++m2)
         chat[m2] = std::fabs(0.5 * chi.ft(2 * kPi * rc * std::sqrt((double)m2) / L) / I1) / m2;
-    for (int mx = -h2; mx < h2; ++mx)
+    // a(m_x) depends on |m_x| only: sum over (m_y, m_z) once per |m_x|
+    std::vector<double> byabs(h2 + 1, 0.0);
+    for (int ax_ = 0; ax_ <= h2; ++ax_)
         for (int my = -h2; my < h2; ++my)
-            for (int mz = -h2; mz < h2; ++mz) {
-                const int m2 = mx * mx + my * my + mz * mz;
-                if (m2) ax[mx + h2] += chat[m2];
-            }
+            for (int mz = -h2; mz < h2; ++mz) byabs[ax_] += chat[ax_ * ax_ + my * my + mz * mz];
+    std::vector<double> ax(n);
+    for (int mx = -h2; mx < h2; ++mx) ax[mx + h2] = byabs[mx < 0 ? -mx : mx];
+    return ax;
+}
+
+static double aliasing_from_weights(const std::vector<double>& ax, int n, double L, double c1, int P) {
+    const double h = L / n;
+    const int h2 = n / 2;
     Prolate win(c1);
     double s = 0.0;
     for (int mx = -h2; mx < h2; ++mx) {
@@ -268,6 +274,27 @@ double aliasing_error(int n, double L, const Prolate& chi, double rc, double c1,
         s += ax[mx + h2] * std::fabs(a / b);
     }
     return 6.0 * s;
+}
+
+double aliasing_error(int n, double L, const Prolate& chi, double rc, double c1, int P) {
+    // E_A = 6 sum_{m in I\0} | chi^(2 pi rc|m|/L)/|m|^2 * phi^(k + 2 pi (n,0,0)/L)/phi^(k) |
+    return aliasing_from_weights(aliasing_weights(n, L, chi, rc), n, L, c1, P);
+}
+
+// Memoised per-c quantities: psi(0) / int_0^1 psi (for S(0)).
+static double chi0_over_I1(double c) {
+    static std::mutex mu;
+    static std::map<double, double> cache;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(c);
+        if (it != cache.end()) return it->second;
+    }
+    Prolate chi(c);
+    const double v = chi(0.0) / chi.integral(1.0);
+    std::lock_guard<std::mutex> g(mu);
+    cache[c] = v;
+    return v;
 }
 
 esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req, esp_params* out,
@@ -291,16 +318,22 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     }
     if (r.nf < r.P) { msg = "grid size must be at least P"; return ESP_E_UNSUPPORTED; }
     r.h = L / r.nf;
-    if (r.rc <= 0) r.rc = r.kappa * r.c * r.h / kPi;
+    // rho = rc/h keys every L-independent cache; exact under the default rule
+    double rho;
+    if (r.rc <= 0) {
+        rho = r.kappa * r.c / kPi;
+        r.rc = rho * r.h;
+    } else {
+        rho = std::round(r.rc / r.h * 1e9) / 1e9;
+    }
     if (r.precision == 0) r.precision = 32;
     if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
     if (r.tile != 0 && (r.tile < 4 || r.tile > 16)) { msg = "tile must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
-    Prolate chi(r.c);
     if (r.c1 <= 0) {
-        // E_A depends on L only through rc/h; memoise per (n, P, c, rc/h)
+        // E_A depends on L only through rc/h; memoise per (n, P, c, rc/h).
+        // Evaluated in the reference box L = n (h = 1, rc = rho).
         static std::mutex mu;
         static std::map<std::tuple<int, int, double, double>, double> cache;
-        const double rho = std::round(r.rc / r.h * 1e12) / 1e12;
         const auto key = std::make_tuple(r.nf, r.P, r.c, rho);
         bool hit = false;
         {
@@ -309,10 +342,12 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
             if (it != cache.end()) { r.c1 = it->second; hit = true; }
         }
         if (!hit) {
+            Prolate chi(r.c);
+            const std::vector<double> ax = aliasing_weights(r.nf, (double)r.nf, chi, rho);
             double best = std::numeric_limits<double>::infinity(), bc1 = r.c;
             for (int i = 0; i <= 50; ++i) {
                 const double c1 = r.c * (0.9 + 0.5 * i / 50.0);
-                const double ea = aliasing_error(r.nf, L, chi, r.rc, c1, r.P);
+                const double ea = aliasing_from_weights(ax, r.nf, (double)r.nf, c1, r.P);
                 if (ea < best) { best = ea; bc1 = c1; }
             }
             r.c1 = bc1;
@@ -320,11 +355,27 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
             cache[key] = bc1;
         }
     }
-    r.s0 = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * r.rc);
+    r.s0 = chi0_over_I1(r.c) / (4.0 * kPi * r.rc);
     if (r.degree != 0 && (r.degree < 4 || r.degree > 16)) { msg = "degree must lie in [4, 16]"; return ESP_E_UNSUPPORTED; }
     if (r.degree == 0) {
-        std::vector<double> coef;
-        window_polynomials(r, coef);
+        // smallest adequate degree; memoised per (c1, P, tol)
+        static std::mutex mu;
+        static std::map<std::tuple<double, int, double>, int> cache;
+        const auto key = std::make_tuple(r.c1, r.P, r.tol);
+        int d = 0;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) d = it->second;
+        }
+        if (d) {
+            r.degree = d;
+        } else {
+            std::vector<double> coef;
+            window_polynomials(r, coef);
+            std::lock_guard<std::mutex> g(mu);
+            cache[key] = r.degree;
+        }
     }
     *out = r;
     return ESP_OK;
@@ -443,7 +494,8 @@ void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, d
 std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {
     static std::mutex mu;
     static std::map<std::tuple<int, int, int, double, double, double>, std::shared_ptr<const ClassTables>> cache;
-    const double rho = std::round(p.rc / p.h * 1e12) / 1e12;
+    double rho = p.kappa * p.c / kPi;  // the default rule's exact rc/h
+    if (std::fabs(rho * p.h - p.rc) > 1e-12 * p.rc) rho = std::round(p.rc / p.h * 1e9) / 1e9;
     const auto key = std::make_tuple(p.nf, p.P, p.degree, p.c, p.c1, rho);
     {
         std::lock_guard<std::mutex> g(mu);

@@ -10,6 +10,8 @@
 #include <new>
 #include <set>
 #include <string>
+#include <thread>
+#include <atomic>
 #include <vector>
 
 #include "assembly.hpp"
@@ -278,6 +280,42 @@ esp_status esp_local_kernel(const esp_params* resolved, const double* r, int64_t
         if (!(r[i] > 0)) return fail(ESP_E_INVALID, "radii must be positive");
     local_kernel(*resolved, r, n, Lr, dLr);
     return ESP_OK;
+}
+
+esp_status esp_warm_tables(const double* tols, int ntol, int nf_max, int threads) {
+    try {
+        if (!tols || ntol < 1) return fail(ESP_E_INVALID, "no tolerances");
+        if (nf_max <= 0 || nf_max > 144) nf_max = 144;
+        std::vector<std::pair<int, double>> work;
+        for (int i = 0; i < ntol; ++i) {
+            const int P = order_for_tol(tols[i]);
+            if (!(tols[i] > 0) || P > 12) return fail(ESP_E_UNSUPPORTED, "tolerance outside the supported orders");
+            for (int n = std::max(8, P); n <= nf_max; ++n)  // grids narrower than the window never occur
+                if (is_smooth(n)) work.emplace_back(n, tols[i]);
+        }
+        if (threads <= 0) threads = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+        std::atomic<size_t> next{0};
+        std::atomic<int> bad{0};
+        auto worker = [&] {
+            for (size_t k; (k = next++) < work.size();) {
+                esp_params req{}, r{};
+                req.nf = work[k].first;
+                std::string msg;
+                // any box with this grid: the class does not depend on L
+                if (resolve_params(1.25 * req.nf, 1000, work[k].second, &req, &r, msg) != ESP_OK) {
+                    ++bad;
+                    continue;
+                }
+                (void)class_tables(r);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 0; t < threads; ++t) pool.emplace_back(worker);
+        for (auto& t : pool) t.join();
+        return bad ? fail(ESP_E_INVALID, "some tolerances could not be resolved") : ESP_OK;
+    } catch (const std::exception& e) {
+        return fail(ESP_E_INVALID, e.what());
+    }
 }
 
 esp_status esp_plan_create_ex(const double box[3], int64_t N, double tol, const esp_params* req, esp_plan** out) {

@@ -37,6 +37,37 @@ class esp_params(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class esp_server_opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_active", C.c_int), ("keep_outputs", C.c_int)]
+
+
+class esp_request(C.Structure):
+    _fields_ = [("L", C.c_double), ("N", C.c_int64), ("tol", C.c_double), ("pos", C.c_void_p),
+                ("q", C.c_void_p), ("nsteps", C.c_int), ("drift", C.c_double), ("seed", C.c_uint64),
+                ("tag", C.c_uint64)]
+
+
+class esp_result(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int), ("nsteps", C.c_int),
+                ("N", C.c_int64), ("nf", C.c_int), ("P", C.c_int), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("E_first", C.c_double), ("E_last", C.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class esp_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("active", C.c_int64), ("waiting", C.c_int64), ("iterations", C.c_int64),
+                ("particle_steps", C.c_double), ("busy_s", C.c_double), ("span_s", C.c_double),
+                ("p50_latency_s", C.c_double), ("p99_latency_s", C.c_double), ("max_latency_s", C.c_double),
+                ("bytes_in_use", C.c_size_t), ("bytes_peak", C.c_size_t), ("build_s", C.c_double),
+                ("admit_s", C.c_double), ("step_s", C.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = C.POINTER
 _vp = C.c_void_p
 _SIGS = {
@@ -44,6 +75,7 @@ _SIGS = {
     "esp_window_coeffs": (C.c_int, [_P(esp_params), _P(C.c_double)]),
     "esp_influence_tables": (C.c_int, [_P(esp_params), _P(C.c_double), _P(C.c_double)]),
     "esp_local_kernel": (C.c_int, [_P(esp_params), _P(C.c_double), C.c_int64, _P(C.c_double), _P(C.c_double)]),
+    "esp_warm_tables": (C.c_int, [_P(C.c_double), C.c_int, C.c_int, C.c_int]),
     "esp_plan_create": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(_vp)]),
     "esp_plan_create_ex": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(esp_params), _P(_vp)]),
     "esp_batch_create": (C.c_int, [C.c_int, _P(C.c_double), _P(C.c_int64), _P(C.c_double), _P(esp_params),
@@ -57,6 +89,16 @@ _SIGS = {
     "esp_plan_set_graph": (C.c_int, [_vp, C.c_int]),
     "esp_plan_destroy": (None, [_vp]),
     "esp_debug_stage": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
+    "esp_plan_profile": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_double)]),
+    "esp_phase_name": (C.c_char_p, [C.c_int]),
+    "esp_server_create": (C.c_int, [_P(esp_server_opts), _P(_vp)]),
+    "esp_server_submit": (C.c_int, [_vp, _P(esp_request), _P(C.c_uint64)]),
+    "esp_server_poll": (C.c_int, [_vp, _P(esp_result), C.c_int, _P(C.c_int)]),
+    "esp_server_fetch": (C.c_int, [_vp, C.c_uint64, _vp, _vp]),
+    "esp_server_wait": (C.c_int, [_vp, C.c_double]),
+    "esp_server_get_stats": (C.c_int, [_vp, _P(esp_server_stats)]),
+    "esp_server_destroy": (None, [_vp]),
+    "esp_server_last_error": (C.c_char_p, []),
     "esp_last_error": (C.c_char_p, []),
     "esp_version": (C.c_char_p, []),
 }
@@ -128,6 +170,13 @@ def esp_local_kernel(params: esp_params, r):
     _check(lib().esp_local_kernel(C.byref(params), r.ctypes.data_as(dp), len(r), Lr.ctypes.data_as(dp),
                                   dLr.ctypes.data_as(dp)))
     return Lr, dLr
+
+
+def esp_warm_tables(tols, nf_max: int = 144, threads: int = 0) -> None:
+    """Precompute the parameter classes of every grid size up to nf_max for
+    each tolerance (host threads; process-wide cache)."""
+    arr = (C.c_double * len(tols))(*[float(t) for t in tols])
+    _check(lib().esp_warm_tables(arr, len(tols), int(nf_max), int(threads)))
 
 
 def _ptr(t):
@@ -202,6 +251,60 @@ class Plan:
     def close(self):
         if self._h:
             lib().esp_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(status):
+    if status != 0:
+        raise EspError(status, lib().esp_server_last_error().decode())
+
+
+class Server:
+    """Continuous-batching request server (esp_server_*); FP32, host inputs."""
+
+    def __init__(self, hbm_budget_bytes=0, max_active=0, keep_outputs=False):
+        self._h = C.c_void_p()
+        o = esp_server_opts(hbm_budget_bytes, max_active, int(bool(keep_outputs)))
+        _scheck(lib().esp_server_create(C.byref(o), C.byref(self._h)))
+
+    def submit(self, pos, q, L, tol, nsteps=1, drift=0.0, seed=0, tag=0):
+        pos = np.ascontiguousarray(pos, dtype=np.float32)
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        r = esp_request(float(L), len(q), float(tol), pos.ctypes.data, q.ctypes.data, int(nsteps), float(drift),
+                        int(seed), int(tag))
+        rid = C.c_uint64()
+        _scheck(lib().esp_server_submit(self._h, C.byref(r), C.byref(rid)))
+        return rid.value
+
+    def poll(self, max_results=1024):
+        buf = (esp_result * max_results)()
+        n = C.c_int()
+        _scheck(lib().esp_server_poll(self._h, buf, max_results, C.byref(n)))
+        return [buf[i].to_dict() for i in range(n.value)]
+
+    def fetch(self, rid, N):
+        phi = np.empty(N, dtype=np.float32)
+        F = np.empty((N, 3), dtype=np.float32)
+        _scheck(lib().esp_server_fetch(self._h, rid, phi.ctypes.data, F.ctypes.data))
+        return phi, F
+
+    def wait(self, timeout_s=60.0):
+        _scheck(lib().esp_server_wait(self._h, float(timeout_s)))
+
+    def stats(self):
+        st = esp_server_stats()
+        _scheck(lib().esp_server_get_stats(self._h, C.byref(st)))
+        return st.to_dict()
+
+    def close(self):
+        if self._h:
+            lib().esp_server_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

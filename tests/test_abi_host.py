@@ -124,3 +124,20 @@ def test_invalid_arguments_return_status(kw, box, tol, status):
         esp.esp_plan_query(box, 100, tol, **kw)
     assert ei.value.status == status
     assert esp.lib().esp_last_error().decode() != ""
+
+
+def test_warm_tables_covers_every_grid_and_rejects_bad_tolerances():
+    """Warm-up resolves every smooth grid of a tolerance (host only); a later
+    query of any box with that grid and tolerance then agrees with the oracle's
+    rules, and tolerances outside Table 2's orders are refused."""
+    _lib_or_skip()
+    from paper_2505_09727_amd import EspError, esp_warm_tables
+    esp_warm_tables([1e-3], nf_max=48, threads=2)
+    prm = esp.esp_plan_query(40.0, 4000, 1e-3)
+    ref = esp_parameters(40.0, 1e-3)
+    assert (prm.nf, prm.P) == (ref["n"], ref["P"])
+    ea = aliasing_error(prm.nf, 40.0, prm.c, prm.rc, prm.c1, prm.P)
+    assert ea <= 1.01 * aliasing_error(prm.nf, 40.0, prm.c, prm.rc, ref["c1"], prm.P)
+    for bad in ([0.0], [1e-14]):
+        with pytest.raises(EspError):
+            esp_warm_tables(bad, nf_max=16)

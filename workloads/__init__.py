@@ -178,3 +178,45 @@ def request_stream(duration_s: float = 10.0, rate_hz: float = 2000.0, lo: int = 
 NACL = dict(cells=4, a=5.64, n=16, P=6, tol=1e-4)
 WATER_9K = dict(n_mol=3000, L=31.0, n=32, tol=1e-4, seed=2)
 WATER_300K = dict(n_mol=100000, L=100.0, n=96, tol=1e-5, seed=3, steps=100)
+
+
+# ---------------------------------------------------------------------------
+# Serving drift stream: counter-based SplitMix64 (Steele, Lea & Flood,
+# "Fast splittable pseudorandom number generators", OOPSLA 2014; constants of
+# Vigna's reference splitmix64.c). The variate of (step k, particle i,
+# component c) is mix(seed + (k * 2^40 + 3 i + c + 1) * GAMMA) / 2^64, and a
+# coordinate moves by drift * (2u - 1) in FP32 with wrapping into [0, L).
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64_mix(z):
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64_sequence(seed: int, count: int):
+    """The classic sequential generator: state += GAMMA, output mix(state)."""
+    k = np.arange(1, count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return splitmix64_mix(np.uint64(seed) + k * _GAMMA)
+
+
+def serving_drift(pos32: np.ndarray, L: float, step: int, seed: int, drift: float) -> np.ndarray:
+    """Positions (float32, N x 3) after the drift of `step` (>= 1)."""
+    N = pos32.shape[0]
+    ctr = (np.uint64(step) << np.uint64(40)) + np.arange(3 * N, dtype=np.uint64) + np.uint64(1)
+    with np.errstate(over="ignore"):
+        z = splitmix64_mix(np.uint64(seed) + ctr * _GAMMA)
+    u = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    d = (drift * (2.0 * u - 1.0)).astype(np.float32).reshape(N, 3)
+    x = (pos32.astype(np.float32) + d).astype(np.float32)
+    Lf = np.float32(L)
+    x = np.where(x >= Lf, (x - Lf).astype(np.float32), x)
+    x = np.where(x < np.float32(0), (x + Lf).astype(np.float32), x)
+    return x.astype(np.float32)
