@@ -128,6 +128,8 @@ struct esp_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::unique_ptr<ServerRequest>> to_plan;    // submitted, parameters not yet resolved
+    std::map<uint64_t, std::unique_ptr<ServerRequest>> planned;  // planned ahead of an earlier request
+    uint64_t next_release = 1;                              // next id to hand to the scheduler
     std::deque<std::unique_ptr<ServerRequest>> arrivals;   // planned, not yet seen by the scheduler
     std::deque<std::unique_ptr<ServerRequest>> waiting;    // seen, waiting for memory
     std::vector<std::unique_ptr<ServerRequest>> active;    // scheduler-owned
@@ -237,18 +239,28 @@ void esp_server::plan_loop() {
         }
         std::lock_guard<std::mutex> lk(mu);
         --planning_n;
+        const uint64_t id = r->id;
         if (st != ESP_OK) {
             r->res.status = st;
             r->res.t_done = now_s(t0);
             ++failed;
             done.push_back(r->res);
             cv_done.notify_all();
-            continue;
+            r.reset();  // a hole in the release order
+        } else {
+            r->res.nf = r->prm.nf;
+            r->res.P = r->prm.P;
         }
-        r->res.nf = r->prm.nf;
-        r->res.P = r->prm.P;
-        arrivals.push_back(std::move(r));
-        cv_work.notify_one();
+        // planners finish out of order; the scheduler sees submission order
+        planned.emplace(id, std::move(r));
+        bool any = false;
+        for (auto it = planned.begin(); it != planned.end() && it->first == next_release;
+             it = planned.erase(it), ++next_release)
+            if (it->second) {
+                arrivals.push_back(std::move(it->second));
+                any = true;
+            }
+        if (any) cv_work.notify_one();
     }
 }
 
@@ -469,8 +481,8 @@ esp_status esp_server_wait(esp_server* s, double timeout_s) {
     std::unique_lock<std::mutex> lk(s->mu);
     const bool ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] {
         return !s->fatal.empty() ||
-               (s->to_plan.empty() && s->arrivals.empty() && s->waiting.empty() && s->active.empty() &&
-                s->planning_n == 0);
+               (s->to_plan.empty() && s->planned.empty() && s->arrivals.empty() && s->waiting.empty() &&
+                s->active.empty() && s->planning_n == 0);
     });
     if (!s->fatal.empty()) return sfail(ESP_E_DEVICE, s->fatal);
     return ok ? ESP_OK : sfail(ESP_E_BUSY, "timed out with requests still queued or running");
@@ -485,7 +497,8 @@ esp_status esp_server_get_stats(esp_server* s, esp_server_stats* st) {
     st->completed = s->completed;
     st->failed = s->failed;
     st->active = (int64_t)s->active.size();
-    st->waiting = (int64_t)(s->waiting.size() + s->arrivals.size() + s->to_plan.size());
+    st->waiting = (int64_t)(s->waiting.size() + s->arrivals.size() + s->planned.size() + s->to_plan.size() +
+                            s->planning_n);
     st->iterations = s->iterations;
     st->particle_steps = s->particle_steps;
     st->busy_s = s->busy_s;
