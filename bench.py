@@ -145,7 +145,20 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=0.5, help="length of the served arrival stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_mib > 0:
+        import torch
+        x = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": x.numel() * 4, "copy_bytes_written_per_launch": y.numel() * 4,
+                          "launches": 10}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
                                    "not implemented", "n_gpus": args.gpus}))

@@ -179,7 +179,8 @@ esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q,
 /* Time each pipeline phase: runs the full pipeline `reps` times on the plan's
  * stream with a HIP event between consecutive phases and writes the mean
  * milliseconds of each phase to ms[0..ESP_NUM_PHASES-1] (names from
- * esp_phase_name). Waits for the stream. */
+ * esp_phase_name). Each timed pass follows an untimed one, so the phases
+ * are not charged for host launch latency. Waits for the stream. */
 #define ESP_NUM_PHASES 9
 esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void* phi, void* F,
                             int reps, double* ms);

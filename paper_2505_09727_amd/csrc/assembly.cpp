@@ -227,8 +227,11 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         g.count = (int)titems_by_P[P].size();
         int E = 0;
         for (const int2& it : titems_by_P[P]) E = std::max(E, hsys_[it.x].E);
-        g.lds_spread = E * E * E * 8;  // 64-bit accumulators (fixed point or double)
-        g.lds_gather = E * E * E * rb;
+        // 64-bit accumulators (fixed point or double) / the potential tile,
+        // then the window coefficients (P x (degree + 1) reals, degree <= 16)
+        const int coef_bytes = 12 * 17 * 8;
+        g.lds_spread = E * E * E * 8 + coef_bytes;
+        g.lds_gather = ((E * E * E * rb + 15) & ~15) + coef_bytes;
         if (g.lds_spread > kMaxLds) {
             msg = "bin tile (T+P)^3 exceeds LDS; reduce tile";
             return ESP_E_UNSUPPORTED;

@@ -330,40 +330,85 @@ __global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys
 // ---------------------------------------------------------------------------
 // Window weights of one axis by Horner in y in [-1/2, 1/2): the P polynomial
 // pieces of psi^{c1}(2 (u - l)/P) for l = l0 .. l0+P-1, l0 = floor(u - P/2) + 1.
+// Window polynomial coefficients of one system staged in LDS, transposed so
+// the P coefficients of one power of y are contiguous: ct[m * P + j]. The
+// global table holds coef[j * (deg + 1) + m] (window piece j, power m).
 template <typename R, int P>
-__device__ __forceinline__ int window(R u, const R* __restrict__ coef, int deg, R* w) {
-    const R hp = R(0.5) * R(P);
-    const R f = floor(u - hp);
-    const R y = (u - hp) - f - R(0.5);
+__device__ __forceinline__ void stage_coef(R* __restrict__ ct, const R* __restrict__ coef, int deg) {
     const int d1 = deg + 1;
-#pragma unroll
-    for (int j = 0; j < P; ++j) w[j] = coef[j * d1 + deg];
-    for (int m = deg - 1; m >= 0; --m) {
-#pragma unroll
-        for (int j = 0; j < P; ++j) w[j] = w[j] * y + coef[j * d1 + m];
+    for (int i = threadIdx.x; i < P * d1; i += blockDim.x) {
+        const int j = i / d1, m = i - j * d1;
+        ct[m * P + j] = coef[i];
     }
-    return (int)f + 1;
 }
 
+// Window weights of the three axes of one particle (eq. spread): the P pieces
+// of the polynomial window at y = frac(u - P/2) - 1/2, evaluated by Horner's
+// rule for all three axes at once so each power's coefficients are read from
+// LDS once. l0[a] is the first grid index of axis a's support.
 template <typename R, int P>
-__device__ __forceinline__ int window_d(R u, const R* __restrict__ coef, int deg, R* w, R* dw) {
+__device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__ ct, int deg, R (&w)[3][P],
+                                         int (&l0)[3]) {
     const R hp = R(0.5) * R(P);
-    const R f = floor(u - hp);
-    const R y = (u - hp) - f - R(0.5);
-    const int d1 = deg + 1;
+    const R u[3] = {ux, uy, uz};
+    R y[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R f = floor(u[a] - hp);
+        y[a] = (u[a] - hp) - f - R(0.5);
+        l0[a] = (int)f + 1;
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        w[j] = coef[j * d1 + deg];
-        dw[j] = R(0);
+        const R c = ct[deg * P + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[a][j] = c;
     }
     for (int m = deg - 1; m >= 0; --m) {
+        R c[P];
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            dw[j] = dw[j] * y + w[j];
-            w[j] = w[j] * y + coef[j * d1 + m];
+        for (int j = 0; j < P; ++j) c[j] = ct[m * P + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int j = 0; j < P; ++j) w[a][j] = w[a][j] * y[a] + c[j];
+    }
+}
+
+// As windows3, with the derivatives d w / d y (= d w / d u).
+template <typename R, int P>
+__device__ __forceinline__ void windows3_d(R ux, R uy, R uz, const R* __restrict__ ct, int deg, R (&w)[3][P],
+                                           R (&dw)[3][P], int (&l0)[3]) {
+    const R hp = R(0.5) * R(P);
+    const R u[3] = {ux, uy, uz};
+    R y[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R f = floor(u[a] - hp);
+        y[a] = (u[a] - hp) - f - R(0.5);
+        l0[a] = (int)f + 1;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const R c = ct[deg * P + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w[a][j] = c;
+            dw[a][j] = R(0);
         }
     }
-    return (int)f + 1;
+    for (int m = deg - 1; m >= 0; --m) {
+        R c[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) c[j] = ct[m * P + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                dw[a][j] = dw[a][j] * y[a] + w[a][j];
+                w[a][j] = w[a][j] * y[a] + c[j];
+            }
+    }
 }
 
 __device__ __forceinline__ int wrapi(int g, int n) {
@@ -381,8 +426,9 @@ __device__ __forceinline__ int wrapi(int g, int n) {
 // LDS accumulator: FP32 systems accumulate in 64-bit fixed point (ds_add_u64;
 // LDS float atomics are ~20x slower than 64-bit integer ones on gfx950, and
 // integer sums are order-independent, so the spread is deterministic). Each
-// contribution q w_x w_y w_z is scaled by the system's 2^F and rounded to an
-// int32; the tile is converted back to float when stored. FP64 systems
+// contribution q w_x w_y w_z is scaled by the system's 2^F and truncated to an
+// int32 (an error of at most 2^-F per term); the tile is converted back to
+// float when stored. FP64 systems
 // accumulate with ds_add_f64.
 template <typename R> struct SpreadAcc {
     using type = R;
@@ -410,32 +456,33 @@ __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys,
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R(0);
         return;
     }
+    R* ct = reinterpret_cast<R*>(smem_raw + (size_t)E3 * sizeof(A));
+    stage_coef<R, P>(ct, reinterpret_cast<const R*>(S.poly), S.degree);
     for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
     __syncthreads();
-    const R* coef = reinterpret_cast<const R*>(S.poly);
     const int deg = S.degree;
     const R scale = kFixed ? R(S.out[4]) : R(1);
     const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = sorted[k];
-        R wx[P], wy[P], wz[P];
-        const int bx = window<R, P>(v.x, coef, deg, wx) - ox;
-        const int by = window<R, P>(v.y, coef, deg, wy) - oy;
-        const int bz = window<R, P>(v.z, coef, deg, wz) - oz;
+        R w[3][P];
+        int l0[3];
+        windows3<R, P>(v.x, v.y, v.z, ct, deg, w, l0);
+        const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
         const R qs = v.w * scale;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
-            const R qa = qs * wx[a];
+            const R qa = qs * w[0][a];
 #pragma unroll
             for (int b = 0; b < P; ++b) {
-                const R qab = qa * wy[b];
+                const R qab = qa * w[1][b];
                 A* row = lds + ((bx + a) * E + (by + b)) * E + bz;
 #pragma unroll
                 for (int c = 0; c < P; ++c) {
                     if constexpr (kFixed)
-                        atomicAdd(row + c, (A)(long long)__float2int_rn(qab * wz[c]));
+                        atomicAdd(row + c, (A)(long long)__float2int_rz(qab * w[2][c]));
                     else
-                        atomicAdd(row + c, qab * wz[c]);
+                        atomicAdd(row + c, qab * w[2][c]);
                 }
             }
         }
@@ -534,13 +581,14 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
     if (beg == end) return;
     const R* g = reinterpret_cast<const R*>(S.grid);
     const int rl = n + 2;
+    R* ct = reinterpret_cast<R*>(smem_raw + (((size_t)E3 * sizeof(R) + 15) & ~size_t(15)));
+    stage_coef<R, P>(ct, reinterpret_cast<const R*>(S.poly), S.degree);
     for (int i = threadIdx.x; i < E3; i += blockDim.x) {
         const int a = i / (E * E), rem = i - a * E * E, b = rem / E, c = rem - b * E;
         const int gx = wrapi(ox + a, n), gy = wrapi(oy + b, n), gz = wrapi(oz + c, n);
         lds[i] = g[((long long)gx * n + gy) * rl + gz];
     }
     __syncthreads();
-    const R* coef = reinterpret_cast<const R*>(S.poly);
     const int deg = S.degree;
     const R sc = R(S.n) * R(S.inv_L);
     const R s0 = R(S.s0);
@@ -549,10 +597,16 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
     R* F = reinterpret_cast<R*>(S.F);
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = sorted[k];
-        R wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
-        const int bx = window_d<R, P>(v.x, coef, deg, wx, dx) - ox;
-        const int by = window_d<R, P>(v.y, coef, deg, wy, dy) - oy;
-        const int bz = window_d<R, P>(v.z, coef, deg, wz, dz) - oz;
+        R w[3][P], dw[3][P];
+        int l0[3];
+        windows3_d<R, P>(v.x, v.y, v.z, ct, deg, w, dw, l0);
+        const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
+        const R(&wx)[P] = w[0];
+        const R(&wy)[P] = w[1];
+        const R(&wz)[P] = w[2];
+        const R(&dx)[P] = dw[0];
+        const R(&dy)[P] = dw[1];
+        const R(&dz)[P] = dw[2];
         R u = 0, gxs = 0, gys = 0, gzs = 0;
         // outer loop kept rolled: a is uniform across the wavefront, and
         // unrolling all P^3 loads would exhaust the register file
