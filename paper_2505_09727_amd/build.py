@@ -38,6 +38,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = [
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(OUT_DIR, "kernels.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "fft.hip"), "-o", os.path.join(OUT_DIR, "fft.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "runtime.cpp"), "-o", os.path.join(OUT_DIR, "runtime.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "assembly.cpp"), "-o", os.path.join(OUT_DIR, "assembly.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "server.cpp"), "-o", os.path.join(OUT_DIR, "server.o")],

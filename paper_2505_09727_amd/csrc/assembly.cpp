@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 namespace esp {
 
@@ -165,8 +166,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     planes_.clear();
     cols_.clear();
     groups_.clear();
+    fgroups_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
-    int nmax = 0, KBmax = 1, nb_max = 1;
+    int nb_max = 1;
     for (int s = 0; s < nsys; ++s) {
         const SystemSlot& sl = systems[s];
         const esp_params& r = sl.prm;
@@ -208,16 +210,35 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
         nb_max = std::max(nb_max, nb);
         for (int t = 0; t < nb; ++t) titems_by_P[r.P].push_back(make_int2(s, t));
-        for (int x = 0; x < r.nf; ++x) planes_.push_back(make_int2(s, x));
-        const int hs = r.nf / 2 + 1;
-        const int nch = (hs + kMaxColumns - 1) / kMaxColumns;
-        const int KB = (hs + nch - 1) / nch;
-        KBmax = std::max(KBmax, KB);
-        d.col_off = (int)cols_.size();
-        for (int ky = 0; ky < r.nf; ++ky)
-            for (int kz0 = 0; kz0 < hs; kz0 += KB) cols_.push_back(make_int4(s, ky, kz0, std::min(KB, hs - kz0)));
-        d.ncol = (int)cols_.size() - d.col_off;
-        nmax = std::max(nmax, r.nf);
+        if (!fft_size_supported(r.nf)) {
+            msg = "no FFT kernels for this grid size";
+            return ESP_E_UNSUPPORTED;
+        }
+        if (fft_plane_lds(r.nf, prec) > kMaxLds) {
+            msg = "grid too large for the LDS-resident plane FFT at this precision";
+            return ESP_E_UNSUPPORTED;
+        }
+    }
+    // FFT work items grouped by grid size (one launch per size and pass)
+    std::map<int, std::vector<int>> by_n;
+    for (int s = 0; s < nsys; ++s) by_n[hsys_[s].n].push_back(s);
+    const int C = fft_x_columns(prec);
+    for (const auto& kv : by_n) {
+        const int n = kv.first, hs = n / 2 + 1;
+        FftGroup fg{};
+        fg.n = n;
+        fg.plane_off = (int)planes_.size();
+        fg.col_off = (int)cols_.size();
+        for (int s : kv.second) {
+            for (int x = 0; x < n; ++x) planes_.push_back(make_int2(s, x));
+            SysDesc& d = hsys_[s];
+            d.col_off = (int)cols_.size();
+            for (int c0 = 0; c0 < n * hs; c0 += C) cols_.push_back(make_int4(s, c0, std::min(C, n * hs - c0), 0));
+            d.ncol = (int)cols_.size() - d.col_off;
+        }
+        fg.plane_count = (int)planes_.size() - fg.plane_off;
+        fg.col_count = (int)cols_.size() - fg.col_off;
+        fgroups_.push_back(fg);
     }
     for (int P = 4; P <= 12; ++P) {
         if (titems_by_P[P].empty()) continue;
@@ -245,20 +266,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.n_pitems = (int)pitems_.size();
     L_.n_planes = (int)planes_.size();
     L_.n_cols = (int)cols_.size();
-    L_.plane_bd = nmax <= 96 ? 256 : 512;
-    int need = 1;
-    for (const SysDesc& d : hsys_) need = std::max(need, ((d.n / 2 + 1) * (d.n / 2) + L_.plane_bd - 1) / L_.plane_bd);
-    L_.plane_maxit = need;
-    L_.plane_lds = (nmax + nmax * (nmax / 2 + 1)) * 2 * rb + (nmax + 1) * 9 * 4;  // + covering tables
-    int needc = 1;
-    for (const SysDesc& d : hsys_) needc = std::max(needc, (KBmax * d.n / 2 + 255) / 256);
-    L_.col_maxit = needc;
-    L_.col_lds = (nmax + nmax * KBmax) * 2 * rb;
     L_.hist_lds = nb_max * 4;
-    if (L_.plane_maxit > 12 || L_.plane_lds > kMaxLds) {
-        msg = "grid too large for the LDS-resident plane FFT at this precision";
-        return ESP_E_UNSUPPORTED;
-    }
     if (L_.hist_lds > kMaxLds) {
         msg = "too many bins per system; raise tile";
         return ESP_E_UNSUPPORTED;

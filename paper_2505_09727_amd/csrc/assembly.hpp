@@ -85,6 +85,7 @@ class LaunchSet {
     esp_status upload_descriptors(std::string& msg);
     const Launch& launch() const { return L_; }
     const std::vector<Group>& groups() const { return groups_; }
+    const std::vector<FftGroup>& fft_groups() const { return fgroups_; }
     int nsys() const { return (int)hsys_.size(); }
     const SysDesc& desc(int s) const { return hsys_[s]; }
 
@@ -93,6 +94,7 @@ class LaunchSet {
     esp_status put(T** dev, size_t* cap, const std::vector<T>& v, std::string& msg);
     Launch L_{};
     std::vector<Group> groups_;
+    std::vector<FftGroup> fgroups_;
     std::vector<SysDesc> hsys_;
     std::vector<int2> pitems_, titems_, planes_;
     std::vector<int4> cols_;

@@ -55,10 +55,9 @@ struct SysDesc {
 //   particle chunk: (sys, first particle of a 256-chunk)
 //   bin:            (sys, bin index within the system)
 //   plane:          (sys, x)
-//   x-column block: (sys, ky, kz0, width)
+//   x-column block: (sys, first flattened (ky, kz) column, columns, 0)
 
 constexpr int kParticleChunk = 256;
-constexpr int kMaxColumns = 16;
 constexpr int kOutDoubles = 8;
 
 }  // namespace esp

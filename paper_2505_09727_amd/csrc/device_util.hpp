@@ -1,0 +1,143 @@
+// Device helpers shared by the pipeline kernels (kernels.hip) and the 3D FFT
+// kernels (fft.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace esp {
+
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <typename R> struct cplx { R x, y; };
+
+// FFT arithmetic is kept free of fused multiply-adds, so every butterfly
+// rounds the same way whatever code the compiler schedules around it.
+#pragma clang fp contract(off)
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFT butterflies, sign s: y_k = sum_m v_m exp(s 2 pi i m k / RAD)
+template <typename R, int RAD> struct Bfly;
+
+template <typename R> struct Bfly<R, 2> {
+    __device__ __forceinline__ static void run(cplx<R>* v, int) {
+        const cplx<R> a = v[0], b = v[1];
+        v[0] = {a.x + b.x, a.y + b.y};
+        v[1] = {a.x - b.x, a.y - b.y};
+    }
+};
+
+template <typename R> struct Bfly<R, 3> {
+    __device__ __forceinline__ static void run(cplx<R>* v, int s) {
+        const R h = R(0.86602540378443864676) * R(s);
+        const cplx<R> a = v[0], b = v[1], c = v[2];
+        const cplx<R> t1 = {b.x + c.x, b.y + c.y};
+        const cplx<R> t2 = {a.x - R(0.5) * t1.x, a.y - R(0.5) * t1.y};
+        const cplx<R> t3 = {h * (b.x - c.x), h * (b.y - c.y)};
+        v[0] = {a.x + t1.x, a.y + t1.y};
+        v[1] = {t2.x - t3.y, t2.y + t3.x};
+        v[2] = {t2.x + t3.y, t2.y - t3.x};
+    }
+};
+
+template <typename R> struct Bfly<R, 4> {
+    __device__ __forceinline__ static void run(cplx<R>* v, int s) {
+        const cplx<R> a = v[0], b = v[1], c = v[2], d = v[3];
+        const cplx<R> t0 = {a.x + c.x, a.y + c.y}, t1 = {a.x - c.x, a.y - c.y};
+        const cplx<R> t2 = {b.x + d.x, b.y + d.y}, t3 = {b.x - d.x, b.y - d.y};
+        const cplx<R> it3 = s > 0 ? cplx<R>{-t3.y, t3.x} : cplx<R>{t3.y, -t3.x};
+        v[0] = {t0.x + t2.x, t0.y + t2.y};
+        v[2] = {t0.x - t2.x, t0.y - t2.y};
+        v[1] = {t1.x + it3.x, t1.y + it3.y};
+        v[3] = {t1.x - it3.x, t1.y - it3.y};
+    }
+};
+
+#pragma clang fp contract(fast)
+
+// ---------------------------------------------------------------------------
+// Deterministic block sum of a double (fixed tree; blockDim a power of two).
+__device__ inline double block_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) t += red[w];
+    return t;  // valid in thread 0
+}
+
+__device__ inline double block_max(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+    return t;  // valid in thread 0
+}
+
+// The (bin, offset) pairs of one axis whose tiles cover grid index g: bin t's
+// tile starts at t*T + lo (mod n) and spans E points, so g lies at offset
+// o = (g - lo - t*T) mod n (and o + n, o + 2n, ... while below E).
+__device__ __forceinline__ int covering(int g, int lo, int T, int t1, int n, int E, int* tb, int* off) {
+    int gm = (g - lo) % n;
+    if (gm < 0) gm += n;
+    const int tf = gm / T;
+    const int o1 = gm - tf * T;
+    int c = 0;
+    for (int k = 0; o1 + k * T < E && c < 4; ++k) {
+        int tt = (tf - k) % t1;
+        if (tt < 0) tt += t1;
+        tb[c] = tt;
+        off[c] = o1 + k * T;
+        ++c;
+    }
+    return c;
+}
+
+// Covering lists of all n indices of an axis, built once per block in LDS.
+struct CoverTab {
+    int cnt;
+    int bin[4];
+    int off[4];
+};
+
+__device__ __forceinline__ void build_cover(CoverTab* tab, const SysDesc& S, int lo) {
+    for (int g = threadIdx.x; g < S.n; g += blockDim.x) {
+        CoverTab c;
+        c.cnt = covering(g, lo, S.T, S.tiles1, S.n, S.E, c.bin, c.off);
+        tab[g] = c;
+    }
+}
+
+// b_l for one grid point, summed over every bin tile that covers it.
+template <typename R>
+__device__ __forceinline__ R fold_point(const R* __restrict__ tiles, const SysDesc& S, const CoverTab& cx,
+                                        const CoverTab& cy, const CoverTab& cz) {
+    const int t1 = S.tiles1, E = S.E;
+    const long long E3 = (long long)E * E * E;
+    R acc = R(0);
+    for (int a = 0; a < cx.cnt; ++a)
+        for (int b = 0; b < cy.cnt; ++b) {
+            const long long base = ((long long)cx.bin[a] * t1 + cy.bin[b]) * t1 * E3 +
+                                   ((long long)cx.off[a] * E + cy.off[b]) * E;
+            for (int c = 0; c < cz.cnt; ++c) acc += tiles[base + (long long)cz.bin[c] * E3 + cz.off[c]];
+        }
+    return acc;
+}
+
+}  // namespace esp

@@ -1,0 +1,343 @@
+// 3D FFT, influence scaling and k-space energy of the ESP long-range
+// pipeline (Methods, "Fast algorithm for the spectral part": the forward
+// transform of the spread grid, the diagonal scaling by p_k of eq. pk, the
+// inverse transform), for gfx950.
+//
+// Real grids are stored n x n x (n+2): the half spectrum n x n x (n/2+1) of an
+// x-plane overwrites that plane in place. The transform runs as three passes:
+//   fwd_zy  one block per x-plane: real-to-complex along z, complex along y;
+//           with from_tiles the plane is first assembled from the spread's
+//           bin tiles (halo fold);
+//   x       one block per chunk of consecutive (ky, kz) columns: forward
+//           along x, scaling by p_k with the energy partial, inverse along x;
+//   inv_yz  one block per x-plane: inverse along y, complex-to-real along z.
+//
+// Every kernel is instantiated per grid size N (even, 2^a 3^b, 8..144), so the
+// Stockham stages are fully resolved at compile time: radix 4 while 4 divides
+// the remaining length, then 2, then 3. A system's result depends only on its
+// own N (not on the other systems of a launch), and the arithmetic is not
+// contracted into FMAs, so results are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "device_util.hpp"
+#include "kernels.hpp"
+
+namespace esp {
+
+#pragma clang fp contract(off)
+
+// One Stockham autosort stage of radix RAD after NS points have been combined,
+// on NL lines of length N held in LDS; element (line, idx) is at
+// buf[line * LS + idx * ES]. Every thread loads and transforms its butterflies
+// into registers, the block synchronises, then every thread stores, so the
+// stage runs in place. LF maps consecutive threads to consecutive lines.
+template <typename R, int N, int RAD, int NS, int NL, int LS, int ES, int BD, bool LF, int DIR>
+__device__ __forceinline__ void st_stage(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw) {
+    constexpr int NB = N / RAD;
+    constexpr int TOTAL = NL * NB;
+    constexpr int SPAN = N / (NS * RAD);
+    constexpr int IT = (TOTAL + BD - 1) / BD;
+    cplx<R> v[IT][RAD];
+    int dst[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int item = threadIdx.x + it * BD;
+        dst[it] = -1;
+        if (TOTAL % BD == 0 || item < TOTAL) {
+            int line, j;
+            if constexpr (LF) {
+                j = item / NL;
+                line = item - j * NL;
+            } else {
+                line = item / NB;
+                j = item - line * NB;
+            }
+            const cplx<R>* src = buf + line * LS + j * ES;
+            const int jm = j % NS;
+#pragma unroll
+            for (int k = 0; k < RAD; ++k) {
+                cplx<R> a = src[k * NB * ES];
+                if constexpr (NS > 1) {
+                    if (k > 0) {
+                        cplx<R> w = tw[k * jm * SPAN];
+                        if constexpr (DIR < 0) w.y = -w.y;
+                        a = cmul(a, w);
+                    }
+                }
+                v[it][k] = a;
+            }
+            Bfly<R, RAD>::run(v[it], DIR);
+            dst[it] = line * LS + ((j - jm) * RAD + jm) * ES;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        if (dst[it] >= 0) {
+#pragma unroll
+            for (int k = 0; k < RAD; ++k) buf[dst[it] + k * NS * ES] = v[it][k];
+        }
+    }
+    __syncthreads();
+}
+
+// Unnormalised DFT y_k = sum_l exp(DIR 2 pi i k l / N) x_l of NL lines in LDS,
+// natural order in and out; tw[t] = exp(2 pi i t / N).
+template <typename R, int N, int NS, int NL, int LS, int ES, int BD, bool LF, int DIR>
+__device__ __forceinline__ void fft_ct(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw) {
+    if constexpr (NS < N) {
+        constexpr int M = N / NS;
+        constexpr int RAD = M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 3);
+        st_stage<R, N, RAD, NS, NL, LS, ES, BD, LF, DIR>(buf, tw);
+        fft_ct<R, N, NS * RAD, NL, LS, ES, BD, LF, DIR>(buf, tw);
+    }
+}
+
+// Launch shapes, functions of N and the real type only.
+template <int N> constexpr int plane_threads() {
+    constexpr int items = (N / 2 + 1) * (N / 4 > 0 ? N / 4 : 1);
+    return items <= 64 ? 64 : items <= 128 ? 128 : items <= 256 ? 256 : 512;
+}
+template <typename R> constexpr int x_columns() { return 256 / (int)sizeof(cplx<R>); }  // 256-byte row chunks
+template <typename R, int N> constexpr int x_threads() {
+    constexpr int items = x_columns<R>() * (N / 4 > 0 ? N / 4 : 1);
+    return items <= 64 ? 64 : items <= 128 ? 128 : items <= 256 ? 256 : 512;
+}
+
+// Forward pass along z (two real rows transformed as one complex row, then
+// separated) and y, for one x-plane.
+template <typename R, int N>
+__global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __restrict__ sys,
+                                                              const int2* __restrict__ items, int from_tiles) {
+    constexpr int HS = N / 2 + 1, RL = N + 2, HALF = N / 2, BD = plane_threads<N>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + N;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
+    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * N * RL;
+    if (from_tiles) {
+        CoverTab* tab = reinterpret_cast<CoverTab*>(buf + N * HS);
+        build_cover(tab, S, -((S.P - 1) / 2));
+        __syncthreads();
+        const CoverTab cx = tab[wi.y];
+        const R* tiles = reinterpret_cast<const R*>(S.tiles);
+        R* bufr = reinterpret_cast<R*>(buf);
+        for (int idx = threadIdx.x; idx < N * N; idx += BD) {
+            const int y = idx / N, z = idx - y * N;
+            // rows 2r and 2r+1 are the real and imaginary parts of pair-row r
+            bufr[2 * ((y >> 1) * N + z) + (y & 1)] = fold_point(tiles, S, cx, tab[y], tab[z]);
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
+            const int r = idx / N, z = idx - r * N;
+            buf[idx] = {plane[(2 * r) * RL + z], plane[(2 * r + 1) * RL + z]};
+        }
+    }
+    __syncthreads();
+    fft_ct<R, N, 1, HALF, N, 1, BD, false, +1>(buf, tw);
+    {
+        constexpr int TOTAL = HALF * HS, IT = (TOTAL + BD - 1) / BD;
+        cplx<R> A[IT], B[IT];
+        int o[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int item = threadIdx.x + it * BD;
+            o[it] = -1;
+            if (item < TOTAL) {
+                const int r = item / HS, k = item - r * HS;
+                const cplx<R> zk = buf[r * N + k];
+                const cplx<R> zn = buf[r * N + (k == 0 ? 0 : N - k)];
+                A[it] = {R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};
+                B[it] = {R(0.5) * (zk.y + zn.y), -R(0.5) * (zk.x - zn.x)};
+                o[it] = (2 * r) * HS + k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+            if (o[it] >= 0) {
+                buf[o[it]] = A[it];
+                buf[o[it] + HS] = B[it];
+            }
+        __syncthreads();
+    }
+    fft_ct<R, N, 1, HS, 1, HS, BD, true, +1>(buf, tw);
+    cplx<R>* gp = reinterpret_cast<cplx<R>*>(plane);
+    for (int idx = threadIdx.x; idx < N * HS; idx += BD) gp[idx] = buf[idx];
+}
+
+// Inverse pass along y, then complex-to-real along z, for one x-plane.
+template <typename R, int N>
+__global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __restrict__ sys,
+                                                              const int2* __restrict__ items) {
+    constexpr int HS = N / 2 + 1, RL = N + 2, HALF = N / 2, BD = plane_threads<N>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + N;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
+    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * N * RL;
+    const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(plane);
+    for (int idx = threadIdx.x; idx < N * HS; idx += BD) buf[idx] = gp[idx];
+    __syncthreads();
+    fft_ct<R, N, 1, HS, 1, HS, BD, true, -1>(buf, tw);
+    {
+        // rows 2r and 2r+1 (half spectra A, B of two real rows) -> Z = A + iB
+        constexpr int TOTAL = HALF * HS, IT = (TOTAL + BD - 1) / BD;
+        cplx<R> Z[IT], Zc[IT];
+        int o[IT], k_[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int item = threadIdx.x + it * BD;
+            o[it] = -1;
+            if (item < TOTAL) {
+                const int r = item / HS, k = item - r * HS;
+                const cplx<R> a = buf[(2 * r) * HS + k], b = buf[(2 * r + 1) * HS + k];
+                Z[it] = {a.x - b.y, a.y + b.x};
+                Zc[it] = {a.x + b.y, b.x - a.y};
+                o[it] = r * N;
+                k_[it] = k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+            if (o[it] >= 0) {
+                const int k = k_[it];
+                buf[o[it] + k] = Z[it];
+                if (k > 0 && k < HALF) buf[o[it] + N - k] = Zc[it];
+            }
+        __syncthreads();
+    }
+    fft_ct<R, N, 1, HALF, N, 1, BD, false, -1>(buf, tw);
+    for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
+        const int r = idx / N, z = idx - r * N;
+        const cplx<R> v = buf[idx];
+        plane[(2 * r) * RL + z] = v.x;
+        plane[(2 * r + 1) * RL + z] = v.y;
+    }
+}
+
+// Pass along x for C consecutive columns c0 .. c0+cnt-1 of the flattened
+// (ky, kz) index ky * (N/2+1) + kz: forward DFT, scaling by
+// p_k = TS[|m|^2] Tphi[|mx|] Tphi[|my|] Tphi[|mz|] (n/L) (eq. pk) with the
+// k-space energy partial
+//   E_k = 1/2 sum_k p_k |b^_k|^2   (half spectrum: weight 2 off the kz = 0, N/2 planes),
+// then the inverse DFT. mode 1 stops after the forward DFT, mode 2 after the
+// scaling (diagnostics). Each x-row of the chunk is one contiguous run.
+template <typename R, int N>
+__global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __restrict__ sys,
+                                                            const int4* __restrict__ items,
+                                                            double* __restrict__ epart, int mode) {
+    constexpr int HS = N / 2 + 1, HALF = N / 2, C = x_columns<R>(), BD = x_threads<R, N>();
+    constexpr int ROW = N * HS;  // complex values per x-plane
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    const int4 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    const int c0 = wi.y, cnt = wi.z;
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + N;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
+    cplx<R>* gp = reinterpret_cast<cplx<R>*>(S.grid) + c0;
+    for (int idx = threadIdx.x; idx < N * C; idx += BD) {
+        const int x = idx / C, l = idx - x * C;
+        buf[idx] = l < cnt ? gp[(long long)x * ROW + l] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    fft_ct<R, N, 1, C, 1, C, BD, true, +1>(buf, tw);
+    double e = 0.0;
+    if (mode != 1) {
+        const R* TS = reinterpret_cast<const R*>(S.TS);
+        const R* Tp = reinterpret_cast<const R*>(S.Tphi);
+        const R ps = R(S.pscale);
+        for (int idx = threadIdx.x; idx < N * C; idx += BD) {
+            const int x = idx / C, l = idx - x * C;
+            if (l >= cnt) continue;
+            const int col = c0 + l;
+            const int ky = col / HS, kz = col - ky * HS;
+            const int mx = x <= HALF ? x : N - x;
+            const int my = ky <= HALF ? ky : N - ky;
+            const R p = TS[mx * mx + my * my + kz * kz] * Tp[mx] * (Tp[my] * ps) * Tp[kz];
+            const cplx<R> b = buf[idx];
+            const double wgt = (kz == 0 || kz == HALF) ? 1.0 : 2.0;
+            e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);
+            buf[idx] = {b.x * p, b.y * p};
+        }
+        __syncthreads();
+        if (mode == 0) fft_ct<R, N, 1, C, 1, C, BD, true, -1>(buf, tw);
+    }
+    for (int idx = threadIdx.x; idx < N * C; idx += BD) {
+        const int x = idx / C, l = idx - x * C;
+        if (l < cnt) gp[(long long)x * ROW + l] = buf[idx];
+    }
+    const double tot = block_sum(e, red);
+    if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
+}
+
+#pragma clang fp contract(fast)
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+template <typename K>
+static hipError_t allow_lds(K kernel, int bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               bytes);
+}
+
+template <typename R, int N>
+static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode) {
+    hipError_t e;
+    const int lds_plane = fft_plane_lds(N, L.prec);
+    if (which == 0) {
+        if ((e = allow_lds(k_fwd_zy<R, N>, lds_plane)) != hipSuccess) return e;
+        k_fwd_zy<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(L.sys, L.planes + G.plane_off,
+                                                                                   mode == 3 ? 0 : 1);
+    } else if (which == 1) {
+        const int lds = fft_x_lds(N, L.prec);
+        if ((e = allow_lds(k_fft_x<R, N>, lds)) != hipSuccess) return e;
+        k_fft_x<R, N><<<G.col_count, x_threads<R, N>(), lds, L.stream>>>(L.sys, L.cols + G.col_off,
+                                                                         L.epart + G.col_off, mode);
+    } else {
+        if ((e = allow_lds(k_inv_yz<R, N>, lds_plane)) != hipSuccess) return e;
+        k_inv_yz<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(L.sys, L.planes + G.plane_off);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t fft_r(const Launch& L, const FftGroup& G, int which, int mode) {
+    switch (G.n) {
+        case 8: return fft_n<R, 8>(L, G, which, mode);
+        case 12: return fft_n<R, 12>(L, G, which, mode);
+        case 16: return fft_n<R, 16>(L, G, which, mode);
+        case 18: return fft_n<R, 18>(L, G, which, mode);
+        case 24: return fft_n<R, 24>(L, G, which, mode);
+        case 32: return fft_n<R, 32>(L, G, which, mode);
+        case 36: return fft_n<R, 36>(L, G, which, mode);
+        case 48: return fft_n<R, 48>(L, G, which, mode);
+        case 54: return fft_n<R, 54>(L, G, which, mode);
+        case 64: return fft_n<R, 64>(L, G, which, mode);
+        case 72: return fft_n<R, 72>(L, G, which, mode);
+        case 96: return fft_n<R, 96>(L, G, which, mode);
+        case 108: return fft_n<R, 108>(L, G, which, mode);
+        case 128: return fft_n<R, 128>(L, G, which, mode);
+        case 144: return fft_n<R, 144>(L, G, which, mode);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode) {
+    return L.prec == 64 ? fft_r<double>(L, G, which, mode) : fft_r<float>(L, G, which, mode);
+}
+
+}  // namespace esp

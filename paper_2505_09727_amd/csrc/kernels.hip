@@ -14,174 +14,10 @@
 #include <type_traits>
 
 #include "device.hpp"
+#include "device_util.hpp"
 #include "kernels.hpp"
 
 namespace esp {
-
-template <typename R> struct Vec4;
-template <> struct Vec4<float> { using type = float4; };
-template <> struct Vec4<double> { using type = double4; };
-
-template <typename R> struct cplx { R x, y; };
-
-// FFT arithmetic is kept free of fused multiply-adds: the FFT kernels are
-// instantiated for several per-thread work bounds (chosen from the largest
-// grid of a launch), and unfused arithmetic rounds every butterfly the same
-// way in each instantiation, so a system's result does not depend on which
-// other systems share its launch.
-#pragma clang fp contract(off)
-
-template <typename R>
-__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-
-// ---------------------------------------------------------------------------
-// Small DFT butterflies, sign s: y_k = sum_m v_m exp(s 2 pi i m k / RAD)
-template <typename R, int RAD> struct Bfly;
-
-template <typename R> struct Bfly<R, 2> {
-    __device__ __forceinline__ static void run(cplx<R>* v, int) {
-        const cplx<R> a = v[0], b = v[1];
-        v[0] = {a.x + b.x, a.y + b.y};
-        v[1] = {a.x - b.x, a.y - b.y};
-    }
-};
-
-template <typename R> struct Bfly<R, 3> {
-    __device__ __forceinline__ static void run(cplx<R>* v, int s) {
-        const R h = R(0.86602540378443864676) * R(s);
-        const cplx<R> a = v[0], b = v[1], c = v[2];
-        const cplx<R> t1 = {b.x + c.x, b.y + c.y};
-        const cplx<R> t2 = {a.x - R(0.5) * t1.x, a.y - R(0.5) * t1.y};
-        const cplx<R> t3 = {h * (b.x - c.x), h * (b.y - c.y)};
-        v[0] = {a.x + t1.x, a.y + t1.y};
-        v[1] = {t2.x - t3.y, t2.y + t3.x};
-        v[2] = {t2.x + t3.y, t2.y - t3.x};
-    }
-};
-
-template <typename R> struct Bfly<R, 4> {
-    __device__ __forceinline__ static void run(cplx<R>* v, int s) {
-        const cplx<R> a = v[0], b = v[1], c = v[2], d = v[3];
-        const cplx<R> t0 = {a.x + c.x, a.y + c.y}, t1 = {a.x - c.x, a.y - c.y};
-        const cplx<R> t2 = {b.x + d.x, b.y + d.y}, t3 = {b.x - d.x, b.y - d.y};
-        const cplx<R> it3 = s > 0 ? cplx<R>{-t3.y, t3.x} : cplx<R>{t3.y, -t3.x};
-        v[0] = {t0.x + t2.x, t0.y + t2.y};
-        v[2] = {t0.x - t2.x, t0.y - t2.y};
-        v[1] = {t1.x + it3.x, t1.y + it3.y};
-        v[3] = {t1.x - it3.x, t1.y - it3.y};
-    }
-};
-
-// One Stockham autosort stage on `nlines` lines held in LDS; element (line,
-// idx) lives at buf[line*lstride + idx*estride]. All threads of the block take
-// part: every thread first loads and transforms its butterflies into
-// registers, the block synchronises, then every thread stores, so the stage
-// runs in place. MAXIT bounds the number of radix-2 butterflies per thread.
-template <typename R, int RAD, int MAXIT>
-__device__ __forceinline__ void stockham_stage(cplx<R>* buf, int n, int nlines, int lstride, int estride,
-                                               int Ns, const cplx<R>* tw, int s, bool line_fast) {
-    constexpr int IT = (2 * MAXIT + RAD - 1) / RAD;
-    const int nb = n / RAD;
-    const int total = nlines * nb;
-    const int span = n / (Ns * RAD);
-    cplx<R> v[IT][RAD];
-    int dst[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int item = threadIdx.x + it * blockDim.x;
-        dst[it] = -1;
-        if (item < total) {
-            int line, j;
-            if (line_fast) {
-                j = item / nlines;
-                line = item - j * nlines;
-            } else {
-                line = item / nb;
-                j = item - line * nb;
-            }
-            const cplx<R>* src = buf + line * lstride + j * estride;
-            const int jm = j % Ns;
-            const int tstep = jm * span;
-#pragma unroll
-            for (int k = 0; k < RAD; ++k) {
-                cplx<R> a = src[k * nb * estride];
-                if (k > 0) {
-                    cplx<R> w = tw[k * tstep];
-                    if (s < 0) w.y = -w.y;
-                    a = cmul(a, w);
-                }
-                v[it][k] = a;
-            }
-            Bfly<R, RAD>::run(v[it], s);
-            dst[it] = line * lstride + ((j - jm) * RAD + jm) * estride;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        if (dst[it] >= 0) {
-#pragma unroll
-            for (int k = 0; k < RAD; ++k) buf[dst[it] + k * Ns * estride] = v[it][k];
-        }
-    }
-    __syncthreads();
-}
-
-// Unnormalised DFT of length n = 2^a 3^b on many lines in LDS:
-// y_k = sum_l exp(s 2 pi i k l / n) x_l, natural order in and out.
-// tw[t] = exp(2 pi i t / n), t in [0, n).
-template <typename R, int MAXIT>
-__device__ void fft_lines(cplx<R>* buf, int n, int nlines, int lstride, int estride, const cplx<R>* tw,
-                          int s, bool line_fast) {
-    int m = n, Ns = 1;
-    while (m % 4 == 0) {
-        stockham_stage<R, 4, MAXIT>(buf, n, nlines, lstride, estride, Ns, tw, s, line_fast);
-        Ns *= 4;
-        m /= 4;
-    }
-    while (m % 2 == 0) {
-        stockham_stage<R, 2, MAXIT>(buf, n, nlines, lstride, estride, Ns, tw, s, line_fast);
-        Ns *= 2;
-        m /= 2;
-    }
-    while (m % 3 == 0) {
-        stockham_stage<R, 3, MAXIT>(buf, n, nlines, lstride, estride, Ns, tw, s, line_fast);
-        Ns *= 3;
-        m /= 3;
-    }
-}
-
-#pragma clang fp contract(fast)
-
-// ---------------------------------------------------------------------------
-// Deterministic block sum of a double (fixed tree; blockDim a power of two).
-__device__ double block_sum(double v, double* red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    const int nw = (blockDim.x + 63) >> 6;
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < nw; ++w) t += red[w];
-    return t;  // valid in thread 0
-}
-
-__device__ double block_max(double v, double* red) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    const int nw = (blockDim.x + 63) >> 6;
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
-    return t;  // valid in thread 0
-}
 
 // Grid coordinate u in [0, n) of one position component.
 template <typename R>
@@ -496,56 +332,6 @@ __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys,
     }
 }
 
-// The (bin, offset) pairs of one axis whose tiles cover grid index g: bin t's
-// tile starts at t*T + lo (mod n) and spans E points, so g lies at offset
-// o = (g - lo - t*T) mod n (and o + n, o + 2n, ... while below E).
-__device__ __forceinline__ int covering(int g, int lo, int T, int t1, int n, int E, int* tb, int* off) {
-    int gm = (g - lo) % n;
-    if (gm < 0) gm += n;
-    const int tf = gm / T;
-    const int o1 = gm - tf * T;
-    int c = 0;
-    for (int k = 0; o1 + k * T < E && c < 4; ++k) {
-        int tt = (tf - k) % t1;
-        if (tt < 0) tt += t1;
-        tb[c] = tt;
-        off[c] = o1 + k * T;
-        ++c;
-    }
-    return c;
-}
-
-// Covering lists of all n indices of an axis, built once per block in LDS.
-struct CoverTab {
-    int cnt;
-    int bin[4];
-    int off[4];
-};
-
-__device__ __forceinline__ void build_cover(CoverTab* tab, const SysDesc& S, int lo) {
-    for (int g = threadIdx.x; g < S.n; g += blockDim.x) {
-        CoverTab c;
-        c.cnt = covering(g, lo, S.T, S.tiles1, S.n, S.E, c.bin, c.off);
-        tab[g] = c;
-    }
-}
-
-// b_l for one grid point, summed over every bin tile that covers it.
-template <typename R>
-__device__ __forceinline__ R fold_point(const R* __restrict__ tiles, const SysDesc& S, const CoverTab& cx,
-                                        const CoverTab& cy, const CoverTab& cz) {
-    const int t1 = S.tiles1, E = S.E;
-    const long long E3 = (long long)E * E * E;
-    R acc = R(0);
-    for (int a = 0; a < cx.cnt; ++a)
-        for (int b = 0; b < cy.cnt; ++b) {
-            const long long base = ((long long)cx.bin[a] * t1 + cy.bin[b]) * t1 * E3 +
-                                   ((long long)cx.off[a] * E + cy.off[b]) * E;
-            for (int c = 0; c < cz.cnt; ++c) acc += tiles[base + (long long)cz.bin[c] * E3 + cz.off[c]];
-        }
-    return acc;
-}
-
 // Diagnostics: fold the bin tiles into the padded real grid (b_l of eq. spread).
 template <typename R>
 __global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
@@ -642,182 +428,6 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
         }
     }
 }
-
-#pragma clang fp contract(off)
-// ---------------------------------------------------------------------------
-// Forward FFT along z (real-to-complex) and y for one x-plane. Pairs of real
-// rows (2r, 2r+1) are transformed as one complex row and split afterwards.
-// With from_tiles the plane is assembled from the spread's bin tiles
-// (fold_point); otherwise it is read from the real grid.
-template <typename R, int MAXIT>
-__global__ void __launch_bounds__(512) k_fft_fwd_zy(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                    int from_tiles) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int2 wi = items[blockIdx.x];
-    const SysDesc& S = sys[wi.x];
-    const int n = S.n, hs = n / 2 + 1, rl = n + 2, half = n / 2;
-    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* buf = tw + n;
-    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_g[i];
-    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * n * rl;
-    if (from_tiles) {
-        CoverTab* tab = reinterpret_cast<CoverTab*>(buf + n * hs);
-        build_cover(tab, S, -((S.P - 1) / 2));
-        __syncthreads();
-        const CoverTab cx = tab[wi.y];
-        const R* tiles = reinterpret_cast<const R*>(S.tiles);
-        R* bufr = reinterpret_cast<R*>(buf);
-        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-            const int y = idx / n, z = idx - y * n;
-            // rows 2r and 2r+1 are the real and imaginary parts of pair-row r
-            bufr[2 * ((y >> 1) * n + z) + (y & 1)] = fold_point(tiles, S, cx, tab[y], tab[z]);
-        }
-    } else {
-        for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
-            const int r = idx / n, z = idx - r * n;
-            buf[idx] = {plane[(2 * r) * rl + z], plane[(2 * r + 1) * rl + z]};
-        }
-    }
-    __syncthreads();
-    fft_lines<R, MAXIT>(buf, n, half, n, 1, tw, +1, false);
-    {
-        cplx<R> A[MAXIT], B[MAXIT];
-        int o[MAXIT];
-        const int total = half * hs;
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it) {
-            const int item = threadIdx.x + it * blockDim.x;
-            o[it] = -1;
-            if (item < total) {
-                const int r = item / hs, k = item - r * hs;
-                const cplx<R> zk = buf[r * n + k];
-                const cplx<R> zn = buf[r * n + (k == 0 ? 0 : n - k)];
-                A[it] = {R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};
-                B[it] = {R(0.5) * (zk.y + zn.y), -R(0.5) * (zk.x - zn.x)};
-                o[it] = (2 * r) * hs + k;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it)
-            if (o[it] >= 0) {
-                buf[o[it]] = A[it];
-                buf[o[it] + hs] = B[it];
-            }
-        __syncthreads();
-    }
-    fft_lines<R, MAXIT>(buf, n, hs, 1, hs, tw, +1, true);
-    cplx<R>* gp = reinterpret_cast<cplx<R>*>(plane);
-    for (int idx = threadIdx.x; idx < n * hs; idx += blockDim.x) gp[idx] = buf[idx];
-}
-
-// Inverse FFT along y, then complex-to-real along z, for one x-plane.
-template <typename R, int MAXIT>
-__global__ void __launch_bounds__(512) k_fft_inv_yz(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int2 wi = items[blockIdx.x];
-    const SysDesc& S = sys[wi.x];
-    const int n = S.n, hs = n / 2 + 1, rl = n + 2, half = n / 2;
-    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* buf = tw + n;
-    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_g[i];
-    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * n * rl;
-    const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(plane);
-    for (int idx = threadIdx.x; idx < n * hs; idx += blockDim.x) buf[idx] = gp[idx];
-    __syncthreads();
-    fft_lines<R, MAXIT>(buf, n, hs, 1, hs, tw, -1, true);
-    {
-        // rows 2r and 2r+1 (half spectra A, B of two real rows) -> Z = A + iB
-        cplx<R> Z[MAXIT], Zc[MAXIT];
-        int o[MAXIT], k_[MAXIT];
-        const int total = half * hs;
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it) {
-            const int item = threadIdx.x + it * blockDim.x;
-            o[it] = -1;
-            if (item < total) {
-                const int r = item / hs, k = item - r * hs;
-                const cplx<R> a = buf[(2 * r) * hs + k], b = buf[(2 * r + 1) * hs + k];
-                Z[it] = {a.x - b.y, a.y + b.x};
-                Zc[it] = {a.x + b.y, b.x - a.y};
-                o[it] = r * n;
-                k_[it] = k;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < MAXIT; ++it)
-            if (o[it] >= 0) {
-                const int k = k_[it];
-                buf[o[it] + k] = Z[it];
-                if (k > 0 && k < half) buf[o[it] + n - k] = Zc[it];
-            }
-        __syncthreads();
-    }
-    fft_lines<R, MAXIT>(buf, n, half, n, 1, tw, -1, false);
-    for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
-        const int r = idx / n, z = idx - r * n;
-        const cplx<R> v = buf[idx];
-        plane[(2 * r) * rl + z] = v.x;
-        plane[(2 * r + 1) * rl + z] = v.y;
-    }
-}
-
-// FFT along x for a block of kz columns at fixed ky, diagonal scaling by the
-// influence function (eq. pk) with the k-space energy
-//   E_k = 1/2 sum_k p_k |b^_k|^2   (half spectrum, weight 2 off the kz = 0, n/2 planes),
-// then the inverse FFT along x. mode 1 stops after the forward FFT, mode 2
-// after the scaling (diagnostics).
-template <typename R, int MAXIT>
-__global__ void __launch_bounds__(256) k_fft_x(const SysDesc* __restrict__ sys, const int4* __restrict__ items,
-                                               double* __restrict__ epart, int mode) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[16];
-    const int4 wi = items[blockIdx.x];
-    const SysDesc& S = sys[wi.x];
-    const int n = S.n, hs = n / 2 + 1, half = n / 2;
-    const int ky = wi.y, kz0 = wi.z, KB = wi.w;
-    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* buf = tw + n;
-    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = tw_g[i];
-    cplx<R>* gp = reinterpret_cast<cplx<R>*>(S.grid);
-    const int cnt = n * KB;
-    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
-        const int x = idx / KB, l = idx - x * KB;
-        buf[idx] = gp[((long long)x * n + ky) * hs + kz0 + l];
-    }
-    __syncthreads();
-    fft_lines<R, MAXIT>(buf, n, KB, 1, KB, tw, +1, true);
-    double e = 0.0;
-    if (mode != 1) {
-        const R* TS = reinterpret_cast<const R*>(S.TS);
-        const R* Tp = reinterpret_cast<const R*>(S.Tphi);
-        const int my = ky <= half ? ky : n - ky;
-        const R py = Tp[my] * R(S.pscale);
-        for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
-            const int x = idx / KB, l = idx - x * KB, kz = kz0 + l;
-            const int mx = x <= half ? x : n - x;
-            const R p = TS[mx * mx + my * my + kz * kz] * Tp[mx] * py * Tp[kz];
-            const cplx<R> b = buf[idx];
-            const double wgt = (kz == 0 || kz == half) ? 1.0 : 2.0;
-            e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);
-            buf[idx] = {b.x * p, b.y * p};
-        }
-        __syncthreads();
-        if (mode == 0) fft_lines<R, MAXIT>(buf, n, KB, 1, KB, tw, -1, true);
-    }
-    for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
-        const int x = idx / KB, l = idx - x * KB;
-        gp[((long long)x * n + ky) * hs + kz0 + l] = buf[idx];
-    }
-    const double tot = block_sum(e, red);
-    if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
-}
-
-#pragma clang fp contract(fast)
 
 // Energy per system: E = E_k - S(0)/2 sum q^2, plus the charge sums.
 __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
@@ -956,36 +566,6 @@ hipError_t launch_fold(const Launch& L) {
     else
         k_fold<float><<<L.n_planes, 256, 0, L.stream>>>(L.sys, L.planes);
     return hipGetLastError();
-}
-
-template <typename R, int MAXIT>
-static hipError_t fft_t(const Launch& L, int which, int mode) {
-    hipError_t e;
-    if (which == 0) {
-        if ((e = allow_lds(k_fft_fwd_zy<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
-        k_fft_fwd_zy<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes, mode == 3 ? 0 : 1);
-    } else if (which == 1) {
-        if ((e = allow_lds(k_fft_x<R, MAXIT>, L.col_lds)) != hipSuccess) return e;
-        k_fft_x<R, MAXIT><<<L.n_cols, 256, L.col_lds, L.stream>>>(L.sys, L.cols, L.epart, mode);
-    } else {
-        if ((e = allow_lds(k_fft_inv_yz<R, MAXIT>, L.plane_lds)) != hipSuccess) return e;
-        k_fft_inv_yz<R, MAXIT><<<L.n_planes, L.plane_bd, L.plane_lds, L.stream>>>(L.sys, L.planes);
-    }
-    return hipGetLastError();
-}
-
-template <typename R>
-static hipError_t fft_r(const Launch& L, int which, int mode) {
-    const int m = which == 1 ? L.col_maxit : L.plane_maxit;
-    if (m <= 2) return fft_t<R, 2>(L, which, mode);
-    if (m <= 4) return fft_t<R, 4>(L, which, mode);
-    if (m <= 8) return fft_t<R, 8>(L, which, mode);
-    if (m <= 12) return fft_t<R, 12>(L, which, mode);
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_fft(const Launch& L, int which, int mode) {
-    return L.prec == 64 ? fft_r<double>(L, which, mode) : fft_r<float>(L, which, mode);
 }
 
 hipError_t launch_drift(const Launch& L) {

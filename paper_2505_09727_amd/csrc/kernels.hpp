@@ -26,16 +26,41 @@ struct Launch {
     const int2* pitems;   // particle chunks
     int n_pitems;
     const int2* titems;   // bins, grouped by P
-    const int2* planes;   // (sys, x)
+    const int2* planes;   // (sys, x), grouped by grid size
     int n_planes;
-    const int4* cols;     // (sys, ky, kz0, width)
+    const int4* cols;     // (sys, first column, columns, 0), grouped by grid size
     int n_cols;
-    int plane_bd, plane_maxit, plane_lds;
-    int col_maxit, col_lds;
     int hist_lds;         // LDS bytes of the per-chunk histogram
     double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
     double* epart;        // per x-column item: k-space energy partial
 };
+
+// Systems sharing one grid size n: one launch per FFT pass.
+struct FftGroup {
+    int n;
+    int plane_off, plane_count;  // x-plane work items
+    int col_off, col_count;      // x-column chunk work items
+};
+
+// Grid sizes with FFT kernels (even 2^a 3^b up to 144).
+inline bool fft_size_supported(int n) {
+    static const int sizes[] = {8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72, 96, 108, 128, 144};
+    for (int s : sizes)
+        if (s == n) return true;
+    return false;
+}
+// Columns per x-pass block: 256-byte runs of complex values.
+inline int fft_x_columns(int prec) { return prec == 64 ? 16 : 32; }
+// Dynamic LDS bytes of the plane passes (twiddles, one half-spectrum plane,
+// covering tables of the halo fold) and of the x pass.
+inline int fft_plane_lds(int n, int prec) {
+    const int rb = prec == 64 ? 8 : 4;
+    return (n + n * (n / 2 + 1)) * 2 * rb + (n + 1) * 9 * 4;
+}
+inline int fft_x_lds(int n, int prec) {
+    const int rb = prec == 64 ? 8 : 4;
+    return (n + n * fft_x_columns(prec)) * 2 * rb;
+}
 
 // Preparation phases: 0 per-chunk bin histograms, 1 scan, 2 scatter into
 // bin order.
@@ -46,7 +71,7 @@ hipError_t launch_fold(const Launch& L);
 // which: 0 forward z/y planes (mode 3: read the real grid instead of the
 // spread tiles), 1 x-columns with scaling (mode 0 full, 1 forward only,
 // 2 forward + scaling), 2 inverse y/z planes.
-hipError_t launch_fft(const Launch& L, int which, int mode);
+hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode);
 hipError_t launch_gather(const Launch& L, const Group& G);
 hipError_t launch_finalize(const Launch& L, double* E_dev);
 // Serving: apply each system's drift step to its resident FP32 positions.

@@ -178,13 +178,13 @@ esp_status run_phase(esp_plan* p, int ph, double* E_dev, int fft_mode) {
             for (const Group& G : p->ls.groups()) HIP_TRY(launch_spread(L, G));
             break;
         case kFftZY:
-            HIP_TRY(launch_fft(L, 0, fft_mode));
+            for (const FftGroup& G : p->ls.fft_groups()) HIP_TRY(launch_fft(L, G, 0, fft_mode));
             break;
         case kFftX:
-            HIP_TRY(launch_fft(L, 1, fft_mode));
+            for (const FftGroup& G : p->ls.fft_groups()) HIP_TRY(launch_fft(L, G, 1, fft_mode));
             break;
         case kFftYZ:
-            HIP_TRY(launch_fft(L, 2, 0));
+            for (const FftGroup& G : p->ls.fft_groups()) HIP_TRY(launch_fft(L, G, 2, 0));
             break;
         case kGather:
             for (const Group& G : p->ls.groups()) HIP_TRY(launch_gather(L, G));

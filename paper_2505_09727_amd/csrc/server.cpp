@@ -321,9 +321,9 @@ void esp_server::loop() {
         for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) e = launch_prepare(L, ph);
         for (const Group& G : ls.groups())
             if (e == hipSuccess) e = launch_spread(L, G);
-        if (e == hipSuccess) e = launch_fft(L, 0, 0);
-        if (e == hipSuccess) e = launch_fft(L, 1, 0);
-        if (e == hipSuccess) e = launch_fft(L, 2, 0);
+        for (int pass = 0; pass < 3; ++pass)
+            for (const FftGroup& G : ls.fft_groups())
+                if (e == hipSuccess) e = launch_fft(L, G, pass, 0);
         for (const Group& G : ls.groups())
             if (e == hipSuccess) e = launch_gather(L, G);
         if (e == hipSuccess) e = launch_finalize(L, nullptr);

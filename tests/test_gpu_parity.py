@@ -5,6 +5,7 @@ rounding; spread/gather/end-to-end against the reference five-step method
 (exact window, matrix DFT) and, for the paper's error measure, against
 classical Ewald minus the local part, to the configured force tolerance
 (relative RMS, eq. Deltadef)."""
+import functools
 import math
 
 import numpy as np
@@ -56,11 +57,26 @@ def _spectrum(buf, n):
 
 # ---------------------------------------------------------------- FFT stages
 
+@functools.lru_cache(maxsize=None)
+def _influence(n, L, P, c, rc, c1):
+    return influence(n, L, P, c, rc, c1)
+
+
+FFT_SIZES = [8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72, 96, 108, 128, 144]
+
+
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("n", [8, 16, 18, 24, 32, 36, 48, 96])
+@pytest.mark.parametrize("n", FFT_SIZES)
 def test_fft_stages_match_textbook_dft(n, prec):
+    """Every grid size with FFT kernels: forward transform, scaling and inverse
+    against the textbook DFT of the reference (one system, real grid input)."""
     rng = np.random.default_rng(n)
     L = 1.25 * n
+    if prec == 64 and n == 144:
+        # one FP64 half-spectrum plane of 144 x 73 exceeds the 160 KB LDS
+        with pytest.raises(EspError):
+            Plan(L, 2, 1e-4, nf=n, precision=prec, P=6)
+        return
     plan = Plan(L, 2, 1e-4, nf=n, precision=prec, P=min(6, n))
     b = np.zeros((n, n, n + 2))
     b[:, :, :n] = rng.standard_normal((n, n, n))
@@ -76,7 +92,7 @@ def test_fft_stages_match_textbook_dft(n, prec):
     # are computed independently in FP64 and agree to ~1e-11)
     tol = max(tol, 1e-9)
     p = plan.params[0]
-    pk = influence(n, L, p.P, p.c, p.rc, p.c1)
+    pk = _influence(n, L, p.P, p.c, p.rc, p.c1)
     plan.debug_stage(None, None, 3, out, grid_in=gin)
     chat = (pk * bhat)[:, :, :n // 2 + 1]
     assert np.max(np.abs(_spectrum(out, n) - chat)) < tol * np.max(np.abs(chat))
