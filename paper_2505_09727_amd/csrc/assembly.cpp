@@ -89,6 +89,14 @@ int choose_tile(int n, int requested, long long target) {
     return smallest ? smallest : n;
 }
 
+// The tile buffer also stages the scatter's output (particles in bin order
+// and their caller indices) before the dealing pass writes the final order;
+// the tiles are written later, by the spread.
+size_t tiles_region(size_t tile_bytes, int64_t N, size_t rb) {
+    const size_t stage = align256(N * 4 * rb) + align256(N * 4);
+    return align256(std::max(tile_bytes, stage));
+}
+
 size_t scratch_bytes(const esp_params& p, int64_t N) {
     const size_t rb = p.precision == 64 ? 8 : 4;
     const size_t nb = nbins(p), E = tile_edge(p), n = p.nf;
@@ -99,7 +107,7 @@ size_t scratch_bytes(const esp_params& p, int64_t N) {
     s += align256(nb * npitems(N) * 4);          // hist
     s += align256((nb + 1) * 4);                 // bin_start
     s += align256(n * n * (n + 2) * rb);         // grid
-    s += align256(nb * E * E * E * rb);          // tiles
+    s += tiles_region(nb * E * E * E * rb, N, rb);  // tiles / staging of the scatter
     s += align256(kOutDoubles * 8);              // out
     return s;
 }
@@ -122,7 +130,7 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
     s.grid = base + o;
     o += align256(n * n * (n + 2) * rb);
     s.tiles = base + o;
-    o += align256(nb * E * E * E * rb);
+    o += tiles_region(nb * E * E * E * rb, N, rb);
     s.out = reinterpret_cast<double*>(base + o);
     return s;
 }
@@ -249,8 +257,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         int E = 0;
         for (const int2& it : titems_by_P[P]) E = std::max(E, hsys_[it.x].E);
         // 64-bit accumulators (fixed point or double) / the potential tile,
-        // then the window coefficients (P x (degree + 1) reals, degree <= 16)
-        const int coef_bytes = 12 * 17 * 8;
+        // then the window coefficients and their derivatives (2 x P x 17
+        // reals at most: degree <= 16)
+        const int coef_bytes = 2 * 12 * 17 * 8;
         g.lds_spread = E * E * E * 8 + coef_bytes;
         g.lds_gather = ((E * E * E * rb + 15) & ~15) + coef_bytes;
         if (g.lds_spread > kMaxLds) {
@@ -264,6 +273,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.nsys = nsys;
     L_.stream = stream;
     L_.n_pitems = (int)pitems_.size();
+    L_.n_titems = (int)titems_.size();
     L_.n_planes = (int)planes_.size();
     L_.n_cols = (int)cols_.size();
     L_.hist_lds = nb_max * 4;

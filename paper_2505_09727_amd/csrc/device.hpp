@@ -43,7 +43,8 @@ struct SysDesc {
     int* hist;        // nbins x npitem counts, then offsets
     int* bin_start;   // nbins + 1
     void* grid;       // n x n x (n + 2) reals (half spectrum in place)
-    void* tiles;      // nbins x E^3 reals
+    void* tiles;      // nbins x E^3 reals; before the spread, the scatter's staging
+                      // (N 4-vectors, then N ints at the next 256-byte boundary)
     double* out;      // 8 doubles: E, sum q, sum |q|, sum q^2, fixed-point scale
     // serving: per-step drift of the resident positions (k_drift)
     unsigned long long seed;  // drift stream of the request
@@ -52,12 +53,13 @@ struct SysDesc {
 };
 
 // Work items: .x = system index in the launch, .y (.z, .w) = position inside it.
-//   particle chunk: (sys, first particle of a 256-chunk)
+//   particle chunk: (sys, first particle of a chunk of kParticleChunk)
 //   bin:            (sys, bin index within the system)
 //   plane:          (sys, x)
 //   x-column block: (sys, first flattened (ky, kz) column, columns, 0)
 
-constexpr int kParticleChunk = 256;
+constexpr int kParticleChunk = 1024;  // particles per chunk work item
+constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
 constexpr int kOutDoubles = 8;
 
 }  // namespace esp

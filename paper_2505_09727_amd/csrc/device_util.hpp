@@ -90,6 +90,37 @@ __device__ inline double block_max(double v, double* red) {
     return t;  // valid in thread 0
 }
 
+// Block reduction of three sums and one maximum (fixed tree, so the result
+// does not depend on timing; blockDim a multiple of 64, at most 1024).
+// red holds 64 doubles. Results valid in thread 0.
+__device__ inline void block_sum3_max(double& a, double& b, double& c, double& m, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+        c += __shfl_down(c, off, 64);
+        m = fmax(m, __shfl_down(m, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[4 * wid + 0] = a;
+        red[4 * wid + 1] = b;
+        red[4 * wid + 2] = c;
+        red[4 * wid + 3] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        a = b = c = m = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            a += red[4 * w + 0];
+            b += red[4 * w + 1];
+            c += red[4 * w + 2];
+            m = fmax(m, red[4 * w + 3]);
+        }
+    }
+}
+
 // The (bin, offset) pairs of one axis whose tiles cover grid index g: bin t's
 // tile starts at t*T + lo (mod n) and spans E points, so g lies at offset
 // o = (g - lo - t*T) mod n (and o + n, o + 2n, ... while below E).

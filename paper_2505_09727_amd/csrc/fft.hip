@@ -105,6 +105,56 @@ template <typename R, int N> constexpr int x_threads() {
     return items <= 64 ? 64 : items <= 128 ? 128 : items <= 256 ? 256 : 512;
 }
 
+// Assemble grid plane x from the spread's bin tiles (the halo fold): every
+// point sums the tile entries that cover it, at most 3 per axis (a tile spans
+// E = T + P - 1 + (P odd) <= T + 12 points and T >= 8). The loads of PG points
+// per thread are all issued before any is summed. The result goes to LDS in
+// pair-row order: rows 2r and 2r+1 are the real and imaginary parts of
+// complex row r.
+template <typename R, int N, int BD>
+__device__ __forceinline__ void fold_plane(R* __restrict__ bufr, const R* __restrict__ tiles, const SysDesc& S,
+                                           const CoverTab* __restrict__ tab, const CoverTab& cx) {
+    constexpr int NP = N * N, PG = 4;
+    const int t1 = S.tiles1, E = S.E, EE = E * E, E3 = EE * E;
+    for (int p0 = 0; p0 < NP; p0 += PG * BD) {
+        R acc[PG];
+#pragma unroll
+        for (int q = 0; q < PG; ++q) acc[q] = R(0);
+        for (int a = 0; a < cx.cnt; ++a) {
+            const R* ta = tiles + cx.bin[a] * t1 * t1 * E3 + cx.off[a] * EE;
+            R v[PG][3][3];
+#pragma unroll
+            for (int q = 0; q < PG; ++q) {
+                const int idx = p0 + q * BD + (int)threadIdx.x;
+                const bool ok = (NP % (PG * BD) == 0) || idx < NP;
+                const int y = ok ? idx / N : 0, z = ok ? idx - (idx / N) * N : 0;
+                const CoverTab cy = tab[y], cz = tab[z];
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        v[q][b][c] = (ok && b < cy.cnt && c < cz.cnt)
+                                         ? ta[(cy.bin[b] * t1 + cz.bin[c]) * E3 + cy.off[b] * E + cz.off[c]]
+                                         : R(0);
+            }
+#pragma unroll
+            for (int q = 0; q < PG; ++q)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[q] += v[q][b][c];
+        }
+#pragma unroll
+        for (int q = 0; q < PG; ++q) {
+            const int idx = p0 + q * BD + (int)threadIdx.x;
+            if ((NP % (PG * BD) == 0) || idx < NP) {
+                const int y = idx / N, z = idx - y * N;
+                bufr[2 * ((y >> 1) * N + z) + (y & 1)] = acc[q];
+            }
+        }
+    }
+}
+
 // Forward pass along z (two real rows transformed as one complex row, then
 // separated) and y, for one x-plane.
 template <typename R, int N>
@@ -123,14 +173,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __
         CoverTab* tab = reinterpret_cast<CoverTab*>(buf + N * HS);
         build_cover(tab, S, -((S.P - 1) / 2));
         __syncthreads();
-        const CoverTab cx = tab[wi.y];
-        const R* tiles = reinterpret_cast<const R*>(S.tiles);
-        R* bufr = reinterpret_cast<R*>(buf);
-        for (int idx = threadIdx.x; idx < N * N; idx += BD) {
-            const int y = idx / N, z = idx - y * N;
-            // rows 2r and 2r+1 are the real and imaginary parts of pair-row r
-            bufr[2 * ((y >> 1) * N + z) + (y & 1)] = fold_point(tiles, S, cx, tab[y], tab[z]);
-        }
+        fold_plane<R, N, BD>(reinterpret_cast<R*>(buf), reinterpret_cast<const R*>(S.tiles), S, tab, tab[wi.y]);
     } else {
         for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
             const int r = idx / N, z = idx - r * N;

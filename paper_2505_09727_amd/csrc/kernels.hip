@@ -41,48 +41,50 @@ __device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
 // ---------------------------------------------------------------------------
 // Binning without global atomics.
 //
-// k_hist: one block per chunk of 256 particles of one system. Grid
+// k_hist: one block per chunk of kParticleChunk particles of one system. Grid
 // coordinates, bin id, and the rank of the particle among the chunk's
 // particles of the same bin (LDS atomics); the chunk's bin counts go to column
 // `item` of the system's bin-major count matrix (plain stores). Also the chunk
 // sums of q, |q|, q^2 and max |q| (neutrality check, self energy, fixed-point
 // range of the spread).
 template <typename R>
-__global__ void __launch_bounds__(256) k_hist(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                              double* __restrict__ bpart) {
+__global__ void __launch_bounds__(kChunkThreads) k_hist(const SysDesc* __restrict__ sys,
+                                                        const int2* __restrict__ items, double* __restrict__ bpart) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int* cnt = reinterpret_cast<int*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[64];
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
     const int n = S.n, t1 = S.tiles1, nb = t1 * t1 * t1;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[b] = 0;
+    for (int b = threadIdx.x; b < nb; b += kChunkThreads) cnt[b] = 0;
     __syncthreads();
-    const int il = wi.y + threadIdx.x;
-    double sq = 0.0, sa = 0.0, s2 = 0.0;
-    if (il < S.N) {
-        const R* pos = reinterpret_cast<const R*>(S.pos);
-        const R inv_L = R(S.inv_L);
-        const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
-        const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
-        const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
-        S.rank[il] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
-        const double qq = (double)reinterpret_cast<const R*>(S.q)[il];
-        sq = qq;
-        sa = fabs(qq);
-        s2 = qq * qq;
+    double sq = 0.0, sa = 0.0, s2 = 0.0, qm = 0.0;
+    const R* pos = reinterpret_cast<const R*>(S.pos);
+    const R* q = reinterpret_cast<const R*>(S.q);
+    const R inv_L = R(S.inv_L);
+#pragma unroll
+    for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
+        const int il = wi.y + threadIdx.x + k * kChunkThreads;
+        if (il < S.N) {
+            const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
+            const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
+            const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
+            S.rank[il] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
+            const double qq = (double)q[il];
+            sq += qq;
+            sa += fabs(qq);
+            s2 += qq * qq;
+            qm = fmax(qm, fabs(qq));
+        }
     }
     __syncthreads();
     const int it = blockIdx.x - S.pitem_off;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) S.hist[b * S.npitem + it] = cnt[b];
-    const double qm = block_max(sa, red);
-    const double t0 = block_sum(sq, red);
-    const double t1s = block_sum(sa, red);
-    const double t2 = block_sum(s2, red);
+    for (int b = threadIdx.x; b < nb; b += kChunkThreads) S.hist[b * S.npitem + it] = cnt[b];
+    block_sum3_max(sq, sa, s2, qm, red);
     if (threadIdx.x == 0) {
-        bpart[4 * blockIdx.x + 0] = t0;
-        bpart[4 * blockIdx.x + 1] = t1s;
-        bpart[4 * blockIdx.x + 2] = t2;
+        bpart[4 * blockIdx.x + 0] = sq;
+        bpart[4 * blockIdx.x + 1] = sa;
+        bpart[4 * blockIdx.x + 2] = s2;
         bpart[4 * blockIdx.x + 3] = qm;
     }
 }
@@ -138,118 +140,281 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
     if (threadIdx.x == 0) S.bin_start[nb] = S.N;
 }
 
-// Scatter particles into bin order as (u_x, u_y, u_z, q) and record the
-// permutation back to the caller's order.
+// Staging of the scatter's output in the tile buffer (the tiles are written
+// later, by the spread).
 template <typename R>
-__global__ void __launch_bounds__(256) k_scatter(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+__device__ __forceinline__ typename Vec4<R>::type* stage_vals(const SysDesc& S) {
+    return reinterpret_cast<typename Vec4<R>::type*>(S.tiles);
+}
+template <typename R>
+__device__ __forceinline__ int* stage_perm(const SysDesc& S) {
+    const size_t off = ((size_t)S.N * sizeof(typename Vec4<R>::type) + 255) & ~size_t(255);
+    return reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(S.tiles) + off);
+}
+
+// Scatter particles into bin order as (u_x, u_y, u_z, q) with their caller
+// indices, into the staging area; the dealing pass writes the final order.
+template <typename R>
+__global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __restrict__ sys,
+                                                           const int2* __restrict__ items) {
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
-    const int il = wi.y + threadIdx.x;
-    if (il >= S.N) return;
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R inv_L = R(S.inv_L);
     const int n = S.n;
-    const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
-    const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
-    const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
-    const int b = bin_of(ux, uy, uz, S);
-    const int dst = S.hist[b * S.npitem + (blockIdx.x - S.pitem_off)] + S.rank[il];
-    typename Vec4<R>::type v;
-    v.x = ux;
-    v.y = uy;
-    v.z = uz;
-    v.w = reinterpret_cast<const R*>(S.q)[il];
-    reinterpret_cast<typename Vec4<R>::type*>(S.sorted)[dst] = v;
-    S.perm[dst] = il;
+    const int* hcol = S.hist + (blockIdx.x - S.pitem_off);
+#pragma unroll
+    for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
+        const int il = wi.y + threadIdx.x + k * kChunkThreads;
+        if (il < S.N) {
+            const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
+            const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
+            const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
+            const int dst = hcol[bin_of(ux, uy, uz, S) * S.npitem] + S.rank[il];
+            typename Vec4<R>::type v;
+            v.x = ux;
+            v.y = uy;
+            v.z = uz;
+            v.w = reinterpret_cast<const R*>(S.q)[il];
+            stage_vals<R>(S)[dst] = v;
+            stage_perm<R>(S)[dst] = il;
+        }
+    }
+}
+
+// Dealing: write the particles of each bin from the staging area to the
+// sorted arrays in an order where consecutive particles fall in distinct LDS
+// bank classes. A particle's class is the linear index, in its bin's E^3
+// tile, of the first entry of its window, mod 32; every tile access of the
+// spread and the gather is that index plus an offset common to all
+// particles, so lanes holding particles of distinct classes hit distinct
+// banks on every access. The order lists round j = 0, 1, ... where round j
+// holds the j-th staged particle of every class that has one, in class order.
+// Any order within a bin gives the same results; a bin whose largest class
+// exceeds kDealRounds keeps the staged order.
+constexpr int kDealRounds = 1024;
+constexpr int kDealRegs = 8;  // staged particles per thread held in registers
+
+template <typename R>
+__device__ __forceinline__ int deal_class(const typename Vec4<R>::type& v, R hp, int ox, int oy, int oz, int E) {
+    const int bx = (int)floor(v.x - hp) + 1 - ox;
+    const int by = (int)floor(v.y - hp) + 1 - oy;
+    const int bz = (int)floor(v.z - hp) + 1 - oz;
+    return ((bx * E + by) * E + bz) & 31;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_deal(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+    using V = typename Vec4<R>::type;
+    constexpr int BD = 256;
+    __shared__ int start[kDealRounds];        // first slot of round j
+    __shared__ unsigned mask[kDealRounds];    // classes present in round j
+    __shared__ int cnt[32];
+    __shared__ int maxc_s;
+    const int2 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    const int t = wi.y, T = S.T, t1 = S.tiles1, E = S.E;
+    const int beg = S.bin_start[t], count = S.bin_start[t + 1] - beg;
+    if (count == 0) return;  // uniform over the block
+    const V* src = stage_vals<R>(S) + beg;
+    const int* srcp = stage_perm<R>(S) + beg;
+    V* dst = reinterpret_cast<V*>(S.sorted) + beg;
+    int* dstp = S.perm + beg;
+    int* key = S.rank + beg;  // free after the scatter; keys beyond the registers
+    const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+    const int lo = -((S.P - 1) / 2);
+    const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
+    const R hp = R(0.5) * R(S.P);
+    if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    // key = class << 16 | rank of the particle within its class
+    V vr[kDealRegs];
+    int pr[kDealRegs], kr[kDealRegs];
+#pragma unroll
+    for (int k = 0; k < kDealRegs; ++k) {
+        const int i = threadIdx.x + k * BD;
+        if (i < count) {
+            vr[k] = src[i];
+            pr[k] = srcp[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kDealRegs; ++k) {
+        const int i = threadIdx.x + k * BD;
+        if (i < count) {
+            const int c = deal_class<R>(vr[k], hp, ox, oy, oz, E);
+            kr[k] = (c << 16) | atomicAdd(&cnt[c], 1);
+        }
+    }
+    for (int i = threadIdx.x + kDealRegs * BD; i < count; i += BD) {
+        const int c = deal_class<R>(src[i], hp, ox, oy, oz, E);
+        key[i] = (c << 16) | atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    // one wave: largest class, then per round the mask of classes present and
+    // the first slot (running sum of the round sizes)
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int cl = lane < 32 ? cnt[lane] : 0;
+        int m = cl;
+        for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+        if (lane == 0) maxc_s = m;
+        if (m <= kDealRounds) {
+            int run = 0;
+            for (int j = 0; j < m; ++j) {
+                const unsigned b = (unsigned)__ballot(cl > j);
+                if (lane == 0) {
+                    mask[j] = b;
+                    start[j] = run;
+                }
+                run += __popc(b);
+            }
+        }
+    }
+    __syncthreads();
+    const int maxc = maxc_s;
+    const bool deal = maxc <= kDealRounds;  // else keep the staged order
+#pragma unroll
+    for (int k = 0; k < kDealRegs; ++k) {
+        const int i = threadIdx.x + k * BD;
+        if (i < count) {
+            int pos = i;
+            if (deal) {
+                const int c = kr[k] >> 16, r = kr[k] & 0xFFFF;
+                pos = start[r] + __popc(mask[r] & ((1u << c) - 1u));
+            }
+            dst[pos] = vr[k];
+            dstp[pos] = pr[k];
+        }
+    }
+    for (int i = threadIdx.x + kDealRegs * BD; i < count; i += BD) {
+        int pos = i;
+        if (deal) {
+            const int kk = key[i], c = kk >> 16, r = kk & 0xFFFF;
+            pos = start[r] + __popc(mask[r] & ((1u << c) - 1u));
+        }
+        dst[pos] = src[i];
+        dstp[pos] = srcp[i];
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Window weights of one axis by Horner in y in [-1/2, 1/2): the P polynomial
-// pieces of psi^{c1}(2 (u - l)/P) for l = l0 .. l0+P-1, l0 = floor(u - P/2) + 1.
 // Window polynomial coefficients of one system staged in LDS, transposed so
 // the P coefficients of one power of y are contiguous: ct[m * P + j]. The
-// global table holds coef[j * (deg + 1) + m] (window piece j, power m).
+// global table holds coef[j * (deg + 1) + m] (window piece j, power m). With
+// ctd != nullptr the derivative coefficients (m + 1) c[m + 1][j] go to
+// ctd[m * P + j] for m < deg, and row deg of ctd is zero.
 template <typename R, int P>
-__device__ __forceinline__ void stage_coef(R* __restrict__ ct, const R* __restrict__ coef, int deg) {
+__device__ __forceinline__ void stage_coef(R* __restrict__ ct, R* __restrict__ ctd, const R* __restrict__ coef,
+                                           int deg) {
     const int d1 = deg + 1;
     for (int i = threadIdx.x; i < P * d1; i += blockDim.x) {
         const int j = i / d1, m = i - j * d1;
         ct[m * P + j] = coef[i];
+        if (ctd) ctd[(m > 0 ? m - 1 : deg) * P + j] = m > 0 ? R(m) * coef[i] : R(0);  // row deg is zero
     }
 }
 
-// Window weights of the three axes of one particle (eq. spread): the P pieces
-// of the polynomial window at y = frac(u - P/2) - 1/2, evaluated by Horner's
-// rule for all three axes at once so each power's coefficients are read from
-// LDS once. l0[a] is the first grid index of axis a's support.
+// Window weights of the three axes of one particle (eq. spread): the P
+// polynomial pieces at y = frac(u - P/2) - 1/2 (|y| <= 1/2), summed as
+// sum_m c[m][j] y^m with a running power of y, so every term is one
+// accumulate and each power's coefficients are read from LDS once for all
+// three axes. Weights are clamped at zero (the window is positive on its
+// support; the clamp only removes rounding noise at the support's edge).
+// l0[a] is the first grid index of axis a's support.
 template <typename R, int P>
 __device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__ ct, int deg, R (&w)[3][P],
                                          int (&l0)[3]) {
     const R hp = R(0.5) * R(P);
     const R u[3] = {ux, uy, uz};
-    R y[3];
+    R y[3], yp[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const R f = floor(u[a] - hp);
         y[a] = (u[a] - hp) - f - R(0.5);
         l0[a] = (int)f + 1;
+        yp[a] = y[a];
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        const R c = ct[deg * P + j];
+        const R c = ct[j];
 #pragma unroll
         for (int a = 0; a < 3; ++a) w[a][j] = c;
     }
-    for (int m = deg - 1; m >= 0; --m) {
+    for (int m = 1; m <= deg; ++m) {
         R c[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) c[j] = ct[m * P + j];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
 #pragma unroll
-            for (int j = 0; j < P; ++j) w[a][j] = w[a][j] * y[a] + c[j];
+            for (int j = 0; j < P; ++j) w[a][j] += c[j] * yp[a];
+            yp[a] *= y[a];
+        }
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < P; ++j) w[a][j] = fmax(w[a][j], R(0));
 }
 
-// As windows3, with the derivatives d w / d y (= d w / d u).
+// As windows3, with the derivatives d w / d u from the staged derivative
+// coefficients ctd (sum_m (m + 1) c[m + 1][j] y^m).
 template <typename R, int P>
-__device__ __forceinline__ void windows3_d(R ux, R uy, R uz, const R* __restrict__ ct, int deg, R (&w)[3][P],
-                                           R (&dw)[3][P], int (&l0)[3]) {
+__device__ __forceinline__ void windows3_d(R ux, R uy, R uz, const R* __restrict__ ct, const R* __restrict__ ctd,
+                                           int deg, R (&w)[3][P], R (&dw)[3][P], int (&l0)[3]) {
     const R hp = R(0.5) * R(P);
     const R u[3] = {ux, uy, uz};
-    R y[3];
+    R y[3], yp[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const R f = floor(u[a] - hp);
         y[a] = (u[a] - hp) - f - R(0.5);
         l0[a] = (int)f + 1;
+        yp[a] = y[a];
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        const R c = ct[deg * P + j];
+        const R c = ct[j], d = ctd[j];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             w[a][j] = c;
-            dw[a][j] = R(0);
+            dw[a][j] = d;
         }
     }
-    for (int m = deg - 1; m >= 0; --m) {
-        R c[P];
+    for (int m = 1; m <= deg; ++m) {
+        R c[P], d[P];
 #pragma unroll
-        for (int j = 0; j < P; ++j) c[j] = ct[m * P + j];
+        for (int j = 0; j < P; ++j) {
+            c[j] = ct[m * P + j];
+            d[j] = ctd[m * P + j];
+        }
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-                dw[a][j] = dw[a][j] * y[a] + w[a][j];
-                w[a][j] = w[a][j] * y[a] + c[j];
+                w[a][j] += c[j] * yp[a];
+                dw[a][j] += d[j] * yp[a];
             }
+            yp[a] *= y[a];
+        }
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < P; ++j) w[a][j] = fmax(w[a][j], R(0));
 }
 
 __device__ __forceinline__ int wrapi(int g, int n) {
     g %= n;
     return g < 0 ? g + n : g;
+}
+
+// Periodic index for -n <= g < 2n (tile origins and offsets: a tile starts at
+// most 6 points before 0 and spans at most T + 12 <= n + 12 points, n >= 8).
+__device__ __forceinline__ int wrap_near(int g, int n) {
+    g += g < 0 ? n : 0;
+    return g >= n ? g - n : g;
 }
 
 // Spread (eq. spread): one block per bin of T^3 grid cells. The block
@@ -262,9 +427,9 @@ __device__ __forceinline__ int wrapi(int g, int n) {
 // LDS accumulator: FP32 systems accumulate in 64-bit fixed point (ds_add_u64;
 // LDS float atomics are ~20x slower than 64-bit integer ones on gfx950, and
 // integer sums are order-independent, so the spread is deterministic). Each
-// contribution q w_x w_y w_z is scaled by the system's 2^F and truncated to an
-// int32 (an error of at most 2^-F per term); the tile is converted back to
-// float when stored. FP64 systems
+// contribution q w_x w_y w_z is scaled by the system's 2^F and converted to
+// an int32 (an error of at most one unit 2^-F per term); the tile is converted
+// back to float when stored. FP64 systems
 // accumulate with ds_add_f64.
 template <typename R> struct SpreadAcc {
     using type = R;
@@ -293,7 +458,7 @@ __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys,
         return;
     }
     R* ct = reinterpret_cast<R*>(smem_raw + (size_t)E3 * sizeof(A));
-    stage_coef<R, P>(ct, reinterpret_cast<const R*>(S.poly), S.degree);
+    stage_coef<R, P>(ct, nullptr, reinterpret_cast<const R*>(S.poly), S.degree);
     for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
     __syncthreads();
     const int deg = S.degree;
@@ -306,6 +471,14 @@ __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys,
         windows3<R, P>(v.x, v.y, v.z, ct, deg, w, l0);
         const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
         const R qs = v.w * scale;
+        // fixed point: every term of a particle has the sign of its charge
+        // (weights >= 0), so the high word of the 64-bit addend is that sign
+        // and the low word is the term truncated toward zero, shifted by -1 for
+        // negative charges so that it is never 0 there (a bias below one unit
+        // 2^-F per term)
+        const bool neg = v.w < R(0);
+        const R shift = neg ? R(-1) : R(0);
+        const unsigned long long hi = neg ? 0xFFFFFFFF00000000ull : 0ull;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
             const R qa = qs * w[0][a];
@@ -316,7 +489,7 @@ __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys,
 #pragma unroll
                 for (int c = 0; c < P; ++c) {
                     if constexpr (kFixed)
-                        atomicAdd(row + c, (A)(long long)__float2int_rz(qab * w[2][c]));
+                        atomicAdd(row + c, (A)(hi | (unsigned)(int)(qab * w[2][c] + shift)));
                     else
                         atomicAdd(row + c, qab * w[2][c]);
                 }
@@ -326,7 +499,7 @@ __global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys,
     __syncthreads();
     if constexpr (kFixed) {
         const R inv = R(1) / scale;
-        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((long long)lds[i]) * inv;
+        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((double)(long long)lds[i] * (double)inv);
     } else {
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = lds[i];
     }
@@ -368,11 +541,26 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
     const R* g = reinterpret_cast<const R*>(S.grid);
     const int rl = n + 2;
     R* ct = reinterpret_cast<R*>(smem_raw + (((size_t)E3 * sizeof(R) + 15) & ~size_t(15)));
-    stage_coef<R, P>(ct, reinterpret_cast<const R*>(S.poly), S.degree);
-    for (int i = threadIdx.x; i < E3; i += blockDim.x) {
-        const int a = i / (E * E), rem = i - a * E * E, b = rem / E, c = rem - b * E;
-        const int gx = wrapi(ox + a, n), gy = wrapi(oy + b, n), gz = wrapi(oz + c, n);
-        lds[i] = g[((long long)gx * n + gy) * rl + gz];
+    R* ctd = ct + 17 * P;
+    stage_coef<R, P>(ct, ctd, reinterpret_cast<const R*>(S.poly), S.degree);
+    {
+        // 32-lane groups walk the E^2 rows of the tile, lane c < E loads
+        // element c of a row (E <= 28)
+        const int c = threadIdx.x & 31;
+        const int gz = wrap_near(oz + c, n);
+        const int rstep = blockDim.x >> 5;
+        int r = threadIdx.x >> 5, a = r / E, b = r - a * E;
+        for (; r < E * E; r += rstep) {
+            if (c < E) {
+                const int gx = wrap_near(ox + a, n), gy = wrap_near(oy + b, n);
+                lds[r * E + c] = g[((long long)gx * n + gy) * rl + gz];
+            }
+            b += rstep;
+            while (b >= E) {
+                b -= E;
+                ++a;
+            }
+        }
     }
     __syncthreads();
     const int deg = S.degree;
@@ -385,7 +573,7 @@ __global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys,
         const typename Vec4<R>::type v = sorted[k];
         R w[3][P], dw[3][P];
         int l0[3];
-        windows3_d<R, P>(v.x, v.y, v.z, ct, deg, w, dw, l0);
+        windows3_d<R, P>(v.x, v.y, v.z, ct, ctd, deg, w, dw, l0);
         const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
         const R(&wx)[P] = w[0];
         const R(&wy)[P] = w[1];
@@ -466,22 +654,26 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
-__global__ void __launch_bounds__(256) k_drift(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+__global__ void __launch_bounds__(kChunkThreads) k_drift(const SysDesc* __restrict__ sys,
+                                                         const int2* __restrict__ items) {
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
-    const int il = wi.y + threadIdx.x;
-    if (S.step <= 0 || il >= S.N) return;
+    if (S.step <= 0) return;
     float* pos = reinterpret_cast<float*>(const_cast<void*>(S.pos));
     const float L = (float)(1.0 / S.inv_L);
-    for (int c = 0; c < 3; ++c) {
-        const unsigned long long ctr = ((unsigned long long)S.step << 40) + 3ULL * il + c + 1ULL;
-        const unsigned long long z = splitmix64(S.seed + ctr * 0x9E3779B97F4A7C15ULL);
-        const double u = (double)(z >> 11) * 0x1.0p-53;
-        const float d = (float)((double)S.drift * (2.0 * u - 1.0));
-        float x = pos[3 * il + c] + d;
-        if (x >= L) x -= L;
-        if (x < 0.0f) x += L;
-        pos[3 * il + c] = x;
+    for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
+        const int il = wi.y + threadIdx.x + k * kChunkThreads;
+        if (il >= S.N) return;
+        for (int c = 0; c < 3; ++c) {
+            const unsigned long long ctr = ((unsigned long long)S.step << 40) + 3ULL * il + c + 1ULL;
+            const unsigned long long z = splitmix64(S.seed + ctr * 0x9E3779B97F4A7C15ULL);
+            const double u = (double)(z >> 11) * 0x1.0p-53;
+            const float d = (float)((double)S.drift * (2.0 * u - 1.0));
+            float x = pos[3 * il + c] + d;
+            if (x >= L) x -= L;
+            if (x < 0.0f) x += L;
+            pos[3 * il + c] = x;
+        }
     }
 }
 
@@ -502,14 +694,17 @@ static hipError_t prepare_t(const Launch& L, int phase) {
     switch (phase) {
         case 0:
             if ((e = allow_lds(k_hist<R>, L.hist_lds)) != hipSuccess) return e;
-            k_hist<R><<<L.n_pitems, 256, L.hist_lds, L.stream>>>(L.sys, L.pitems, L.bpart);
+            k_hist<R><<<L.n_pitems, kChunkThreads, L.hist_lds, L.stream>>>(L.sys, L.pitems, L.bpart);
             break;
         case 1:
             k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.bpart);
             break;
-        case 2:
-            k_scatter<R><<<L.n_pitems, 256, 0, L.stream>>>(L.sys, L.pitems);
+        case 2: {
+            k_scatter<R><<<L.n_pitems, kChunkThreads, 0, L.stream>>>(L.sys, L.pitems);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (L.n_titems > 0) k_deal<R><<<L.n_titems, 256, 0, L.stream>>>(L.sys, L.titems);
             break;
+        }
         default:
             return hipErrorInvalidValue;
     }
@@ -569,7 +764,7 @@ hipError_t launch_fold(const Launch& L) {
 }
 
 hipError_t launch_drift(const Launch& L) {
-    k_drift<<<L.n_pitems, 256, 0, L.stream>>>(L.sys, L.pitems);
+    k_drift<<<L.n_pitems, kChunkThreads, 0, L.stream>>>(L.sys, L.pitems);
     return hipGetLastError();
 }
 

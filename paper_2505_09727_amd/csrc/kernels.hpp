@@ -26,6 +26,7 @@ struct Launch {
     const int2* pitems;   // particle chunks
     int n_pitems;
     const int2* titems;   // bins, grouped by P
+    int n_titems;
     const int2* planes;   // (sys, x), grouped by grid size
     int n_planes;
     const int4* cols;     // (sys, first column, columns, 0), grouped by grid size
@@ -63,7 +64,7 @@ inline int fft_x_lds(int n, int prec) {
 }
 
 // Preparation phases: 0 per-chunk bin histograms, 1 scan, 2 scatter into
-// bin order.
+// bin order and deal each bin into LDS bank classes.
 hipError_t launch_prepare(const Launch& L, int phase);
 hipError_t launch_spread(const Launch& L, const Group& G);
 // Diagnostics: fold the spread tiles into the real grid.
