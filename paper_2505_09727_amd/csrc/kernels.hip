@@ -192,6 +192,16 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
 // holds the j-th staged particle of every class that has one, in class order.
 // Any order within a bin gives the same results; a bin whose largest class
 // exceeds kDealRounds keeps the staged order.
+// Threads per spread / gather block (one block per bin).
+#ifndef ESP_SPREAD_THREADS
+#define ESP_SPREAD_THREADS 512
+#endif
+#ifndef ESP_GATHER_THREADS
+#define ESP_GATHER_THREADS 512
+#endif
+constexpr int kSpreadThreads = ESP_SPREAD_THREADS;
+constexpr int kGatherThreads = ESP_GATHER_THREADS;
+
 constexpr int kDealRounds = 1024;
 constexpr int kDealRegs = 8;  // staged particles per thread held in registers
 
@@ -439,7 +449,7 @@ template <> struct SpreadAcc<float> {
 };
 
 template <typename R, int P>
-__global__ void __launch_bounds__(256) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+__global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     using A = typename SpreadAcc<R>::type;
     constexpr bool kFixed = !std::is_floating_point<A>::value;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -526,7 +536,7 @@ __global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, c
 // Gather (eq. interp) with analytic window derivatives (AD forces):
 // phi_i = u~_i - q_i S(0), F_i = -q_i (n/L) grad_u u~_i, written in caller order.
 template <typename R, int P>
-__global__ void __launch_bounds__(256) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+__global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* lds = reinterpret_cast<R*>(smem_raw);
     const int2 wi = items[blockIdx.x];
@@ -719,7 +729,7 @@ template <typename R, int P>
 static hipError_t spread_p(const Launch& L, const Group& G) {
     hipError_t e = allow_lds(k_spread<R, P>, G.lds_spread);
     if (e != hipSuccess) return e;
-    k_spread<R, P><<<G.count, 256, G.lds_spread, L.stream>>>(L.sys, L.titems + G.off);
+    k_spread<R, P><<<G.count, kSpreadThreads, G.lds_spread, L.stream>>>(L.sys, L.titems + G.off);
     return hipGetLastError();
 }
 
@@ -727,7 +737,7 @@ template <typename R, int P>
 static hipError_t gather_p(const Launch& L, const Group& G) {
     hipError_t e = allow_lds(k_gather<R, P>, G.lds_gather);
     if (e != hipSuccess) return e;
-    k_gather<R, P><<<G.count, 256, G.lds_gather, L.stream>>>(L.sys, L.titems + G.off);
+    k_gather<R, P><<<G.count, kGatherThreads, G.lds_gather, L.stream>>>(L.sys, L.titems + G.off);
     return hipGetLastError();
 }
 
