@@ -62,6 +62,64 @@ def algorithmic_cost(phase, N, n, P, deg, prec):
     return b, f
 
 
+# LDS: 128 bytes per clock per CU (32 banks x 4 B) -> 16 lanes of 64-bit atomics
+# or 32 lanes of 32-bit reads per clock per CU, over 256 CUs at 2.4 GHz.
+PEAK_LDS_U64_ATOMICS_GOPS = 16 * 256 * 2.4
+PEAK_LDS_F32_READS_GOPS = 32 * 256 * 2.4
+
+PHASE_KERNEL = {"hist": "k_hist<float>", "scan": "k_scan", "scatter": "k_scatter<float>",
+                "spread": "k_spread<float, {P}>", "fft_zy": "k_fwd_zy<float, {n}>",
+                "fft_x_scale": "k_fft_x<float, {n}>", "fft_yz": "k_inv_yz<float, {n}>",
+                "gather": "k_gather<float, {P}>", "finalize": "k_finalize"}
+
+
+def measured_traffic(phase, n, P):
+    """HBM bytes per dispatch of the phase's main kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "esp_fp32_water9k_b128_hbm_traffic.md")
+    try:
+        txt = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    for f, h in rec["source_sha256_16"].items():
+        src = os.path.join(ROOT, "paper_2505_09727_amd", "csrc", f)
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != h:
+            return None
+    return rec["hbm_bytes_per_dispatch"].get(PHASE_KERNEL.get(phase, "").format(n=n, P=P))
+
+
+def roofline(phase, ms, B, N, n, P, deg):
+    """Roofline record of one phase launch over the batch (algorithmic bytes
+    and flops from algorithmic_cost, measured launch time ms)."""
+    b1, f1 = algorithmic_cost(phase, N, n, P, deg, 32)
+    bytes_launch, flops_launch = B * b1, B * f1
+    t = ms / 1e3
+    gbs, tfl = bytes_launch / t / 1e9, flops_launch / t / 1e12
+    if flops_launch / (PEAK_FP32_VALU_TFLOPS * 1e12) > bytes_launch / (PEAK_HBM_GBS * 1e9):
+        r = dict(kernel=phase, bound="alu", achieved=tfl, peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s",
+                 frac=tfl / PEAK_FP32_VALU_TFLOPS, hbm_achieved_GBs=gbs, hbm_frac=gbs / PEAK_HBM_GBS)
+    else:
+        r = dict(kernel=phase, bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
+                 frac=gbs / PEAK_HBM_GBS, alu_achieved_TFLOPs=tfl)
+    tr = measured_traffic(phase, n, P)
+    r["traffic"] = tr
+    r["avg_launch_ms"] = ms
+    r["algorithmic_bytes_per_launch"] = bytes_launch
+    r["algorithmic_flops_per_launch"] = flops_launch
+    if phase == "spread":
+        ops = B * N * P ** 3 / t / 1e9
+        r["lds_u64_atomics"] = dict(achieved_Gops=ops, peak_Gops=PEAK_LDS_U64_ATOMICS_GOPS,
+                                    frac=ops / PEAK_LDS_U64_ATOMICS_GOPS)
+    if phase == "gather":
+        ops = B * N * P ** 3 / t / 1e9
+        r["lds_f32_reads"] = dict(achieved_Gops=ops, peak_Gops=PEAK_LDS_F32_READS_GOPS,
+                                  frac=ops / PEAK_LDS_F32_READS_GOPS)
+    return r
+
+
 def cpu_baseline(pos, q, L, prm, budget_s=12.0):
     from threadpoolctl import threadpool_limits
     from oracle.fivestep import five_step
@@ -220,21 +278,9 @@ def main():
     assert st == 0, lib().esp_last_error()
     phases = {lib().esp_phase_name(i).decode(): ms[i] for i in range(nph)}
     dom = max(phases, key=phases.get)
-    b1, f1 = algorithmic_cost(dom, N, prm.nf, prm.P, prm.degree, 32)
-    bytes_launch, flops_launch = B * b1, B * f1
-    t_dom = phases[dom] / 1e3
-    gbs = bytes_launch / t_dom / 1e9
-    tfl = flops_launch / t_dom / 1e12
-    if flops_launch / (PEAK_FP32_VALU_TFLOPS * 1e12) > bytes_launch / (PEAK_HBM_GBS * 1e9):
-        roof = dict(kernel=dom, bound="alu", achieved=tfl, peak=PEAK_FP32_VALU_TFLOPS, unit="TFLOP/s",
-                    frac=tfl / PEAK_FP32_VALU_TFLOPS, traffic=None,
-                    hbm_achieved_GBs=gbs, hbm_frac=gbs / PEAK_HBM_GBS)
-    else:
-        roof = dict(kernel=dom, bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=gbs / PEAK_HBM_GBS, traffic=None, alu_achieved_TFLOPs=tfl)
-    roof["avg_launch_ms"] = phases[dom]
-    roof["algorithmic_bytes_per_launch"] = bytes_launch
-    roof["algorithmic_flops_per_launch"] = flops_launch
+    roof = roofline(dom, phases[dom], B, N, prm.nf, prm.P, prm.degree)
+    kernels = {ph: roofline(ph, phases[ph], B, N, prm.nf, prm.P, prm.degree)
+               for ph in ("spread", "gather", "fft_zy", "fft_x_scale", "fft_yz")}
     plan.close()
 
     # FP64 plain single-system path on one box (same workload shape)
@@ -287,6 +333,7 @@ def main():
         "parity_vs_reference": parity,
         "phases_ms": phases,
         "roofline": roof,
+        "kernel_rooflines": kernels,
         "cpu_baseline": cpu,
         "serving": serving,
     }
