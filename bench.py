@@ -191,6 +191,129 @@ def serving_run(seconds, rate, budget_gb, seed=5):
     }
 
 
+def _time_plan(plan, ext, pos, q, phi, F, steps):
+    """Mean ms per step of `steps` enqueued steps on the plan's stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ext)
+    for _ in range(steps):
+        plan.longrange_async(pos, q, phi, F)
+    e1.record(ext)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def ensemble_run(steps, seed=4):
+    """256 water-like boxes at 1 g/cm^3 with log-uniform sizes in one FP32 plan
+    (autotuned bin edges, graph replay) against the FP64 plain path run one
+    system at a time."""
+    import torch
+    import workloads as W
+    from collections import Counter
+    from oracle.metrics import rel_rms
+    from paper_2505_09727_amd.esp import Plan
+    dev = torch.device("cuda:0")
+    systems = W.ensemble(n_sys=256, seed=seed)
+    Ls = [s[2] for s in systems]
+    Ns = [len(s[1]) for s in systems]
+    off = np.cumsum([0] + Ns)
+    Ntot = int(off[-1])
+    pos = torch.tensor(np.concatenate([s[0] for s in systems]), dtype=torch.float32, device=dev)
+    q = torch.tensor(np.concatenate([s[1] for s in systems]), dtype=torch.float32, device=dev)
+    phi = torch.empty(Ntot, dtype=torch.float32, device=dev)
+    F = torch.empty((Ntot, 3), dtype=torch.float32, device=dev)
+    plan = Plan(Ls, Ns, 1e-4)
+    default_tiles = Counter(p.tile for p in plan.params)
+    grids = sorted({p.nf for p in plan.params})
+    ext = torch.cuda.ExternalStream(plan.stream)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange_async(pos, q, phi, F)
+    ms_default = _time_plan(plan, ext, pos, q, phi, F, steps)
+    t0 = time.perf_counter()
+    tiles = plan.autotune(pos, q, phi, F, reps=3)
+    tune_s = time.perf_counter() - t0
+    for _ in range(3):
+        plan.longrange_async(pos, q, phi, F)
+    ms = _time_plan(plan, ext, pos, q, phi, F, steps)
+    plan.longrange(pos, q, phi, F)
+    F32 = F.cpu().double().numpy()
+    plan.close()
+    # FP64 plain, one single-system plan after another
+    ms64, errs = 0.0, []
+    for s, (ps, qs, L) in enumerate(systems):
+        p64 = Plan(L, len(qs), 1e-4, precision=64)
+        tp = torch.tensor(ps, dtype=torch.float64, device=dev)
+        tq = torch.tensor(qs, dtype=torch.float64, device=dev)
+        ph = torch.empty(len(qs), dtype=torch.float64, device=dev)
+        Fs = torch.empty((len(qs), 3), dtype=torch.float64, device=dev)
+        e64 = torch.cuda.ExternalStream(p64.stream)
+        p64.longrange_async(tp, tq, ph, Fs)
+        ms64 += _time_plan(p64, e64, tp, tq, ph, Fs, 3)
+        errs.append(rel_rms(F32[off[s]:off[s + 1]], Fs.cpu().numpy()))
+        p64.close()
+    return {
+        "workload": f"256 water-like boxes at 1 g/cm^3, atoms log-uniform in [500, 20000] (total {Ntot}), "
+                    f"grids {grids[0]}^3..{grids[-1]}^3, tol 1e-4, FP32 batched plan, HIP graph replay",
+        "particle_steps_per_s": Ntot / (ms / 1e3), "ms_per_step": ms,
+        "ms_per_step_default_tiles": ms_default, "autotune_s": tune_s,
+        "tiles_default": dict(default_tiles), "tiles_autotuned": dict(Counter(tiles)),
+        "fp64_plain": {"particle_steps_per_s": Ntot / (ms64 / 1e3), "ms_per_sweep": ms64,
+                       "what": "256 single-system FP64 plans run one after another"},
+        "speedup_vs_fp64_plain": ms64 / ms,
+        "rel_rms_F_fp32_vs_fp64": {"median": float(np.median(errs)), "max": float(np.max(errs))},
+    }
+
+
+def large_run(steps, serve_steps=100):
+    """300,000-atom water-like box (L = 100, tol 1e-5): FP32 plan vs FP64 plain
+    on the same positions, and 100 served steps with 0.01 drift (device
+    resident, one request)."""
+    import torch
+    import workloads as W
+    from oracle.metrics import rel_rms
+    from paper_2505_09727_amd.esp import Plan, Server
+    dev = torch.device("cuda:0")
+    cfg = W.WATER_300K
+    pos, q = W.water_box(cfg["n_mol"], cfg["L"], seed=cfg["seed"])
+    L, N, tol = cfg["L"], len(q), cfg["tol"]
+    out = {"workload": f"{N} atoms (water-like), L={L}, tol {tol}"}
+    res = {}
+    for prec, dt in ((32, torch.float32), (64, torch.float64)):
+        plan = Plan(L, N, tol, precision=prec)
+        tp = torch.tensor(pos, dtype=dt, device=dev)
+        tq = torch.tensor(q, dtype=dt, device=dev)
+        ph = torch.empty(N, dtype=dt, device=dev)
+        Fs = torch.empty((N, 3), dtype=dt, device=dev)
+        ext = torch.cuda.ExternalStream(plan.stream)
+        if prec == 32:
+            plan.set_graph(True)
+        for _ in range(3):
+            plan.longrange_async(tp, tq, ph, Fs)
+        ms = _time_plan(plan, ext, tp, tq, ph, Fs, steps)
+        E = plan.longrange(tp, tq, ph, Fs)
+        p = plan.params[0]
+        res[prec] = dict(ms=ms, F=Fs.cpu().double().numpy(), E=float(E[0]))
+        out[f"fp{prec}"] = {"particle_steps_per_s": N / (ms / 1e3), "ms_per_step": ms,
+                            "grid": p.nf, "P": p.P, "tile": p.tile}
+        plan.close()
+    out["speedup_fp32_vs_fp64_plain"] = res[64]["ms"] / res[32]["ms"]
+    out["rel_rms_F_fp32_vs_fp64"] = rel_rms(res[32]["F"], res[64]["F"])
+    out["rel_E_fp32_vs_fp64"] = abs(res[32]["E"] - res[64]["E"]) / abs(res[64]["E"])
+    srv = Server()
+    t0 = time.perf_counter()
+    srv.submit(pos.astype(np.float32), q.astype(np.float32), L, tol, nsteps=serve_steps, drift=0.01, seed=3)
+    srv.wait(300)
+    wall = time.perf_counter() - t0
+    r = srv.poll()
+    srv.close()
+    out["served_drift"] = {"steps": serve_steps, "wall_s": wall, "particle_steps_per_s": N * serve_steps / wall,
+                           "E_first": r[0]["E_first"] if r else None, "E_last": r[0]["E_last"] if r else None,
+                           "what": "one request, positions resident, seeded 0.01 drift per step, "
+                                   "wall time incl. upload and planning"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +326,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=0.5, help="length of the served arrival stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-system ensemble section")
+    ap.add_argument("--no-large", action="store_true", help="skip the 300,000-atom section")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -307,6 +432,8 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(boxes[0][0], boxes[0][1], L, prm)
     serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_budget_gb) if args.serve_seconds > 0 else None
+    ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
+    large = None if args.no_large else large_run(max(10, args.steps // 10))
 
     out = {
         "metric": "long-range particle-steps/s at 1e-4 force err (FP32 batched vs FP64 plain); p50/p99 latency",
@@ -336,6 +463,8 @@ def main():
         "kernel_rooflines": kernels,
         "cpu_baseline": cpu,
         "serving": serving,
+        "ensemble": ensemble,
+        "large_system": large,
     }
     print(json.dumps(out))
 

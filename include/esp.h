@@ -154,6 +154,21 @@ esp_status esp_longrange_async(esp_plan* plan, const void* pos, const void* q,
                                void* phi, void* F, double* E_dev);
 esp_status esp_plan_sync(esp_plan* plan);
 
+/* Autotuner of the bin edge T (spec batching: tile and bin sizes picked
+ * by measurement). Systems are grouped by (grid size, window width); for each
+ * group, largest total particle count first, every admissible T (divisors of
+ * the grid size in [8, 16] whose spread tile and bin histogram fit in the
+ * 160 KB LDS) is timed over `reps` full steps on the caller's data (pos, q,
+ * phi, F as for esp_longrange_async, device, concatenated in system order)
+ * with the other groups held at their current T, and the fastest is kept.
+ * The plan is then rebuilt with the chosen T: its scratch is reallocated and
+ * a captured graph is dropped (recaptured on the next graph call). tiles_out
+ * (nsys ints, may be NULL) receives the chosen T per system. Blocks until
+ * done. Results do not depend on T beyond rounding (FP64) or at all (the FP32
+ * fixed-point spread). */
+esp_status esp_plan_autotune(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
+                             int* tiles_out);
+
 /* Capture the whole pipeline for fixed buffers into a HIP graph and replay it
  * on every later esp_longrange call with the same pointers (0 disables). */
 esp_status esp_plan_set_graph(esp_plan* plan, int enable);

@@ -74,7 +74,10 @@ esp_status TableStore::get(const esp_params& p, const DeviceClass** out, std::st
 
 int choose_tile(int n, int requested, long long target) {
     if (requested > 0) {
-        for (int d = std::min(requested, n); d >= 4; --d)
+        // T >= 8 keeps every grid index inside at most 3 tiles per axis
+        for (int d = std::min(requested, n); d >= 8; --d)
+            if (n % d == 0) return d;
+        for (int d = 8; d <= n; ++d)
             if (n % d == 0) return d;
         return n;
     }
@@ -87,6 +90,17 @@ int choose_tile(int n, int requested, long long target) {
     }
     if (best) return best;
     return smallest ? smallest : n;
+}
+
+std::vector<int> tile_candidates(int n, int P) {
+    std::vector<int> out;
+    for (int d = 8; d <= 16; ++d) {
+        if (n % d) continue;
+        const int E = d + P - 1 + (P & 1);
+        const long long nb = (long long)(n / d) * (n / d) * (n / d);
+        if ((long long)E * E * E * 8 + 2 * 12 * 17 * 8 <= kMaxLds && nb * 4 <= kMaxLds) out.push_back(d);
+    }
+    return out;
 }
 
 // The tile buffer also stages the scatter's output (particles in bin order

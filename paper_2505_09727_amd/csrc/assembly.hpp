@@ -39,8 +39,11 @@ class TableStore {
 };
 
 // Bin edge: a divisor of n in [8, 16] giving at least `target` bins when
-// possible (requested > 0 rounds a caller's choice down to a divisor).
+// possible (requested > 0 rounds a caller's choice down to a divisor >= 8).
 int choose_tile(int n, int requested, long long target);
+// Bin edges an autotuner may try for grid n and window P: divisors of n in
+// [8, 16] whose spread tile and bin histogram fit in LDS.
+std::vector<int> tile_candidates(int n, int P);
 
 // Scratch of one system, carved from one block of device memory.
 struct SysScratch {

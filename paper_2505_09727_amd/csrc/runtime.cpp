@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -79,6 +80,44 @@ struct esp_plan {
 
 namespace {
 
+// (Re)allocate the systems' scratch for their current tiles, carve it, and
+// build the launch set. Drops a captured graph and the bound caller buffers.
+esp_status assemble(esp_plan* p) {
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+    }
+    if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    p->io_set = false;
+    if (p->scratch) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        HIP_TRY(hipFree(p->scratch));
+        p->scratch = nullptr;
+    }
+    const int nsys = p->nsys;
+    std::vector<size_t> off(nsys + 1, 0);
+    for (int s = 0; s < nsys; ++s) off[s + 1] = off[s] + scratch_bytes(p->prm[s], p->Ns[s]);
+    HIP_TRY(hipMalloc(&p->scratch, std::max<size_t>(off[nsys], 256)));
+    for (int s = 0; s < nsys; ++s) {
+        SystemSlot& sl = p->slots[s];
+        sl.prm = p->prm[s];
+        sl.N = p->Ns[s];
+        std::string msg;
+        esp_status st = p->tables.get(sl.prm, &sl.cls, msg);
+        if (st != ESP_OK) return fail(st, msg);
+        sl.scr = carve_scratch(p->scratch + off[s], sl.prm, p->Ns[s]);
+        sl.scr.out = p->d_out + (size_t)kOutDoubles * s;
+    }
+    std::string msg;
+    esp_status st = p->ls.build(p->slots, p->prec, p->stream, msg);
+    if (st != ESP_OK) return fail(st, msg);
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return ESP_OK;
+}
+
 esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const double* tols, const esp_params* reqs,
                       bool per_system_req, esp_plan** out) {
     if (!out) return fail(ESP_E_INVALID, "out is NULL");
@@ -111,29 +150,14 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
     for (int s = 1; s < nsys; ++s)
         if (p->prm[s].precision != p->prec) return fail(ESP_E_INVALID, "all systems of a batch must share one precision");
 
-    std::vector<size_t> off(nsys + 1, 0);
-    for (int s = 0; s < nsys; ++s) off[s + 1] = off[s] + scratch_bytes(p->prm[s], Ns[s]);
-    HIP_TRY(hipMalloc(&p->scratch, std::max<size_t>(off[nsys], 256)));
     HIP_TRY(hipMalloc(&p->d_out, sizeof(double) * kOutDoubles * nsys));
     HIP_TRY(hipMemset(p->d_out, 0, sizeof(double) * kOutDoubles * nsys));
     HIP_TRY(hipHostMalloc((void**)&p->h_out, sizeof(double) * kOutDoubles * nsys, hipHostMallocDefault));
     HIP_TRY(hipStreamCreate(&p->stream));
     p->own_stream = true;
     p->slots.resize(nsys);
-    for (int s = 0; s < nsys; ++s) {
-        SystemSlot& sl = p->slots[s];
-        sl.prm = p->prm[s];
-        sl.N = Ns[s];
-        std::string msg;
-        esp_status st = p->tables.get(sl.prm, &sl.cls, msg);
-        if (st != ESP_OK) return fail(st, msg);
-        sl.scr = carve_scratch(p->scratch + off[s], sl.prm, Ns[s]);
-        sl.scr.out = p->d_out + (size_t)kOutDoubles * s;
-    }
-    std::string msg;
-    esp_status st = p->ls.build(p->slots, p->prec, p->stream, msg);
-    if (st != ESP_OK) return fail(st, msg);
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    esp_status st = assemble(p);
+    if (st != ESP_OK) return st;
     *out = holder.release();
     return ESP_OK;
 }
@@ -403,6 +427,66 @@ esp_status esp_longrange(esp_plan* plan, const void* pos, const void* q, void* p
     s = esp_plan_sync(plan);
     for (int i = 0; i < plan->nsys; ++i) E[i] = plan->h_out[kOutDoubles * i];
     return s;
+}
+
+esp_status esp_plan_autotune(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
+                             int* tiles_out) {
+    if (!plan || !pos || !q || reps < 1) return fail(ESP_E_INVALID, "bad argument");
+    // groups of systems sharing (grid, window width), largest work first
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int s = 0; s < plan->nsys; ++s) groups[{plan->prm[s].nf, plan->prm[s].P}].push_back(s);
+    std::vector<std::pair<double, std::vector<int>>> order;
+    for (auto& kv : groups) {
+        double w = 0.0;
+        for (int s : kv.second) w += (double)plan->Ns[s];
+        order.push_back({w, kv.second});
+    }
+    std::sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_steps = [&](double* ms) -> esp_status {
+        esp_status st = bind_io(plan, pos, q, phi, F);
+        if (st != ESP_OK) return st;
+        if ((st = enqueue(plan, nullptr, 0, nullptr)) != ESP_OK) return st;  // warm-up
+        HIP_TRY(hipEventRecord(e0, plan->stream));
+        for (int r = 0; r < reps; ++r)
+            if ((st = enqueue(plan, nullptr, 0, nullptr)) != ESP_OK) return st;
+        HIP_TRY(hipEventRecord(e1, plan->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        *ms = t;
+        return ESP_OK;
+    };
+    esp_status st = ESP_OK;
+    for (auto& g : order) {
+        const std::vector<int>& sys = g.second;
+        const esp_params& r0 = plan->prm[sys[0]];
+        const std::vector<int> cand = tile_candidates(r0.nf, r0.P);
+        if (cand.size() < 2) continue;
+        int best = plan->prm[sys[0]].tile;
+        double best_ms = 1e30;
+        for (int T : cand) {
+            for (int s : sys) plan->prm[s].tile = T;
+            if ((st = assemble(plan)) != ESP_OK) break;
+            double ms = 0.0;
+            if ((st = time_steps(&ms)) != ESP_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = T;
+            }
+        }
+        if (st != ESP_OK) break;
+        for (int s : sys) plan->prm[s].tile = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ESP_OK) return st;
+    if ((st = assemble(plan)) != ESP_OK) return st;
+    if (tiles_out)
+        for (int s = 0; s < plan->nsys; ++s) tiles_out[s] = plan->prm[s].tile;
+    return ESP_OK;
 }
 
 esp_status esp_plan_set_graph(esp_plan* plan, int enable) {

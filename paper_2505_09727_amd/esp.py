@@ -87,6 +87,7 @@ _SIGS = {
     "esp_longrange_async": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esp_plan_sync": (C.c_int, [_vp]),
     "esp_plan_set_graph": (C.c_int, [_vp, C.c_int]),
+    "esp_plan_autotune": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_int)]),
     "esp_plan_destroy": (None, [_vp]),
     "esp_debug_stage": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
     "esp_plan_profile": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_double)]),
@@ -240,6 +241,19 @@ class Plan:
 
     def set_graph(self, enable: bool = True):
         _check(lib().esp_plan_set_graph(self._h, int(bool(enable))))
+
+    def autotune(self, pos, q, phi=None, F=None, reps: int = 3):
+        """esp_plan_autotune: time the admissible bin edges per (grid, P) group
+        on these buffers and rebuild the plan with the fastest; returns the
+        chosen bin edge of every system."""
+        import torch
+        ext = self._order_after_torch()
+        tiles = (C.c_int * self.nsys)()
+        st = lib().esp_plan_autotune(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), int(reps), tiles)
+        torch.cuda.current_stream().wait_stream(ext)
+        _check(st)
+        self.params = [self.get_params(s) for s in range(self.nsys)]
+        return list(tiles)
 
     def debug_stage(self, pos, q, stage, out, grid_in=None):
         import torch
