@@ -233,6 +233,7 @@ def ensemble_run(steps, seed=4):
     t0 = time.perf_counter()
     tiles = plan.autotune(pos, q, phi, F, reps=3)
     tune_s = time.perf_counter() - t0
+    one_block_fft = sum(1 for p in plan.params if p.fft_passes == 1)
     for _ in range(3):
         plan.longrange_async(pos, q, phi, F)
     ms = _time_plan(plan, ext, pos, q, phi, F, steps)
@@ -258,6 +259,7 @@ def ensemble_run(steps, seed=4):
         "particle_steps_per_s": Ntot / (ms / 1e3), "ms_per_step": ms,
         "ms_per_step_default_tiles": ms_default, "autotune_s": tune_s,
         "tiles_default": dict(default_tiles), "tiles_autotuned": dict(Counter(tiles)),
+        "systems_on_one_block_fft": one_block_fft,
         "fp64_plain": {"particle_steps_per_s": Ntot / (ms64 / 1e3), "ms_per_sweep": ms64,
                        "what": "256 single-system FP64 plans run one after another"},
         "speedup_vs_fp64_plain": ms64 / ms,

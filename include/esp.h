@@ -72,10 +72,14 @@ typedef struct {
     int    P;             /* window width in grid points, 4..12 */
     int    degree;        /* window polynomial degree, 4..16 */
     int    precision;     /* 32 (default) or 64 */
-    int    tile;          /* particle bin edge in grid points, 4..16, rounded down to a
-                             divisor of nf (0: chosen per plan; reported by
+    int    tile;          /* particle bin edge in grid points, 8..16, rounded down to a
+                             divisor of nf >= 8 (0: chosen per plan; reported by
                              esp_plan_get_params, 0 from esp_plan_query) */
-    int    deterministic; /* reserved: 1 requests a fixed reduction order */
+    int    fft_passes;    /* 0: three FFT passes (x-planes, x-columns, x-planes);
+                             1: one block per system for the whole 3D FFT where
+                             the half spectrum fits in LDS (nf <= 32 in FP32,
+                             <= 24 in FP64), three passes otherwise. Both are
+                             deterministic; esp_plan_autotune may pick either. */
     double c;             /* splitting-kernel PSWF shape parameter */
     double c1;            /* window PSWF shape parameter */
     double rc;            /* cutoff radius of the local part */
@@ -161,7 +165,8 @@ esp_status esp_plan_sync(esp_plan* plan);
  * 160 KB LDS) is timed over `reps` full steps on the caller's data (pos, q,
  * phi, F as for esp_longrange_async, device, concatenated in system order)
  * with the other groups held at their current T, and the fastest is kept.
- * The plan is then rebuilt with the chosen T: its scratch is reallocated and
+ * Where the one-block FFT applies (fft_passes), both FFT paths are timed for
+ * every T. The plan is then rebuilt with the choice: its scratch is reallocated and
  * a captured graph is dropped (recaptured on the next graph call). tiles_out
  * (nsys ints, may be NULL) receives the chosen T per system. Blocks until
  * done. Results do not depend on T beyond rounding (FP64) or at all (the FP32

@@ -150,7 +150,7 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
 }
 
 LaunchSet::~LaunchSet() {
-    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_cols_, d_bpart_, d_epart_};
+    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_fsys_, d_cols_, d_bpart_, d_epart_};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -189,6 +189,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     cols_.clear();
     groups_.clear();
     fgroups_.clear();
+    fsys_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
     int nb_max = 1;
     for (int s = 0; s < nsys; ++s) {
@@ -241,18 +242,34 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             return ESP_E_UNSUPPORTED;
         }
     }
-    // FFT work items grouped by grid size (one launch per size and pass)
-    std::map<int, std::vector<int>> by_n;
-    for (int s = 0; s < nsys; ++s) by_n[hsys_[s].n].push_back(s);
+    // FFT work items grouped by (grid size, path): one launch per group and
+    // pass. Systems that ask for the one-block transform and whose half
+    // spectrum fits in LDS take it; their energy partial goes to one slot
+    // after the x-column items.
+    std::map<std::pair<int, int>, std::vector<int>> by_n;
+    for (int s = 0; s < nsys; ++s) {
+        const int n = hsys_[s].n;
+        const int fused = systems[s].prm.fft_passes == 1 && fft_fused_lds(n, prec) <= kMaxLds;
+        by_n[{n, fused}].push_back(s);
+    }
     const int C = fft_x_columns(prec);
+    std::vector<int> fused_sys;
     for (const auto& kv : by_n) {
-        const int n = kv.first, hs = n / 2 + 1;
+        const int n = kv.first.first, hs = n / 2 + 1;
         FftGroup fg{};
         fg.n = n;
+        fg.fused = kv.first.second;
         fg.plane_off = (int)planes_.size();
         fg.col_off = (int)cols_.size();
+        fg.sys_off = (int)fsys_.size();
         for (int s : kv.second) {
+            // x-planes of every system (the diagnostic fold walks them all)
             for (int x = 0; x < n; ++x) planes_.push_back(make_int2(s, x));
+            if (fg.fused) {
+                fsys_.push_back(make_int2(s, 0));
+                fused_sys.push_back(s);
+                continue;
+            }
             SysDesc& d = hsys_[s];
             d.col_off = (int)cols_.size();
             for (int c0 = 0; c0 < n * hs; c0 += C) cols_.push_back(make_int4(s, c0, std::min(C, n * hs - c0), 0));
@@ -260,7 +277,14 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         }
         fg.plane_count = (int)planes_.size() - fg.plane_off;
         fg.col_count = (int)cols_.size() - fg.col_off;
+        fg.sys_count = (int)fsys_.size() - fg.sys_off;
         fgroups_.push_back(fg);
+    }
+    const int n_eslots = (int)cols_.size() + (int)fused_sys.size();
+    for (size_t k = 0; k < fused_sys.size(); ++k) {
+        SysDesc& d = hsys_[fused_sys[k]];
+        d.col_off = (int)cols_.size() + (int)k;
+        d.ncol = 1;
     }
     for (int P = 4; P <= 12; ++P) {
         if (titems_by_P[P].empty()) continue;
@@ -301,6 +325,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     if ((st = put(&d_titems_, &cap_titems_, titems_, msg)) != ESP_OK) return st;
     if ((st = put(&d_planes_, &cap_planes_, planes_, msg)) != ESP_OK) return st;
     if ((st = put(&d_cols_, &cap_cols_, cols_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_fsys_, &cap_fsys_, fsys_, msg)) != ESP_OK) return st;
     // partial sums are written before they are read: capacity only
     auto reserve = [&](double** dev, size_t* cap, size_t need) {
         if (need <= *cap && *dev) return ESP_OK;
@@ -316,12 +341,13 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         return ESP_OK;
     };
     if ((st = reserve(&d_bpart_, &cap_bpart_, 4 * pitems_.size())) != ESP_OK) return st;
-    if ((st = reserve(&d_epart_, &cap_epart_, cols_.size())) != ESP_OK) return st;
+    if ((st = reserve(&d_epart_, &cap_epart_, (size_t)n_eslots)) != ESP_OK) return st;
     L_.sys = d_sys_;
     L_.pitems = d_pitems_;
     L_.titems = d_titems_;
     L_.planes = d_planes_;
     L_.cols = d_cols_;
+    L_.fsys = d_fsys_;
     L_.bpart = d_bpart_;
     L_.epart = d_epart_;
     return ESP_OK;

@@ -29,10 +29,11 @@ namespace esp {
 
 // One Stockham autosort stage of radix RAD after NS points have been combined,
 // on NL lines of length N held in LDS; element (line, idx) is at
-// buf[line * LS + idx * ES]. Every thread loads and transforms its butterflies
+// buf[base(line) + idx * ES], base(line) = (line / L1) S1 + (line % L1) S2
+// (lines grouped L1 to a plane). Every thread loads and transforms its butterflies
 // into registers, the block synchronises, then every thread stores, so the
 // stage runs in place. LF maps consecutive threads to consecutive lines.
-template <typename R, int N, int RAD, int NS, int NL, int LS, int ES, int BD, bool LF, int DIR>
+template <typename R, int N, int RAD, int NS, int NL, int L1, int S1, int S2, int ES, int BD, bool LF, int DIR>
 __device__ __forceinline__ void st_stage(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw) {
     constexpr int NB = N / RAD;
     constexpr int TOTAL = NL * NB;
@@ -53,7 +54,8 @@ __device__ __forceinline__ void st_stage(cplx<R>* __restrict__ buf, const cplx<R
                 line = item / NB;
                 j = item - line * NB;
             }
-            const cplx<R>* src = buf + line * LS + j * ES;
+            const int lb = (line / L1) * S1 + (line % L1) * S2;
+            const cplx<R>* src = buf + lb + j * ES;
             const int jm = j % NS;
 #pragma unroll
             for (int k = 0; k < RAD; ++k) {
@@ -68,7 +70,7 @@ __device__ __forceinline__ void st_stage(cplx<R>* __restrict__ buf, const cplx<R
                 v[it][k] = a;
             }
             Bfly<R, RAD>::run(v[it], DIR);
-            dst[it] = line * LS + ((j - jm) * RAD + jm) * ES;
+            dst[it] = lb + ((j - jm) * RAD + jm) * ES;
         }
     }
     __syncthreads();
@@ -84,14 +86,20 @@ __device__ __forceinline__ void st_stage(cplx<R>* __restrict__ buf, const cplx<R
 
 // Unnormalised DFT y_k = sum_l exp(DIR 2 pi i k l / N) x_l of NL lines in LDS,
 // natural order in and out; tw[t] = exp(2 pi i t / N).
-template <typename R, int N, int NS, int NL, int LS, int ES, int BD, bool LF, int DIR>
-__device__ __forceinline__ void fft_ct(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw) {
+template <typename R, int N, int NS, int NL, int L1, int S1, int S2, int ES, int BD, bool LF, int DIR>
+__device__ __forceinline__ void fft_ct2(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw) {
     if constexpr (NS < N) {
         constexpr int M = N / NS;
         constexpr int RAD = M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 3);
-        st_stage<R, N, RAD, NS, NL, LS, ES, BD, LF, DIR>(buf, tw);
-        fft_ct<R, N, NS * RAD, NL, LS, ES, BD, LF, DIR>(buf, tw);
+        st_stage<R, N, RAD, NS, NL, L1, S1, S2, ES, BD, LF, DIR>(buf, tw);
+        fft_ct2<R, N, NS * RAD, NL, L1, S1, S2, ES, BD, LF, DIR>(buf, tw);
     }
+}
+
+// Lines at buf[line * LS + idx * ES].
+template <typename R, int N, int NS, int NL, int LS, int ES, int BD, bool LF, int DIR>
+__device__ __forceinline__ void fft_ct(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw) {
+    fft_ct2<R, N, NS, NL, NL, 0, LS, ES, BD, LF, DIR>(buf, tw);
 }
 
 // Launch shapes, functions of N and the real type only.
@@ -325,6 +333,227 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
     if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
 }
 
+// ---------------------------------------------------------------------------
+// Whole 3D transform of one system in one block, for grids whose half
+// spectrum fits in LDS (FP32 n <= 32, FP64 n <= 24): halo fold, forward z, y
+// and x, scaling with the energy, inverse x, y and z, one write of the real
+// grid. The passes and their arithmetic are those of the three-kernel path;
+// planes sit at buf[x * N (N/2+1)] in the same layouts.
+
+template <int N, typename R> constexpr bool fused_fits() {
+    return (N + N * N * (N / 2 + 1)) * 2 * (int)sizeof(R) + (N + 1) * (int)sizeof(CoverTab) <= 160 * 1024;
+}
+constexpr int kFusedThreads = 1024;
+
+template <typename R, int N, int BD>
+__device__ __forceinline__ void fold_volume(R* __restrict__ bufr, const R* __restrict__ tiles, const SysDesc& S,
+                                            const CoverTab* __restrict__ tab) {
+    constexpr int NV = N * N * N, PG = 2, PL2 = 2 * N * (N / 2 + 1);
+    const int t1 = S.tiles1, E = S.E, EE = E * E, E3 = EE * E;
+    for (int p0 = 0; p0 < NV; p0 += PG * BD) {
+        R acc[PG];
+        int xs[PG], ys[PG], zs[PG];
+#pragma unroll
+        for (int q = 0; q < PG; ++q) {
+            const int idx = p0 + q * BD + (int)threadIdx.x;
+            const int i = idx < NV ? idx : 0;
+            xs[q] = i / (N * N);
+            ys[q] = (i / N) % N;
+            zs[q] = i % N;
+            acc[q] = R(0);
+        }
+#pragma unroll 1
+        for (int a = 0; a < 3; ++a) {
+            R v[PG][3][3];
+#pragma unroll
+            for (int q = 0; q < PG; ++q) {
+                const int idx = p0 + q * BD + (int)threadIdx.x;
+                const CoverTab cx = tab[xs[q]], cy = tab[ys[q]], cz = tab[zs[q]];
+                const bool okx = ((NV % (PG * BD) == 0) || idx < NV) && a < cx.cnt;
+                const R* ta = tiles + (okx ? cx.bin[a] * t1 * t1 * E3 + cx.off[a] * EE : 0);
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        v[q][b][c] = (okx && b < cy.cnt && c < cz.cnt)
+                                         ? ta[(cy.bin[b] * t1 + cz.bin[c]) * E3 + cy.off[b] * E + cz.off[c]]
+                                         : R(0);
+            }
+#pragma unroll
+            for (int q = 0; q < PG; ++q)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[q] += v[q][b][c];
+        }
+#pragma unroll
+        for (int q = 0; q < PG; ++q) {
+            const int idx = p0 + q * BD + (int)threadIdx.x;
+            if ((NV % (PG * BD) == 0) || idx < NV) {
+                const int y = ys[q], z = zs[q];
+                bufr[xs[q] * PL2 + 2 * ((y >> 1) * N + z) + (y & 1)] = acc[q];
+            }
+        }
+    }
+}
+
+// The same fold streamed tile by tile: the block adds each bin tile's E^3
+// entries (contiguous in HBM, loaded row by row by 32-lane groups) into the
+// zeroed LDS grid, one tile after another. A tile covers distinct grid points
+// when E <= N, so the adds of one tile never collide; the caller uses
+// fold_volume otherwise.
+template <typename R, int N, int BD>
+__device__ __forceinline__ void fold_stream(R* __restrict__ bufr, const R* __restrict__ tiles, const SysDesc& S) {
+    constexpr int PL2 = 2 * N * (N / 2 + 1);
+    const int T = S.T, t1 = S.tiles1, E = S.E, EE = E * E, E3 = EE * E;
+    const int lo = -((S.P - 1) / 2);
+    for (int i = threadIdx.x; i < N * PL2; i += BD) bufr[i] = R(0);
+    const int c = threadIdx.x & 31;
+    constexpr int rstep = BD >> 5;
+    const int nb = t1 * t1 * t1;
+    for (int t = 0; t < nb; ++t) {
+        __syncthreads();
+        const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+        const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
+        const R* tp = tiles + (size_t)t * E3;
+        int z = oz + c;
+        z += z < 0 ? N : 0;
+        z -= z >= N ? N : 0;
+        int r = threadIdx.x >> 5, a = r / E, b = r - a * E;
+        for (; r < EE; r += rstep) {
+            if (c < E) {
+                int x = ox + a, y = oy + b;
+                x += x < 0 ? N : 0;
+                x -= x >= N ? N : 0;
+                y += y < 0 ? N : 0;
+                y -= y >= N ? N : 0;
+                bufr[x * PL2 + 2 * ((y >> 1) * N + z) + (y & 1)] += tp[r * E + c];
+            }
+            b += rstep;
+            while (b >= E) {
+                b -= E;
+                ++a;
+            }
+        }
+    }
+}
+
+// Pair rows (2r, 2r+1) transformed as complex row r -> half spectra of the two
+// real rows, in every plane (forward), or back (inverse).
+template <typename R, int N, int BD, bool FWD>
+__device__ __forceinline__ void untangle_all(cplx<R>* __restrict__ buf) {
+    constexpr int HS = N / 2 + 1, HALF = N / 2, PL = N * HS;
+    constexpr int TOTAL = N * HALF * HS, IT = (TOTAL + BD - 1) / BD;
+    cplx<R> A[IT], B[IT];
+    int o[IT], k_[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int item = threadIdx.x + it * BD;
+        o[it] = -1;
+        if (item < TOTAL) {
+            const int x = item / (HALF * HS), rem = item - x * (HALF * HS);
+            const int r = rem / HS, k = rem - r * HS;
+            cplx<R>* pl = buf + x * PL;
+            if constexpr (FWD) {
+                const cplx<R> zk = pl[r * N + k];
+                const cplx<R> zn = pl[r * N + (k == 0 ? 0 : N - k)];
+                A[it] = {R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};
+                B[it] = {R(0.5) * (zk.y + zn.y), -R(0.5) * (zk.x - zn.x)};
+                o[it] = x * PL + (2 * r) * HS + k;
+            } else {
+                const cplx<R> a = pl[(2 * r) * HS + k], b = pl[(2 * r + 1) * HS + k];
+                A[it] = {a.x - b.y, a.y + b.x};
+                B[it] = {a.x + b.y, b.x - a.y};
+                o[it] = x * PL + r * N;
+                k_[it] = k;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+        if (o[it] >= 0) {
+            if constexpr (FWD) {
+                buf[o[it]] = A[it];
+                buf[o[it] + HS] = B[it];
+            } else {
+                const int k = k_[it];
+                buf[o[it] + k] = A[it];
+                if (k > 0 && k < HALF) buf[o[it] + N - k] = B[it];
+            }
+        }
+    __syncthreads();
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(kFusedThreads) k_fft3d(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                         double* __restrict__ epart, int from_tiles, int mode) {
+    constexpr int HS = N / 2 + 1, RL = N + 2, HALF = N / 2, PL = N * HS, BD = kFusedThreads;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + N;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
+    R* grid = reinterpret_cast<R*>(S.grid);
+    if (from_tiles && S.E <= N) {
+        fold_stream<R, N, BD>(reinterpret_cast<R*>(buf), reinterpret_cast<const R*>(S.tiles), S);
+    } else if (from_tiles) {
+        CoverTab* tab = reinterpret_cast<CoverTab*>(buf + N * PL);
+        build_cover(tab, S, -((S.P - 1) / 2));
+        __syncthreads();
+        fold_volume<R, N, BD>(reinterpret_cast<R*>(buf), reinterpret_cast<const R*>(S.tiles), S, tab);
+    } else {
+        for (int idx = threadIdx.x; idx < N * HALF * N; idx += BD) {
+            const int x = idx / (HALF * N), rem = idx - x * (HALF * N), r = rem / N, z = rem - r * N;
+            buf[x * PL + r * N + z] = {grid[(x * N + 2 * r) * RL + z], grid[(x * N + 2 * r + 1) * RL + z]};
+        }
+    }
+    __syncthreads();
+    fft_ct2<R, N, 1, N * HALF, HALF, PL, N, 1, BD, false, +1>(buf, tw);   // z, pair rows
+    untangle_all<R, N, BD, true>(buf);
+    fft_ct2<R, N, 1, N * HS, HS, PL, 1, HS, BD, true, +1>(buf, tw);       // y
+    fft_ct2<R, N, 1, PL, PL, 0, 1, PL, BD, true, +1>(buf, tw);            // x
+    double e = 0.0;
+    if (mode != 1) {
+        const R* TS = reinterpret_cast<const R*>(S.TS);
+        const R* Tp = reinterpret_cast<const R*>(S.Tphi);
+        const R ps = R(S.pscale);
+        for (int idx = threadIdx.x; idx < N * PL; idx += BD) {
+            const int x = idx / PL, col = idx - x * PL;
+            const int ky = col / HS, kz = col - ky * HS;
+            const int mx = x <= HALF ? x : N - x;
+            const int my = ky <= HALF ? ky : N - ky;
+            const R p = TS[mx * mx + my * my + kz * kz] * Tp[mx] * (Tp[my] * ps) * Tp[kz];
+            const cplx<R> b = buf[idx];
+            const double wgt = (kz == 0 || kz == HALF) ? 1.0 : 2.0;
+            e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);
+            buf[idx] = {b.x * p, b.y * p};
+        }
+        __syncthreads();
+    }
+    if (mode == 0) {
+        fft_ct2<R, N, 1, PL, PL, 0, 1, PL, BD, true, -1>(buf, tw);        // x
+        fft_ct2<R, N, 1, N * HS, HS, PL, 1, HS, BD, true, -1>(buf, tw);   // y
+        untangle_all<R, N, BD, false>(buf);
+        fft_ct2<R, N, 1, N * HALF, HALF, PL, N, 1, BD, false, -1>(buf, tw);  // z
+        for (int idx = threadIdx.x; idx < N * HALF * N; idx += BD) {
+            const int x = idx / (HALF * N), rem = idx - x * (HALF * N), r = rem / N, z = rem - r * N;
+            const cplx<R> v = buf[x * PL + r * N + z];
+            grid[(x * N + 2 * r) * RL + z] = v.x;
+            grid[(x * N + 2 * r + 1) * RL + z] = v.y;
+        }
+    } else {
+        // diagnostics: the (scaled) half spectrum in the grid's complex layout
+        cplx<R>* gp = reinterpret_cast<cplx<R>*>(grid);
+        for (int idx = threadIdx.x; idx < N * PL; idx += BD) gp[idx] = buf[idx];
+    }
+    const double tot = block_sum(e, red);
+    if (threadIdx.x == 0) epart[S.col_off] = 0.5 * tot;
+}
+
 #pragma clang fp contract(fast)
 
 // ---------------------------------------------------------------------------
@@ -340,11 +569,23 @@ static hipError_t allow_lds(K kernel, int bytes) {
 template <typename R, int N>
 static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode) {
     hipError_t e;
+    if constexpr (fused_fits<N, R>()) {
+        if (G.fused) {
+            // one kernel for the whole transform: launched at the first pass;
+            // mode packs (source 3 = real grid) x 4 + (x-pass mode)
+            if (which != 0) return hipSuccess;
+            const int lds = fft_fused_lds(N, L.prec);
+            if ((e = allow_lds(k_fft3d<R, N>, lds)) != hipSuccess) return e;
+            k_fft3d<R, N><<<G.sys_count, kFusedThreads, lds, L.stream>>>(L.sys, L.fsys + G.sys_off, L.epart,
+                                                                          (mode & 3) == 3 ? 0 : 1, mode >> 2);
+            return hipGetLastError();
+        }
+    }
     const int lds_plane = fft_plane_lds(N, L.prec);
     if (which == 0) {
         if ((e = allow_lds(k_fwd_zy<R, N>, lds_plane)) != hipSuccess) return e;
         k_fwd_zy<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(L.sys, L.planes + G.plane_off,
-                                                                                   mode == 3 ? 0 : 1);
+                                                                                   (mode & 3) == 3 ? 0 : 1);
     } else if (which == 1) {
         const int lds = fft_x_lds(N, L.prec);
         if ((e = allow_lds(k_fft_x<R, N>, lds)) != hipSuccess) return e;

@@ -31,6 +31,7 @@ struct Launch {
     int n_planes;
     const int4* cols;     // (sys, first column, columns, 0), grouped by grid size
     int n_cols;
+    const int2* fsys;     // (sys, 0) of systems on the one-block transform, grouped by grid size
     int hist_lds;         // LDS bytes of the per-chunk histogram
     double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
     double* epart;        // per x-column item: k-space energy partial
@@ -39,8 +40,10 @@ struct Launch {
 // Systems sharing one grid size n: one launch per FFT pass.
 struct FftGroup {
     int n;
-    int plane_off, plane_count;  // x-plane work items
-    int col_off, col_count;      // x-column chunk work items
+    int fused;                   // 1: one block per system for the whole transform
+    int plane_off, plane_count;  // x-plane work items (three-pass path)
+    int col_off, col_count;      // x-column chunk work items (three-pass path)
+    int sys_off, sys_count;      // system work items (fused path)
 };
 
 // Grid sizes with FFT kernels (even 2^a 3^b up to 144).
@@ -62,6 +65,12 @@ inline int fft_x_lds(int n, int prec) {
     const int rb = prec == 64 ? 8 : 4;
     return (n + n * fft_x_columns(prec)) * 2 * rb;
 }
+// Dynamic LDS of the one-block transform (twiddles, the whole half spectrum,
+// covering tables); the path is taken when this fits in 160 KB.
+inline int fft_fused_lds(int n, int prec) {
+    const int rb = prec == 64 ? 8 : 4;
+    return (n + n * n * (n / 2 + 1)) * 2 * rb + (n + 1) * 9 * 4;
+}
 
 // Preparation phases: 0 per-chunk bin histograms, 1 scan, 2 scatter into
 // bin order and deal each bin into LDS bank classes.
@@ -69,9 +78,11 @@ hipError_t launch_prepare(const Launch& L, int phase);
 hipError_t launch_spread(const Launch& L, const Group& G);
 // Diagnostics: fold the spread tiles into the real grid.
 hipError_t launch_fold(const Launch& L);
-// which: 0 forward z/y planes (mode 3: read the real grid instead of the
-// spread tiles), 1 x-columns with scaling (mode 0 full, 1 forward only,
-// 2 forward + scaling), 2 inverse y/z planes.
+// which: 0 forward z/y planes, 1 x-columns with scaling, 2 inverse y/z
+// planes. For which = 0, mode & 3 == 3 reads the real grid instead of the
+// spread tiles and mode >> 2 is the x-pass mode; for which = 1 the mode is
+// 0 full, 1 forward only, 2 forward + scaling. A fused group runs its whole
+// transform at which = 0 (with mode >> 2) and nothing at 1 and 2.
 hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode);
 hipError_t launch_gather(const Launch& L, const Group& G);
 hipError_t launch_finalize(const Launch& L, double* E_dev);

@@ -239,7 +239,7 @@ esp_status enqueue(esp_plan* p, double* E_dev, int upto, const void* grid_in) {
         }
     }
     const int xmode = upto == 2 ? 1 : upto == 3 ? 2 : 0;
-    if ((s = run_phase(p, kFftZY, E_dev, grid_in ? 3 : 0)) != ESP_OK) return s;
+    if ((s = run_phase(p, kFftZY, E_dev, (grid_in ? 3 : 0) | (xmode << 2))) != ESP_OK) return s;
     if ((s = run_phase(p, kFftX, E_dev, xmode)) != ESP_OK) return s;
     if (upto == 2 || upto == 3) return ESP_OK;
     if ((s = run_phase(p, kFftYZ, E_dev, 0)) != ESP_OK) return s;
@@ -464,21 +464,30 @@ esp_status esp_plan_autotune(esp_plan* plan, const void* pos, const void* q, voi
         const std::vector<int>& sys = g.second;
         const esp_params& r0 = plan->prm[sys[0]];
         const std::vector<int> cand = tile_candidates(r0.nf, r0.P);
-        if (cand.size() < 2) continue;
-        int best = plan->prm[sys[0]].tile;
+        const int npaths = fft_fused_lds(r0.nf, plan->prec) <= kMaxLds ? 2 : 1;
+        if (cand.size() * npaths < 2) continue;
+        int best = plan->prm[sys[0]].tile, best_path = plan->prm[sys[0]].fft_passes;
         double best_ms = 1e30;
-        for (int T : cand) {
-            for (int s : sys) plan->prm[s].tile = T;
-            if ((st = assemble(plan)) != ESP_OK) break;
-            double ms = 0.0;
-            if ((st = time_steps(&ms)) != ESP_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = T;
+        for (int path = 0; path < npaths && st == ESP_OK; ++path)
+            for (int T : cand) {
+                for (int s : sys) {
+                    plan->prm[s].tile = T;
+                    plan->prm[s].fft_passes = path;
+                }
+                if ((st = assemble(plan)) != ESP_OK) break;
+                double ms = 0.0;
+                if ((st = time_steps(&ms)) != ESP_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = T;
+                    best_path = path;
+                }
             }
-        }
         if (st != ESP_OK) break;
-        for (int s : sys) plan->prm[s].tile = best;
+        for (int s : sys) {
+            plan->prm[s].tile = best;
+            plan->prm[s].fft_passes = best_path;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

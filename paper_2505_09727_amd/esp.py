@@ -28,7 +28,7 @@ class EspError(RuntimeError):
 
 class esp_params(C.Structure):
     _fields_ = [("nf", C.c_int), ("P", C.c_int), ("degree", C.c_int), ("precision", C.c_int),
-                ("tile", C.c_int), ("deterministic", C.c_int),
+                ("tile", C.c_int), ("fft_passes", C.c_int),
                 ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
                 ("s0", C.c_double)]

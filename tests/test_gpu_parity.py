@@ -65,19 +65,22 @@ def _influence(n, L, P, c, rc, c1):
 FFT_SIZES = [8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72, 96, 108, 128, 144]
 
 
+@pytest.mark.parametrize("passes", [0, 1])
 @pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("n", FFT_SIZES)
-def test_fft_stages_match_textbook_dft(n, prec):
-    """Every grid size with FFT kernels: forward transform, scaling and inverse
-    against the textbook DFT of the reference (one system, real grid input)."""
+def test_fft_stages_match_textbook_dft(n, prec, passes):
+    """Every grid size with FFT kernels, on both paths (passes 0: three
+    passes; 1: one kernel per system where the half spectrum fits in LDS):
+    forward transform, scaling and inverse against the textbook DFT of the
+    reference (one system, real grid input)."""
     rng = np.random.default_rng(n)
     L = 1.25 * n
     if prec == 64 and n == 144:
         # one FP64 half-spectrum plane of 144 x 73 exceeds the 160 KB LDS
         with pytest.raises(EspError):
-            Plan(L, 2, 1e-4, nf=n, precision=prec, P=6)
+            Plan(L, 2, 1e-4, nf=n, precision=prec, P=6, fft_passes=passes)
         return
-    plan = Plan(L, 2, 1e-4, nf=n, precision=prec, P=min(6, n))
+    plan = Plan(L, 2, 1e-4, nf=n, precision=prec, P=min(6, n), fft_passes=passes)
     b = np.zeros((n, n, n + 2))
     b[:, :, :n] = rng.standard_normal((n, n, n))
     gin = _t(b.ravel(), prec)
