@@ -89,14 +89,38 @@ __global__ void __launch_bounds__(kChunkThreads) k_hist(const SysDesc* __restric
     }
 }
 
-// Exclusive scan of a system's bin-major count matrix (one block per system):
-// the entry (bin, item) becomes the first sorted slot of that chunk's
-// particles in that bin; bin_start[bin] is the first slot of the bin. Also
-// the fixed-point scale of the FP32 spread: 2^F with every single
-// contribution |q w_x w_y w_z| 2^F <= 2^30, so it is exact through int32.
+// Exclusive scan of each bin's row of the count matrix (one wave per bin):
+// entry (bin, item) becomes the first slot of that chunk's particles within
+// the bin, and the bin's total goes to bin_start[bin] (turned into the bin's
+// first slot by k_scan).
+__global__ void __launch_bounds__(256) k_scan_rows(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                   int n_items) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_items) return;  // uniform over the wave
+    const int2 wi = items[w];
+    const SysDesc& S = sys[wi.x];
+    const int lane = threadIdx.x & 63;
+    int* row = S.hist + (size_t)wi.y * S.npitem;
+    int carry = 0;
+    for (int base = 0; base < S.npitem; base += 64) {
+        const int l = base + lane;
+        const int v = l < S.npitem ? row[l] : 0;
+        int x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (l < S.npitem) row[l] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) S.bin_start[wi.y] = carry;
+}
+
+// Per system (one block): exclusive scan of the bin totals into the bins'
+// first slots, and the fixed-point scale of the FP32 spread: 2^F with every
+// single term |q w_x w_y w_z| 2^F <= 2^30, so it is exact through int32.
 __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, const double* __restrict__ bpart) {
     __shared__ int warp_tot[16];
-    __shared__ int carry_s;
     __shared__ double red[16];
     const SysDesc& S = sys[blockIdx.x];
     {
@@ -110,32 +134,25 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
         }
     }
     const int t1 = S.tiles1, nb = t1 * t1 * t1;
-    const int total = nb * S.npitem;
-    int* hist = S.hist;
-    if (threadIdx.x == 0) carry_s = 0;
+    // each thread owns a contiguous run of bins (at most a few)
+    const int per = (nb + blockDim.x - 1) / blockDim.x;
+    const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+    int run = 0;
+    for (int b = b0; b < b1; ++b) run += S.bin_start[b];
+    int x = run;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) warp_tot[wid] = x;
     __syncthreads();
-    for (int base = 0; base < total; base += blockDim.x) {
-        const int l = base + threadIdx.x;
-        const int v = l < total ? hist[l] : 0;
-        int x = v;
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) warp_tot[wid] = x;
-        __syncthreads();
-        int before = 0;
-        for (int w = 0; w < wid; ++w) before += warp_tot[w];
-        const int carry = carry_s;
-        if (l < total) {
-            const int off = carry + before + x - v;
-            hist[l] = off;
-            if (l % S.npitem == 0) S.bin_start[l / S.npitem] = off;
-        }
-        __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) carry_s = carry + before + x;
-        __syncthreads();
+    int off = x - run;
+    for (int w = 0; w < wid; ++w) off += warp_tot[w];
+    for (int b = b0; b < b1; ++b) {
+        const int v = S.bin_start[b];
+        S.bin_start[b] = off;
+        off += v;
     }
     if (threadIdx.x == 0) S.bin_start[nb] = S.N;
 }
@@ -170,7 +187,8 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
             const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
             const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
             const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
-            const int dst = hcol[bin_of(ux, uy, uz, S) * S.npitem] + S.rank[il];
+            const int bin = bin_of(ux, uy, uz, S);
+            const int dst = S.bin_start[bin] + hcol[bin * S.npitem] + S.rank[il];
             typename Vec4<R>::type v;
             v.x = ux;
             v.y = uy;
@@ -707,6 +725,10 @@ static hipError_t prepare_t(const Launch& L, int phase) {
             k_hist<R><<<L.n_pitems, kChunkThreads, L.hist_lds, L.stream>>>(L.sys, L.pitems, L.bpart);
             break;
         case 1:
+            if (L.n_titems > 0) {
+                k_scan_rows<<<(L.n_titems + 3) / 4, 256, 0, L.stream>>>(L.sys, L.titems, L.n_titems);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
             k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.bpart);
             break;
         case 2: {
