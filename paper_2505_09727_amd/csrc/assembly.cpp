@@ -150,7 +150,7 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
 }
 
 LaunchSet::~LaunchSet() {
-    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_fsys_, d_cols_, d_bpart_, d_epart_};
+    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_, d_cols_, d_bpart_, d_epart_};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -190,8 +190,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     groups_.clear();
     fgroups_.clear();
     fsys_.clear();
+    bsys_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
-    int nb_max = 1;
+    int nb_max = 1, nb_small_max = 1;
     for (int s = 0; s < nsys; ++s) {
         const SystemSlot& sl = systems[s];
         const esp_params& r = sl.prm;
@@ -202,6 +203,8 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.N = (int)sl.N;
         d.T = r.tile;
         d.tiles1 = r.nf / r.tile;
+        d.mT = (int)(((1 << 20) + d.T - 1) / d.T);
+        d.mt1 = (int)(((1 << 20) + d.tiles1 - 1) / d.tiles1);
         d.E = tile_edge(r);
         d.degree = r.degree;
         d.inv_L = 1.0 / r.L;
@@ -231,7 +234,13 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         for (int c = 0; c < d.N; c += kParticleChunk) pitems_.push_back(make_int2(s, c));
         d.npitem = (int)pitems_.size() - d.pitem_off;
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
-        nb_max = std::max(nb_max, nb);
+        d.small = d.N <= kSmallMaxN && nb <= kSmallMaxBins;
+        if (d.small) {
+            bsys_.push_back(make_int2(s, 0));
+            nb_small_max = std::max(nb_small_max, nb);
+        } else {
+            nb_max = std::max(nb_max, nb);
+        }
         for (int t = 0; t < nb; ++t) titems_by_P[r.P].push_back(make_int2(s, t));
         if (!fft_size_supported(r.nf)) {
             msg = "no FFT kernels for this grid size";
@@ -315,6 +324,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.n_planes = (int)planes_.size();
     L_.n_cols = (int)cols_.size();
     L_.hist_lds = nb_max * 4;
+    L_.n_small = (int)bsys_.size();
+    L_.n_large = nsys - L_.n_small;
+    L_.small_lds = (nb_small_max * 32 + 2 * (nb_small_max + 1) + 2 * kSmallRounds) * 4;
     if (L_.hist_lds > kMaxLds) {
         msg = "too many bins per system; raise tile";
         return ESP_E_UNSUPPORTED;
@@ -326,6 +338,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     if ((st = put(&d_planes_, &cap_planes_, planes_, msg)) != ESP_OK) return st;
     if ((st = put(&d_cols_, &cap_cols_, cols_, msg)) != ESP_OK) return st;
     if ((st = put(&d_fsys_, &cap_fsys_, fsys_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_bsys_, &cap_bsys_, bsys_, msg)) != ESP_OK) return st;
     // partial sums are written before they are read: capacity only
     auto reserve = [&](double** dev, size_t* cap, size_t need) {
         if (need <= *cap && *dev) return ESP_OK;
@@ -348,6 +361,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.planes = d_planes_;
     L_.cols = d_cols_;
     L_.fsys = d_fsys_;
+    L_.bsys = d_bsys_;
     L_.bpart = d_bpart_;
     L_.epart = d_epart_;
     return ESP_OK;

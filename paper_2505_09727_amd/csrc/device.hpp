@@ -21,7 +21,9 @@ struct SysDesc {
     int pitem_off;    // ... starting at this index of the launch's list
     int ncol;         // x-column work items ...
     int col_off;      // ... starting here
-    int pad0;
+    int small;        // 1: binned by one block (k_bin_small), 0: chunked kernels
+    int mT;           // ceil(2^20 / T): x / T == (x mT) >> 20 for 0 <= x < 2^20 / T
+    int mt1;          // ceil(2^20 / tiles1), likewise
     double inv_L;     // 1/L
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
@@ -58,6 +60,12 @@ struct SysDesc {
 //   plane:          (sys, x)
 //   x-column block: (sys, first flattened (ky, kz) column, columns, 0)
 
+#ifndef ESP_SMALL_MAX_N
+#define ESP_SMALL_MAX_N 65536
+#endif
+constexpr int kSmallMaxN = ESP_SMALL_MAX_N;  // systems up to this size ...
+constexpr int kSmallMaxBins = 512;    // ... and bin count are binned by one block
+constexpr int kSmallRounds = 8192;    // deal rounds a one-block binning can hold
 constexpr int kParticleChunk = 1024;  // particles per chunk work item
 constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
 constexpr int kOutDoubles = 8;

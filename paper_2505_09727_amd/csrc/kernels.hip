@@ -19,6 +19,12 @@
 
 namespace esp {
 
+// x / d for 0 <= x < 2^20 / d with m = ceil(2^20 / d) (the error term of m
+// times x stays below 2^20).
+__device__ __forceinline__ int fdiv(int x, int m) {
+    return (int)(((unsigned long long)(unsigned)x * (unsigned)m) >> 20);
+}
+
 // Grid coordinate u in [0, n) of one position component.
 template <typename R>
 __device__ __forceinline__ R grid_coord(R x, R inv_L, int n) {
@@ -32,10 +38,27 @@ __device__ __forceinline__ R grid_coord(R x, R inv_L, int n) {
 
 // Bin of a particle: cells floor(u) grouped into T^3 blocks (T divides n).
 template <typename R>
-__device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
+__device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S, int& tx, int& ty, int& tz) {
     const int nm1 = S.n - 1;
     const int cx = min((int)ux, nm1), cy = min((int)uy, nm1), cz = min((int)uz, nm1);
-    return (cx / S.T * S.tiles1 + cy / S.T) * S.tiles1 + cz / S.T;
+    tx = fdiv(cx, S.mT);
+    ty = fdiv(cy, S.mT);
+    tz = fdiv(cz, S.mT);
+    return (tx * S.tiles1 + ty) * S.tiles1 + tz;
+}
+
+template <typename R>
+__device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
+    int tx, ty, tz;
+    return bin_of(ux, uy, uz, S, tx, ty, tz);
+}
+
+// Coordinates (tx, ty, tz) of bin t.
+__device__ __forceinline__ void bin_coords(int t, const SysDesc& S, int& tx, int& ty, int& tz) {
+    const int r = fdiv(t, S.mt1);
+    tz = t - r * S.tiles1;
+    tx = fdiv(r, S.mt1);
+    ty = r - tx * S.tiles1;
 }
 
 // ---------------------------------------------------------------------------
@@ -55,6 +78,7 @@ __global__ void __launch_bounds__(kChunkThreads) k_hist(const SysDesc* __restric
     __shared__ double red[64];
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
+    if (S.small) return;  // uniform over the block
     const int n = S.n, t1 = S.tiles1, nb = t1 * t1 * t1;
     for (int b = threadIdx.x; b < nb; b += kChunkThreads) cnt[b] = 0;
     __syncthreads();
@@ -99,6 +123,7 @@ __global__ void __launch_bounds__(256) k_scan_rows(const SysDesc* __restrict__ s
     if (w >= n_items) return;  // uniform over the wave
     const int2 wi = items[w];
     const SysDesc& S = sys[wi.x];
+    if (S.small) return;  // uniform over the wave
     const int lane = threadIdx.x & 63;
     int* row = S.hist + (size_t)wi.y * S.npitem;
     int carry = 0;
@@ -123,6 +148,7 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
     __shared__ int warp_tot[16];
     __shared__ double red[16];
     const SysDesc& S = sys[blockIdx.x];
+    if (S.small) return;  // uniform over the block
     {
         double qm = 0.0;
         for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) qm = fmax(qm, bpart[4 * (S.pitem_off + i) + 3]);
@@ -176,6 +202,7 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
                                                            const int2* __restrict__ items) {
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
+    if (S.small) return;  // uniform over the block
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R inv_L = R(S.inv_L);
     const int n = S.n;
@@ -241,6 +268,7 @@ __global__ void __launch_bounds__(256) k_deal(const SysDesc* __restrict__ sys, c
     __shared__ int maxc_s;
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
+    if (S.small) return;  // uniform over the block
     const int t = wi.y, T = S.T, t1 = S.tiles1, E = S.E;
     const int beg = S.bin_start[t], count = S.bin_start[t + 1] - beg;
     if (count == 0) return;  // uniform over the block
@@ -249,7 +277,8 @@ __global__ void __launch_bounds__(256) k_deal(const SysDesc* __restrict__ sys, c
     V* dst = reinterpret_cast<V*>(S.sorted) + beg;
     int* dstp = S.perm + beg;
     int* key = S.rank + beg;  // free after the scatter; keys beyond the registers
-    const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+    int tx, ty, tz;
+    bin_coords(t, S, tx, ty, tz);
     const int lo = -((S.P - 1) / 2);
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const R hp = R(0.5) * R(S.P);
@@ -475,7 +504,8 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
     const int t = wi.y, T = S.T, t1 = S.tiles1;
-    const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+    int tx, ty, tz;
+    bin_coords(t, S, tx, ty, tz);
     const int lo = -((P - 1) / 2);
     const int E = S.E, E3 = E * E * E;
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
@@ -560,7 +590,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
     const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
-    const int tz = t % t1, ty = (t / t1) % t1, tx = t / (t1 * t1);
+    int tx, ty, tz;
+    bin_coords(t, S, tx, ty, tz);
     const int lo = -((P - 1) / 2);
     const int E = S.E, E3 = E * E * E;
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
@@ -706,6 +737,208 @@ __global__ void __launch_bounds__(kChunkThreads) k_drift(const SysDesc* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Binning of a small system by one block, in place of k_hist, the scans, the
+// scatter and the deal: LDS counters per (bin, bank class), the bins' first
+// slots, the deal's rounds per bin, and one write of every particle to its
+// dealt slot. The order is the one k_deal produces (round j of a bin holds the
+// j-th particle of every class present, in class order), up to the order of
+// particles within a (bin, class), which the LDS counters leave open and which
+// no result depends on. If the rounds exceed kSmallRounds the bins are written
+// class by class instead. The charge statistics go to the system's first
+// chunk slot (the others are zeroed) and the fixed-point scale to out[4].
+
+constexpr int kSmallBatch = 8;
+
+template <typename R>
+__device__ __forceinline__ void small_bin_class(const SysDesc& S, R x, R y, R z, R inv_L, R hp, int lo, R& ux,
+                                                R& uy, R& uz, int& b, int& c) {
+    const int n = S.n, T = S.T, t1 = S.tiles1, E = S.E;
+    ux = grid_coord(x, inv_L, n);
+    uy = grid_coord(y, inv_L, n);
+    uz = grid_coord(z, inv_L, n);
+    int tx, ty, tz;
+    b = bin_of(ux, uy, uz, S, tx, ty, tz);
+    const int bx = (int)floor(ux - hp) + 1 - (tx * T + lo);
+    const int by = (int)floor(uy - hp) + 1 - (ty * T + lo);
+    const int bz = (int)floor(uz - hp) + 1 - (tz * T + lo);
+    c = ((bx * E + by) * E + bz) & 31;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                    double* __restrict__ bpart) {
+    using V = typename Vec4<R>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[64];
+    __shared__ int deal_s;
+    const SysDesc& S = sys[items[blockIdx.x].x];
+    const int t1 = S.tiles1, nb = t1 * t1 * t1, N = S.N;
+    int* cnt = reinterpret_cast<int*>(smem_raw);  // nb x 32
+    int* binoff = cnt + nb * 32;                  // nb + 1
+    int* rbase = binoff + nb + 1;                 // nb + 1: first round of each bin
+    int* rstart = rbase + nb + 1;                 // kSmallRounds
+    unsigned* rmask = reinterpret_cast<unsigned*>(rstart + kSmallRounds);
+    const R* pos = reinterpret_cast<const R*>(S.pos);
+    const R* q = reinterpret_cast<const R*>(S.q);
+    const R inv_L = R(S.inv_L), hp = R(0.5) * R(S.P);
+    const int lo = -((S.P - 1) / 2);
+    for (int i = threadIdx.x; i < nb * 32; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    double sq = 0.0, sa = 0.0, s2 = 0.0, qm = 0.0;
+    // batches of kSmallBatch particles per thread: every load of a batch is
+    // issued before any is used
+    for (int base = 0; base < N; base += kSmallBatch * 1024) {
+        R px[kSmallBatch], py[kSmallBatch], pz[kSmallBatch], pq[kSmallBatch];
+#pragma unroll
+        for (int k = 0; k < kSmallBatch; ++k) {
+            const int i = base + k * 1024 + threadIdx.x;
+            if (i < N) {
+                px[k] = pos[3 * i + 0];
+                py[k] = pos[3 * i + 1];
+                pz[k] = pos[3 * i + 2];
+                pq[k] = q[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSmallBatch; ++k) {
+            const int i = base + k * 1024 + threadIdx.x;
+            if (i < N) {
+                R ux, uy, uz;
+                int b, c;
+                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, hp, lo, ux, uy, uz, b, c);
+                S.rank[i] = atomicAdd(&cnt[b * 32 + c], 1);
+                const double qq = (double)pq[k];
+                sq += qq;
+                sa += fabs(qq);
+                s2 += qq * qq;
+                qm = fmax(qm, fabs(qq));
+            }
+        }
+    }
+    block_sum3_max(sq, sa, s2, qm, red);  // also orders the counters
+    if (threadIdx.x == 0) {
+        double* bp = bpart + 4 * S.pitem_off;
+        bp[0] = sq;
+        bp[1] = sa;
+        bp[2] = s2;
+        bp[3] = qm;
+        const double bound = qm * S.wmax3;
+        const int F = bound > 0.0 ? 30 - (int)ceil(log2(bound)) : 30;
+        S.out[4] = ldexp(1.0, max(-100, min(100, F)));
+    }
+    for (int k = 1 + threadIdx.x; k < S.npitem; k += blockDim.x)
+        for (int j = 0; j < 4; ++j) bpart[4 * (S.pitem_off + k) + j] = 0.0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // per bin (one wave per bin): particle total and largest class
+    for (int b = wid; b < nb; b += nw) {
+        const int cl = lane < 32 ? cnt[b * 32 + lane] : 0;
+        int t = cl, m = cl;
+        for (int off = 32; off > 0; off >>= 1) {
+            t += __shfl_xor(t, off, 64);
+            m = max(m, __shfl_xor(m, off, 64));
+        }
+        if (lane == 0) {
+            binoff[b] = t;
+            rbase[b] = m;
+        }
+    }
+    __syncthreads();
+    // exclusive scans over bins of the totals and of the round counts (wave 0)
+    if (wid == 0) {
+        int ct = 0, cr = 0;
+        for (int base = 0; base < nb; base += 64) {
+            const int l = base + lane;
+            const int vt = l < nb ? binoff[l] : 0, vr = l < nb ? rbase[l] : 0;
+            int xt = vt, xr = vr;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int yt = __shfl_up(xt, off, 64), yr = __shfl_up(xr, off, 64);
+                if (lane >= off) {
+                    xt += yt;
+                    xr += yr;
+                }
+            }
+            if (l < nb) {
+                binoff[l] = ct + xt - vt;
+                rbase[l] = cr + xr - vr;
+            }
+            ct += __shfl(xt, 63, 64);
+            cr += __shfl(xr, 63, 64);
+        }
+        if (lane == 0) {
+            binoff[nb] = ct;
+            rbase[nb] = cr;
+            deal_s = cr <= kSmallRounds;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b <= nb; b += blockDim.x) S.bin_start[b] = binoff[b];
+    const bool deal = deal_s;
+    for (int b = wid; b < nb; b += nw) {
+        const int cl = lane < 32 ? cnt[b * 32 + lane] : 0;
+        if (deal) {
+            const int r0 = rbase[b], nr = rbase[b + 1] - r0;
+            int run = 0;
+            for (int j = 0; j < nr; ++j) {
+                const unsigned m = (unsigned)__ballot(cl > j);
+                if (lane == 0) {
+                    rstart[r0 + j] = run;
+                    rmask[r0 + j] = m;
+                }
+                run += __popc(m);
+            }
+        } else {
+            // class-major order: exclusive scan of the class counts of the bin
+            int x = cl;
+            for (int off = 1; off < 32; off <<= 1) {
+                const int y = __shfl_up(x, off, 64);
+                if (lane >= off) x += y;
+            }
+            if (lane < 32) cnt[b * 32 + lane] = x - cl;
+        }
+    }
+    __syncthreads();
+    V* sorted = reinterpret_cast<V*>(S.sorted);
+    for (int base = 0; base < N; base += kSmallBatch * 1024) {
+        R px[kSmallBatch], py[kSmallBatch], pz[kSmallBatch], pq[kSmallBatch];
+        int pr[kSmallBatch];
+#pragma unroll
+        for (int k = 0; k < kSmallBatch; ++k) {
+            const int i = base + k * 1024 + threadIdx.x;
+            if (i < N) {
+                px[k] = pos[3 * i + 0];
+                py[k] = pos[3 * i + 1];
+                pz[k] = pos[3 * i + 2];
+                pq[k] = q[i];
+                pr[k] = S.rank[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSmallBatch; ++k) {
+            const int i = base + k * 1024 + threadIdx.x;
+            if (i < N) {
+                R ux, uy, uz;
+                int b, c;
+                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, hp, lo, ux, uy, uz, b, c);
+                int p = binoff[b];
+                if (deal) {
+                    const int j = rbase[b] + pr[k];
+                    p += rstart[j] + __popc(rmask[j] & ((1u << c) - 1u));
+                } else {
+                    p += cnt[b * 32 + c] + pr[k];
+                }
+                V v;
+                v.x = ux;
+                v.y = uy;
+                v.z = uz;
+                v.w = pq[k];
+                sorted[p] = v;
+                S.perm[p] = i;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -721,10 +954,17 @@ static hipError_t prepare_t(const Launch& L, int phase) {
     hipError_t e;
     switch (phase) {
         case 0:
+            if (L.n_small > 0) {
+                if ((e = allow_lds(k_bin_small<R>, L.small_lds)) != hipSuccess) return e;
+                k_bin_small<R><<<L.n_small, 1024, L.small_lds, L.stream>>>(L.sys, L.bsys, L.bpart);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+            if (L.n_large == 0) break;
             if ((e = allow_lds(k_hist<R>, L.hist_lds)) != hipSuccess) return e;
             k_hist<R><<<L.n_pitems, kChunkThreads, L.hist_lds, L.stream>>>(L.sys, L.pitems, L.bpart);
             break;
         case 1:
+            if (L.n_large == 0) break;
             if (L.n_titems > 0) {
                 k_scan_rows<<<(L.n_titems + 3) / 4, 256, 0, L.stream>>>(L.sys, L.titems, L.n_titems);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -732,6 +972,7 @@ static hipError_t prepare_t(const Launch& L, int phase) {
             k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.bpart);
             break;
         case 2: {
+            if (L.n_large == 0) break;
             k_scatter<R><<<L.n_pitems, kChunkThreads, 0, L.stream>>>(L.sys, L.pitems);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (L.n_titems > 0) k_deal<R><<<L.n_titems, 256, 0, L.stream>>>(L.sys, L.titems);

@@ -33,6 +33,10 @@ struct Launch {
     int n_cols;
     const int2* fsys;     // (sys, 0) of systems on the one-block transform, grouped by grid size
     int hist_lds;         // LDS bytes of the per-chunk histogram
+    int n_large;          // systems binned by the chunked kernels
+    const int2* bsys;     // (sys, 0) of systems binned by one block
+    int n_small;
+    int small_lds;        // LDS bytes of the one-block binning
     double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
     double* epart;        // per x-column item: k-space energy partial
 };
