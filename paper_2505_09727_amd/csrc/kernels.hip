@@ -522,8 +522,12 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
     const int deg = S.degree;
     const R scale = kFixed ? R(S.out[4]) : R(1);
     const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
+    // each thread's next particle is loaded while the current one is spread
+    typename Vec4<R>::type vn{};
+    if (beg + (int)threadIdx.x < end) vn = sorted[beg + threadIdx.x];
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
-        const typename Vec4<R>::type v = sorted[k];
+        const typename Vec4<R>::type v = vn;
+        if (k + (int)blockDim.x < end) vn = sorted[k + blockDim.x];
         R w[3][P];
         int l0[3];
         windows3<R, P>(v.x, v.y, v.z, ct, deg, w, l0);
