@@ -376,9 +376,10 @@ __device__ __forceinline__ void stage_coef(R* __restrict__ ct, R* __restrict__ c
 // polynomial pieces at y = frac(u - P/2) - 1/2 (|y| <= 1/2), summed as
 // sum_m c[m][j] y^m with a running power of y, so every term is one
 // accumulate and each power's coefficients are read from LDS once for all
-// three axes. Weights are clamped at zero (the window is positive on its
-// support; the clamp only removes rounding noise at the support's edge).
-// l0[a] is the first grid index of axis a's support.
+// three axes (the sums start at c[0] + c[1] y, degree >= 4). Weights are
+// clamped at zero (the window is positive on its support; the clamp only
+// removes rounding noise at the support's edge, and the fixed-point spread
+// relies on it). l0[a] is the first grid index of axis a's support.
 template <typename R, int P>
 __device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__ ct, int deg, R (&w)[3][P],
                                          int (&l0)[3]) {
@@ -390,15 +391,16 @@ __device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__
         const R f = floor(u[a] - hp);
         y[a] = (u[a] - hp) - f - R(0.5);
         l0[a] = (int)f + 1;
-        yp[a] = y[a];
+        yp[a] = y[a] * y[a];
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        const R c = ct[j];
+        const R c0 = ct[j], c1 = ct[P + j];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) w[a][j] = c;
+        for (int a = 0; a < 3; ++a) w[a][j] = c1 * y[a] + c0;
     }
-    for (int m = 1; m <= deg; ++m) {
+#pragma unroll 1
+    for (int m = 2; m <= deg; ++m) {
         R c[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) c[j] = ct[m * P + j];
@@ -415,8 +417,8 @@ __device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__
         for (int j = 0; j < P; ++j) w[a][j] = fmax(w[a][j], R(0));
 }
 
-// As windows3, with the derivatives d w / d u from the staged derivative
-// coefficients ctd (sum_m (m + 1) c[m + 1][j] y^m).
+// As windows3 without the clamp, with the derivatives d w / d u from the
+// staged derivative coefficients ctd (sum_m (m + 1) c[m + 1][j] y^m).
 template <typename R, int P>
 __device__ __forceinline__ void windows3_d(R ux, R uy, R uz, const R* __restrict__ ct, const R* __restrict__ ctd,
                                            int deg, R (&w)[3][P], R (&dw)[3][P], int (&l0)[3]) {
@@ -428,18 +430,19 @@ __device__ __forceinline__ void windows3_d(R ux, R uy, R uz, const R* __restrict
         const R f = floor(u[a] - hp);
         y[a] = (u[a] - hp) - f - R(0.5);
         l0[a] = (int)f + 1;
-        yp[a] = y[a];
+        yp[a] = y[a] * y[a];
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        const R c = ct[j], d = ctd[j];
+        const R c0 = ct[j], c1 = ct[P + j], d0 = ctd[j], d1 = ctd[P + j];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            w[a][j] = c;
-            dw[a][j] = d;
+            w[a][j] = c1 * y[a] + c0;
+            dw[a][j] = d1 * y[a] + d0;
         }
     }
-    for (int m = 1; m <= deg; ++m) {
+#pragma unroll 1
+    for (int m = 2; m <= deg; ++m) {
         R c[P], d[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -456,10 +459,6 @@ __device__ __forceinline__ void windows3_d(R ux, R uy, R uz, const R* __restrict
             yp[a] *= y[a];
         }
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int j = 0; j < P; ++j) w[a][j] = fmax(w[a][j], R(0));
 }
 
 __device__ __forceinline__ int wrapi(int g, int n) {
