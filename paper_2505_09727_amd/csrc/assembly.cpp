@@ -192,7 +192,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     fsys_.clear();
     bsys_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
-    int nb_max = 1, nb_small_max = 1;
+    int nb_max = 1, nb_small_max = 1, n_eligible = 0;
     for (int s = 0; s < nsys; ++s) {
         const SystemSlot& sl = systems[s];
         const esp_params& r = sl.prm;
@@ -235,12 +235,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.npitem = (int)pitems_.size() - d.pitem_off;
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
         d.small = d.N <= kSmallMaxN && nb <= kSmallMaxBins;
-        if (d.small) {
-            bsys_.push_back(make_int2(s, 0));
-            nb_small_max = std::max(nb_small_max, nb);
-        } else {
-            nb_max = std::max(nb_max, nb);
-        }
+        if (d.small) ++n_eligible;
         for (int t = 0; t < nb; ++t) titems_by_P[r.P].push_back(make_int2(s, t));
         if (!fft_size_supported(r.nf)) {
             msg = "no FFT kernels for this grid size";
@@ -249,6 +244,20 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         if (fft_plane_lds(r.nf, prec) > kMaxLds) {
             msg = "grid too large for the LDS-resident plane FFT at this precision";
             return ESP_E_UNSUPPORTED;
+        }
+    }
+    // one block per system bins a system faster than the chunked kernels only
+    // when enough systems share the launch to fill the GPU (the particle order
+    // within a bin, which is all the path changes, affects no result)
+    for (int s = 0; s < nsys; ++s) {
+        SysDesc& d = hsys_[s];
+        const int nb = d.tiles1 * d.tiles1 * d.tiles1;
+        if (n_eligible < kSmallMinSystems) d.small = 0;
+        if (d.small) {
+            bsys_.push_back(make_int2(s, 0));
+            nb_small_max = std::max(nb_small_max, nb);
+        } else {
+            nb_max = std::max(nb_max, nb);
         }
     }
     // FFT work items grouped by (grid size, path): one launch per group and
