@@ -118,7 +118,7 @@ template <typename R, int N> constexpr int x_threads() {
 // E = T + P - 1 + (P odd) <= T + 12 points and T >= 8). The loads of PG points
 // per thread are all issued before any is summed. The result goes to LDS in
 // pair-row order: rows 2r and 2r+1 are the real and imaginary parts of
-// complex row r.
+// complex row r, rows N + 1 complex values apart (conflict-free z stages).
 template <typename R, int N, int BD>
 __device__ __forceinline__ void fold_plane(R* __restrict__ bufr, const R* __restrict__ tiles, const SysDesc& S,
                                            const CoverTab* __restrict__ tab, const CoverTab& cx) {
@@ -157,7 +157,7 @@ __device__ __forceinline__ void fold_plane(R* __restrict__ bufr, const R* __rest
             const int idx = p0 + q * BD + (int)threadIdx.x;
             if ((NP % (PG * BD) == 0) || idx < NP) {
                 const int y = idx / N, z = idx - y * N;
-                bufr[2 * ((y >> 1) * N + z) + (y & 1)] = acc[q];
+                bufr[2 * ((y >> 1) * (N + 1) + z) + (y & 1)] = acc[q];
             }
         }
     }
@@ -185,11 +185,12 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __
     } else {
         for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
             const int r = idx / N, z = idx - r * N;
-            buf[idx] = {plane[(2 * r) * RL + z], plane[(2 * r + 1) * RL + z]};
+            buf[r * (N + 1) + z] = {plane[(2 * r) * RL + z], plane[(2 * r + 1) * RL + z]};
         }
     }
     __syncthreads();
-    fft_ct<R, N, 1, HALF, N, 1, BD, false, +1>(buf, tw);
+    // z: pair rows N + 1 apart, consecutive threads on consecutive rows
+    fft_ct<R, N, 1, HALF, N + 1, 1, BD, true, +1>(buf, tw);
     {
         constexpr int TOTAL = HALF * HS, IT = (TOTAL + BD - 1) / BD;
         cplx<R> A[IT], B[IT];
@@ -200,8 +201,8 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __
             o[it] = -1;
             if (item < TOTAL) {
                 const int r = item / HS, k = item - r * HS;
-                const cplx<R> zk = buf[r * N + k];
-                const cplx<R> zn = buf[r * N + (k == 0 ? 0 : N - k)];
+                const cplx<R> zk = buf[r * (N + 1) + k];
+                const cplx<R> zn = buf[r * (N + 1) + (k == 0 ? 0 : N - k)];
                 A[it] = {R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};
                 B[it] = {R(0.5) * (zk.y + zn.y), -R(0.5) * (zk.x - zn.x)};
                 o[it] = (2 * r) * HS + k;
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __
                 const cplx<R> a = buf[(2 * r) * HS + k], b = buf[(2 * r + 1) * HS + k];
                 Z[it] = {a.x - b.y, a.y + b.x};
                 Zc[it] = {a.x + b.y, b.x - a.y};
-                o[it] = r * N;
+                o[it] = r * (N + 1);
                 k_[it] = k;
             }
         }
@@ -266,10 +267,11 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __
             }
         __syncthreads();
     }
-    fft_ct<R, N, 1, HALF, N, 1, BD, false, -1>(buf, tw);
+    // z: pair rows N + 1 apart, consecutive threads on consecutive rows
+    fft_ct<R, N, 1, HALF, N + 1, 1, BD, true, -1>(buf, tw);
     for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
         const int r = idx / N, z = idx - r * N;
-        const cplx<R> v = buf[idx];
+        const cplx<R> v = buf[r * (N + 1) + z];
         plane[(2 * r) * RL + z] = v.x;
         plane[(2 * r + 1) * RL + z] = v.y;
     }
