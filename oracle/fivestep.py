@@ -18,7 +18,12 @@ Readings (listed in the design notes):
     phi^(xi) = prod_d (P h/2) int_{-1}^{1} psi^{c1}(t) cos(xi_d P h t/2) dt.
     p_0 = 0 (m = 0 dropped, tin-foil boundary).
   * Forces by the AD route: F_i = -q_i grad u~(r_i), differentiating the
-    window analytically.
+    window analytically (five_step), or by the "ik" route (five_step_ik):
+    the scaled spectrum is multiplied by the spectral derivative of the
+    inverse transform, c_l = sum_k exp(-2 pi i k.l/n) c^_k, i.e. by
+    -2 pi i m_d / L along axis d (m_d = k_d or k_d - n), with the factor 0 at
+    the Nyquist index k_d = n/2, whose two signed images cancel; each
+    gradient grid is then interpolated with the window itself.
   * Self term: phi_i = u~_i - q_i S(0); E = (1/2) sum_i q_i phi_i.
 """
 from __future__ import annotations
@@ -130,3 +135,35 @@ def five_step(pos, q, L, n, P, c, rc, c1):
     Ek = 0.5 * float(np.sum(p * np.abs(bhat) ** 2))
     return dict(b=b, bhat=bhat, p=p, chat=chat, c=cgrid, u_tilde=ut, grad=grad,
                 phi=phi, F=F, E=E, Ek=Ek, s0=s0)
+
+
+def ik_factors(n, L):
+    """Spectral derivative factors of one axis, index k in [0, n): the
+    derivative of exp(-2 pi i m x/L) is -2 pi i m/L times it (m = k or k - n);
+    0 at the Nyquist index n/2."""
+    k = np.arange(n)
+    m = np.where(k <= n // 2, k, k - n).astype(np.float64)
+    d = -2j * math.pi * m / L
+    d[n // 2] = 0.0
+    return d
+
+
+def five_step_ik(pos, q, L, n, P, c, rc, c1):
+    """Five-step method with forces by the "ik" route (Methods, force
+    paragraph): the potentials and energy are those of five_step; the force
+    on particle i is -q_i times the window interpolation of the three
+    gradient grids IFFT(d_ax c^)."""
+    base = five_step(pos, q, L, n, P, c, rc, c1)
+    d = ik_factors(n, L)
+    grids, grad = [], np.zeros((len(q), 3))
+    for ax in range(3):
+        shape = [1, 1, 1]
+        shape[ax] = n
+        g = dft3(base["chat"] * d.reshape(shape), -1)
+        grids.append(np.real(g))
+        grad[:, ax], _ = interpolate(pos, L, n, P, c1, np.real(g))
+    out = dict(base)
+    out["grad"] = grad
+    out["grad_grids"] = grids
+    out["F"] = -np.asarray(q, np.float64)[:, None] * grad
+    return out

@@ -136,3 +136,56 @@ def test_nacl_energy_and_madelung():
     assert abs(E_esp - E) < 1e-4 * abs(E)
     phi_tot = r["phi"] + ul
     assert np.max(np.abs(phi_tot - u)) < 1e-4 * np.max(np.abs(u))
+
+
+# ---------------------------------------------------------------- ik forces
+
+def test_ik_factors_differentiate_a_single_mode():
+    # c^ with one pair of modes +-m0 along y: c(x) = 2 cos(2 pi m0 y/L) on the
+    # grid (inverse transform c_l = sum exp(-2 pi i k.l/n) c^_k); its derivative
+    # is -(4 pi m0/L) sin(2 pi m0 y/L)
+    from oracle.fivestep import ik_factors
+    n, L, m0 = 12, 7.5, 3
+    chat = np.zeros((n, n, n), complex)
+    chat[0, m0, 0] = 1.0
+    chat[0, n - m0, 0] = 1.0
+    y = np.arange(n) * L / n
+    c = np.real(dft3(chat, -1))
+    assert np.allclose(c[0, :, 0], 2 * np.cos(2 * np.pi * m0 * y / L), atol=1e-12)
+    dy = np.real(dft3(chat * ik_factors(n, L).reshape(1, n, 1), -1))
+    assert np.allclose(dy[0, :, 0], -(4 * np.pi * m0 / L) * np.sin(2 * np.pi * m0 * y / L), atol=1e-12)
+    # the mode is constant along x and z, and so is its y-derivative
+    assert np.allclose(dy, np.broadcast_to(dy[:1, :, :1], dy.shape), atol=1e-12)
+    for ax in (0, 2):
+        shape = [1, 1, 1]
+        shape[ax] = n
+        assert np.allclose(np.real(dft3(chat * ik_factors(n, L).reshape(shape), -1)), 0.0, atol=1e-12)
+
+
+def test_ik_forces_conserve_momentum_and_match_ad():
+    # the ik route with one window for spreading and interpolation makes the
+    # net force vanish exactly (odd derivative factors against the even,
+    # real p |b^|^2); both routes approximate the same spectral force
+    from oracle.fivestep import five_step_ik
+    pos, q = W.water_box(200, 12.0, seed=21)
+    L, n, P, tol = 12.0, 16, 6, 1e-4
+    prm = esp_parameters(L, tol)
+    ik = five_step_ik(pos, q, L, n, P, prm["c"], prm["rc"], prm["c1"])
+    ad = five_step(pos, q, L, n, P, prm["c"], prm["rc"], prm["c1"])
+    fscale = np.sqrt(np.mean(ik["F"] ** 2))
+    assert np.max(np.abs(ik["F"].sum(axis=0))) < 1e-12 * fscale * len(q)
+    assert np.max(np.abs(ad["F"].sum(axis=0))) > 1e3 * np.max(np.abs(ik["F"].sum(axis=0)))
+    assert rel_rms(ik["F"], ad["F"]) < 1e-3
+    assert np.allclose(ik["phi"], ad["phi"]) and ik["E"] == ad["E"]
+
+
+def test_ik_error_meets_tolerance_against_ewald():
+    from oracle.fivestep import five_step_ik
+    pos, q = W.water_box(200, 12.0, seed=22)
+    L, tol = 12.0, 1e-4
+    prm = esp_parameters(L, tol)
+    ik = five_step_ik(pos, q, L, prm["n"], prm["P"], prm["c"], prm["rc"], prm["c1"])
+    _, F_ewald, _ = ewald(pos, q, L)
+    ul, gl = local_sum(pos, q, L, PSWFSplit(prm["c"], prm["rc"]))
+    Fs_exact = F_ewald + q[:, None] * gl
+    assert rel_rms(ik["F"], Fs_exact, F_ewald) < tol
