@@ -203,6 +203,36 @@ def _time_plan(plan, ext, pos, q, phi, F, steps):
     return e0.elapsed_time(e1) / steps
 
 
+def ik_run(pos, q, L, B, N, steps, F_ad, box0):
+    """The same batch with forces by spectral derivatives (ik): cost beside
+    the AD route, force difference, net force, parity of box 0 against the
+    reference's ik route."""
+    import torch
+    from oracle.fivestep import five_step_ik
+    from oracle.metrics import rel_rms
+    from paper_2505_09727_amd.esp import Plan
+    dev = torch.device("cuda:0")
+    plan = Plan([L] * B, [N] * B, 1e-4, force_method=1)
+    phi = torch.empty(B * N, dtype=torch.float32, device=dev)
+    F = torch.empty((B * N, 3), dtype=torch.float32, device=dev)
+    ext = torch.cuda.ExternalStream(plan.stream)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange_async(pos, q, phi, F)
+    ms = _time_plan(plan, ext, pos, q, phi, F, steps)
+    plan.longrange(pos, q, phi, F)
+    p = plan.params[0]
+    Fik = F.cpu().double().numpy()
+    plan.close()
+    ref = five_step_ik(box0[0], box0[1], L, p.nf, p.P, p.c, p.rc, p.c1)
+    F0 = Fik[:N]
+    net = np.abs(F0.sum(axis=0)).max() / (N * np.sqrt(np.mean(F0 ** 2)))
+    net_ad = np.abs(F_ad[:N].sum(axis=0)).max() / (N * np.sqrt(np.mean(F_ad[:N] ** 2)))
+    return {"particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms,
+            "rel_rms_F_ik_vs_ad": rel_rms(Fik, F_ad), "rel_rms_F_vs_reference_ik": rel_rms(F0, ref["F"]),
+            "net_force_rel": {"ik": float(net), "ad": float(net_ad)}}
+
+
 def ensemble_run(steps, seed=4):
     """256 water-like boxes at 1 g/cm^3 with log-uniform sizes in one FP32 plan
     (autotuned bin edges, graph replay) against the FP64 plain path run one
@@ -329,6 +359,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-system ensemble section")
+    ap.add_argument("--no-ik", action="store_true", help="skip the ik-forces section")
     ap.add_argument("--no-large", action="store_true", help="skip the 300,000-atom section")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
@@ -394,7 +425,8 @@ def main():
     from oracle.fivestep import five_step
     from oracle.metrics import rel_rms
     ref = five_step(boxes[0][0], boxes[0][1], L, prm.nf, prm.P, prm.c, prm.rc, prm.c1)
-    F0 = F[:N].double().cpu().numpy()
+    F_all = F.double().cpu().numpy()
+    F0 = F_all[:N]
     parity = dict(rel_rms_F=rel_rms(F0, ref["F"]), rel_E=abs(E0[0] - ref["E"]) / abs(ref["E"]))
 
     # per-phase timing (HIP events between phases on the plan's stream)
@@ -434,6 +466,7 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(boxes[0][0], boxes[0][1], L, prm)
     serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_budget_gb) if args.serve_seconds > 0 else None
+    ik = None if args.no_ik else ik_run(pos, q, L, B, N, max(10, args.steps // 4), F_all, boxes[0])
     ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
     large = None if args.no_large else large_run(max(10, args.steps // 10))
 
@@ -465,6 +498,7 @@ def main():
         "kernel_rooflines": kernels,
         "cpu_baseline": cpu,
         "serving": serving,
+        "ik_forces": ik,
         "ensemble": ensemble,
         "large_system": large,
     }

@@ -90,6 +90,10 @@ typedef struct {
     double h;             /* grid spacing L/nf */
     double tol;           /* requested tolerance */
     double s0;            /* self constant S(0) = chi(0)/(4 pi rc) */
+    int    force_method;  /* forces (Methods, force paragraph): 0 analytic derivatives of
+                             the window in the interpolation ("AD", default); 1 spectral
+                             derivatives of the scaled spectrum ("ik": three more
+                             gradient grids, each interpolated with the window) */
 } esp_params;
 
 typedef struct esp_plan esp_plan;

@@ -121,6 +121,7 @@ size_t scratch_bytes(const esp_params& p, int64_t N) {
     s += align256(nb * npitems(N) * 4);          // hist
     s += align256((nb + 1) * 4);                 // bin_start
     s += align256(n * n * (n + 2) * rb);         // grid
+    if (p.force_method == 1) s += align256(3 * n * n * (n + 2) * rb);  // gradient grids
     s += tiles_region(nb * E * E * E * rb, N, rb);  // tiles / staging of the scatter
     s += align256(kOutDoubles * 8);              // out
     return s;
@@ -143,6 +144,11 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
     o += align256((nb + 1) * 4);
     s.grid = base + o;
     o += align256(n * n * (n + 2) * rb);
+    s.grad = nullptr;
+    if (p.force_method == 1) {
+        s.grad = base + o;
+        o += align256(3 * n * n * (n + 2) * rb);
+    }
     s.tiles = base + o;
     o += tiles_region(nb * E * E * E * rb, N, rb);
     s.out = reinterpret_cast<double*>(base + o);
@@ -193,6 +199,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     bsys_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
     int nb_max = 1, nb_small_max = 1, n_eligible = 0;
+    bool any_ik = false;
     for (int s = 0; s < nsys; ++s) {
         const SystemSlot& sl = systems[s];
         const esp_params& r = sl.prm;
@@ -225,6 +232,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.hist = sl.scr.hist;
         d.bin_start = sl.scr.bin_start;
         d.grid = sl.scr.grid;
+        d.grad = sl.scr.grad;
+        d.ik = r.force_method == 1;
+        any_ik = any_ik || d.ik;
         d.tiles = sl.scr.tiles;
         d.out = sl.scr.out;
         d.seed = sl.seed;
@@ -267,7 +277,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     std::map<std::pair<int, int>, std::vector<int>> by_n;
     for (int s = 0; s < nsys; ++s) {
         const int n = hsys_[s].n;
-        const int fused = systems[s].prm.fft_passes == 1 && fft_fused_lds(n, prec) <= kMaxLds;
+        const int fused = systems[s].prm.fft_passes == 1 && !hsys_[s].ik && fft_fused_lds(n, prec) <= kMaxLds;
         by_n[{n, fused}].push_back(s);
     }
     const int C = fft_x_columns(prec);
@@ -333,6 +343,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.n_planes = (int)planes_.size();
     L_.n_cols = (int)cols_.size();
     L_.hist_lds = nb_max * 4;
+    L_.any_ik = any_ik;
     L_.n_small = (int)bsys_.size();
     L_.n_large = nsys - L_.n_small;
     L_.small_lds = (nb_small_max * 32 + 2 * (nb_small_max + 1) + 2 * kSmallRounds) * 4;

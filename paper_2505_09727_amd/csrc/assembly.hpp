@@ -53,6 +53,7 @@ struct SysScratch {
     int* hist;
     int* bin_start;
     void* grid;
+    void* grad;   // ik: three more grids (null otherwise)
     void* tiles;
     double* out;
 };

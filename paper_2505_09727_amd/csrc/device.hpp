@@ -24,6 +24,7 @@ struct SysDesc {
     int small;        // 1: binned by one block (k_bin_small), 0: chunked kernels
     int mT;           // ceil(2^20 / T): x / T == (x mT) >> 20 for 0 <= x < 2^20 / T
     int mt1;          // ceil(2^20 / tiles1), likewise
+    int ik;           // 1: forces by spectral derivatives (three gradient grids)
     double inv_L;     // 1/L
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
@@ -47,6 +48,8 @@ struct SysDesc {
     void* grid;       // n x n x (n + 2) reals (half spectrum in place)
     void* tiles;      // nbins x E^3 reals; before the spread, the scatter's staging
                       // (N 4-vectors, then N ints at the next 256-byte boundary)
+    void* grad;       // ik only: three grids like `grid` (d/dx, d/dy, d/dz), each
+                      // n x n x (n + 2) reals, one after another
     double* out;      // 8 doubles: E, sum q, sum |q|, sum q^2, fixed-point scale
     // serving: per-step drift of the resident positions (k_drift)
     unsigned long long seed;  // drift stream of the request

@@ -222,21 +222,32 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __
     for (int idx = threadIdx.x; idx < N * HS; idx += BD) gp[idx] = buf[idx];
 }
 
-// Inverse pass along y, then complex-to-real along z, for one x-plane.
+// Spectral derivative factor of one axis for index k of an n-point
+// transform: the derivative of exp(-2 pi i m x/L) is -2 pi i m/L times it
+// (m = k or k - n); 0 at the Nyquist index n/2. Returned without the i.
 template <typename R, int N>
-__global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __restrict__ sys,
-                                                              const int2* __restrict__ items) {
-    constexpr int HS = N / 2 + 1, RL = N + 2, HALF = N / 2, BD = plane_threads<N>();
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int2 wi = items[blockIdx.x];
-    const SysDesc& S = sys[wi.x];
-    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* buf = tw + N;
-    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
-    for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
-    R* plane = reinterpret_cast<R*>(S.grid) + (long long)wi.y * N * RL;
-    const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(plane);
-    for (int idx = threadIdx.x; idx < N * HS; idx += BD) buf[idx] = gp[idx];
+__device__ __forceinline__ R ik_factor(int k, R inv_L) {
+    const int m = k <= N / 2 ? k : k - N;
+    return k == N / 2 ? R(0) : R(-2.0 * 3.14159265358979323846) * R(m) * inv_L;
+}
+
+// Inverse y then complex-to-real z of one x-plane: src holds the plane's
+// half spectrum (complex, [ky][kz]), dst receives the real plane (rows of
+// N + 2). deriv 2 / 3 first multiplies by the y / z derivative factor (ik).
+template <typename R, int N, int BD>
+__device__ __forceinline__ void inv_yz_plane(cplx<R>* __restrict__ buf, const cplx<R>* __restrict__ tw,
+                                             const R* src, R* dst, int deriv, R inv_L) {
+    constexpr int HS = N / 2 + 1, RL = N + 2, HALF = N / 2;
+    const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(src);
+    for (int idx = threadIdx.x; idx < N * HS; idx += BD) {
+        cplx<R> v = gp[idx];
+        if (deriv >= 2) {
+            const int ky = idx / HS, kz = idx - ky * HS;
+            const R d = deriv == 2 ? ik_factor<R, N>(ky, inv_L) : ik_factor<R, N>(kz, inv_L);
+            v = {-v.y * d, v.x * d};
+        }
+        buf[idx] = v;
+    }
     __syncthreads();
     fft_ct<R, N, 1, HS, 1, HS, BD, true, -1>(buf, tw);
     {
@@ -272,8 +283,42 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __
     for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
         const int r = idx / N, z = idx - r * N;
         const cplx<R> v = buf[r * (N + 1) + z];
-        plane[(2 * r) * RL + z] = v.x;
-        plane[(2 * r + 1) * RL + z] = v.y;
+        dst[(2 * r) * RL + z] = v.x;
+        dst[(2 * r + 1) * RL + z] = v.y;
+    }
+}
+
+// Inverse pass along y, then complex-to-real along z, for one x-plane. With
+// ik forces the block also makes the plane of each gradient grid: d/dy and
+// d/dz from the potential's spectrum (read before the potential overwrites
+// it in place), d/dx from the x-derivative spectrum the x pass left in the
+// first gradient grid (in place).
+template <typename R, int N>
+__global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __restrict__ sys,
+                                                              const int2* __restrict__ items) {
+    constexpr int RL = N + 2, BD = plane_threads<N>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* buf = tw + N;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
+    const long long off = (long long)wi.y * N * RL;
+    R* plane = reinterpret_cast<R*>(S.grid) + off;
+    const R inv_L = R(S.inv_L);
+    if (S.ik) {  // uniform over the block
+        R* g = reinterpret_cast<R*>(S.grad);
+        const long long G = (long long)N * N * RL;
+        inv_yz_plane<R, N, BD>(buf, tw, plane, g + G + off, 2, inv_L);
+        __syncthreads();
+        inv_yz_plane<R, N, BD>(buf, tw, plane, g + 2 * G + off, 3, inv_L);
+        __syncthreads();
+        inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, inv_L);
+        __syncthreads();
+        inv_yz_plane<R, N, BD>(buf, tw, g + off, g + off, 0, inv_L);
+    } else {
+        inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, inv_L);
     }
 }
 
@@ -297,6 +342,8 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
     const int c0 = wi.y, cnt = wi.z;
     cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
     cplx<R>* buf = tw + N;
+    cplx<R>* bufx = buf + N * C;  // ik: the x-derivative of the scaled spectrum
+    const bool ik = S.ik && mode == 0;
     const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
     for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
     cplx<R>* gp = reinterpret_cast<cplx<R>*>(S.grid) + c0;
@@ -322,14 +369,27 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
             const cplx<R> b = buf[idx];
             const double wgt = (kz == 0 || kz == HALF) ? 1.0 : 2.0;
             e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);
-            buf[idx] = {b.x * p, b.y * p};
+            const cplx<R> cb = {b.x * p, b.y * p};
+            buf[idx] = cb;
+            if (ik) {
+                const R d = ik_factor<R, N>(x, R(S.inv_L));
+                bufx[idx] = {-cb.y * d, cb.x * d};
+            }
         }
         __syncthreads();
         if (mode == 0) fft_ct<R, N, 1, C, 1, C, BD, true, -1>(buf, tw);
+        if (ik) fft_ct<R, N, 1, C, 1, C, BD, true, -1>(bufx, tw);
     }
     for (int idx = threadIdx.x; idx < N * C; idx += BD) {
         const int x = idx / C, l = idx - x * C;
         if (l < cnt) gp[(long long)x * ROW + l] = buf[idx];
+    }
+    if (ik) {
+        cplx<R>* gx = reinterpret_cast<cplx<R>*>(S.grad) + c0;
+        for (int idx = threadIdx.x; idx < N * C; idx += BD) {
+            const int x = idx / C, l = idx - x * C;
+            if (l < cnt) gx[(long long)x * ROW + l] = bufx[idx];
+        }
     }
     const double tot = block_sum(e, red);
     if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
@@ -589,7 +649,7 @@ static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode)
         k_fwd_zy<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(L.sys, L.planes + G.plane_off,
                                                                                    (mode & 3) == 3 ? 0 : 1);
     } else if (which == 1) {
-        const int lds = fft_x_lds(N, L.prec);
+        const int lds = fft_x_lds(N, L.prec, L.any_ik);
         if ((e = allow_lds(k_fft_x<R, N>, lds)) != hipSuccess) return e;
         k_fft_x<R, N><<<G.col_count, x_threads<R, N>(), lds, L.stream>>>(L.sys, L.cols + G.col_off,
                                                                          L.epart + G.col_off, mode);

@@ -380,7 +380,7 @@ __device__ __forceinline__ void stage_coef(R* __restrict__ ct, R* __restrict__ c
 // clamped at zero (the window is positive on its support; the clamp only
 // removes rounding noise at the support's edge, and the fixed-point spread
 // relies on it). l0[a] is the first grid index of axis a's support.
-template <typename R, int P>
+template <typename R, int P, bool CLAMP = true>
 __device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__ ct, int deg, R (&w)[3][P],
                                          int (&l0)[3]) {
     const R hp = R(0.5) * R(P);
@@ -411,10 +411,12 @@ __device__ __forceinline__ void windows3(R ux, R uy, R uz, const R* __restrict__
             yp[a] *= y[a];
         }
     }
+    if constexpr (CLAMP) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int j = 0; j < P; ++j) w[a][j] = fmax(w[a][j], R(0));
+            for (int j = 0; j < P; ++j) w[a][j] = fmax(w[a][j], R(0));
+    }
 }
 
 // As windows3 without the clamp, with the derivatives d w / d u from the
@@ -584,6 +586,80 @@ __global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, c
     }
 }
 
+// The E^3 window tile of a bin (origin ox, oy, oz, periodic) from a grid
+// stored n x n x (n + 2): 32-lane groups walk the E^2 rows of the tile, lane
+// c < E loads element c of a row (E <= 28).
+template <typename R>
+__device__ __forceinline__ void load_tile(R* __restrict__ lds, const R* __restrict__ g, int n, int E, int ox, int oy,
+                                          int oz) {
+    const int rl = n + 2;
+    const int c = threadIdx.x & 31;
+    const int gz = wrap_near(oz + c, n);
+    const int rstep = blockDim.x >> 5;
+    int r = threadIdx.x >> 5, a = r / E, b = r - a * E;
+    for (; r < E * E; r += rstep) {
+        if (c < E) {
+            const int gx = wrap_near(ox + a, n), gy = wrap_near(oy + b, n);
+            lds[r * E + c] = g[((long long)gx * n + gy) * rl + gz];
+        }
+        b += rstep;
+        while (b >= E) {
+            b -= E;
+            ++a;
+        }
+    }
+}
+
+// Gather with ik forces (Methods, force paragraph): four passes over the
+// bin's particles, each interpolating one grid with the window itself:
+// the potential (phi_i = u~_i - q_i S(0)) and the three gradient grids
+// (F_i = -q_i times the interpolated gradient, physical units).
+template <typename R, int P>
+__device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __restrict__ ct, int ox, int oy, int oz,
+                          int beg, int end) {
+    const int n = S.n, E = S.E, deg = S.degree;
+    const long long G = (long long)n * n * (n + 2);
+    const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
+    R* phi = reinterpret_cast<R*>(S.phi);
+    R* F = reinterpret_cast<R*>(S.F);
+    const R s0 = R(S.s0);
+    for (int pass = 0; pass < 4; ++pass) {
+        if (pass == 0 && !phi) continue;
+        if (pass > 0 && !F) break;
+        const R* src = pass == 0 ? reinterpret_cast<const R*>(S.grid)
+                                 : reinterpret_cast<const R*>(S.grad) + (pass - 1) * G;
+        __syncthreads();
+        load_tile<R>(lds, src, n, E, ox, oy, oz);
+        __syncthreads();
+        for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
+            const typename Vec4<R>::type v = sorted[k];
+            R w[3][P];
+            int l0[3];
+            windows3<R, P, false>(v.x, v.y, v.z, ct, deg, w, l0);
+            const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
+            R u = 0;
+#pragma unroll 1
+            for (int a = 0; a < P; ++a) {
+                R su = 0;
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    const R* row = lds + ((bx + a) * E + (by + b)) * E + bz;
+                    R s = 0;
+#pragma unroll
+                    for (int c = 0; c < P; ++c) s += row[c] * w[2][c];
+                    su += s * w[1][b];
+                }
+                u += su * w[0][a];
+            }
+            const int o = S.perm[k];
+            if (pass == 0)
+                phi[o] = u - v.w * s0;
+            else
+                F[3LL * o + (pass - 1)] = -v.w * u;
+        }
+    }
+}
+
 // Gather (eq. interp) with analytic window derivatives (AD forces):
 // phi_i = u~_i - q_i S(0), F_i = -q_i (n/L) grad_u u~_i, written in caller order.
 template <typename R, int P>
@@ -600,30 +676,14 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const int beg = S.bin_start[t], end = S.bin_start[t + 1];
     if (beg == end) return;
-    const R* g = reinterpret_cast<const R*>(S.grid);
-    const int rl = n + 2;
     R* ct = reinterpret_cast<R*>(smem_raw + (((size_t)E3 * sizeof(R) + 15) & ~size_t(15)));
     R* ctd = ct + 17 * P;
     stage_coef<R, P>(ct, ctd, reinterpret_cast<const R*>(S.poly), S.degree);
-    {
-        // 32-lane groups walk the E^2 rows of the tile, lane c < E loads
-        // element c of a row (E <= 28)
-        const int c = threadIdx.x & 31;
-        const int gz = wrap_near(oz + c, n);
-        const int rstep = blockDim.x >> 5;
-        int r = threadIdx.x >> 5, a = r / E, b = r - a * E;
-        for (; r < E * E; r += rstep) {
-            if (c < E) {
-                const int gx = wrap_near(ox + a, n), gy = wrap_near(oy + b, n);
-                lds[r * E + c] = g[((long long)gx * n + gy) * rl + gz];
-            }
-            b += rstep;
-            while (b >= E) {
-                b -= E;
-                ++a;
-            }
-        }
+    if (S.ik) {  // uniform over the block
+        gather_ik<R, P>(S, lds, ct, ox, oy, oz, beg, end);
+        return;
     }
+    load_tile<R>(lds, reinterpret_cast<const R*>(S.grid), n, E, ox, oy, oz);
     __syncthreads();
     const int deg = S.degree;
     const R sc = R(S.n) * R(S.inv_L);

@@ -33,6 +33,7 @@ struct Launch {
     int n_cols;
     const int2* fsys;     // (sys, 0) of systems on the one-block transform, grouped by grid size
     int hist_lds;         // LDS bytes of the per-chunk histogram
+    int any_ik;           // some system takes ik forces (x pass keeps two column buffers)
     int n_large;          // systems binned by the chunked kernels
     const int2* bsys;     // (sys, 0) of systems binned by one block
     int n_small;
@@ -65,9 +66,9 @@ inline int fft_plane_lds(int n, int prec) {
     const int rb = prec == 64 ? 8 : 4;
     return (n + n * (n / 2 + 1)) * 2 * rb + (n + 1) * 9 * 4;
 }
-inline int fft_x_lds(int n, int prec) {
+inline int fft_x_lds(int n, int prec, bool ik = false) {
     const int rb = prec == 64 ? 8 : 4;
-    return (n + n * fft_x_columns(prec)) * 2 * rb;
+    return (n + (ik ? 2 : 1) * n * fft_x_columns(prec)) * 2 * rb;
 }
 // Dynamic LDS of the one-block transform (twiddles, the whole half spectrum,
 // covering tables); the path is taken when this fits in 160 KB.

@@ -330,6 +330,7 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
     if (r.tile != 0 && (r.tile < 8 || r.tile > 16)) { msg = "tile must lie in [8, 16]"; return ESP_E_UNSUPPORTED; }
     if (r.fft_passes != 0 && r.fft_passes != 1) { msg = "fft_passes must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.force_method != 0 && r.force_method != 1) { msg = "force_method must be 0 or 1"; return ESP_E_INVALID; }
     if (r.c1 <= 0) {
         // E_A depends on L only through rc/h; memoise per (n, P, c, rc/h).
         // Evaluated in the reference box L = n (h = 1, rc = rho).

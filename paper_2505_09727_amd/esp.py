@@ -31,7 +31,7 @@ class esp_params(C.Structure):
                 ("tile", C.c_int), ("fft_passes", C.c_int),
                 ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
-                ("s0", C.c_double)]
+                ("s0", C.c_double), ("force_method", C.c_int)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -187,7 +187,9 @@ def _ptr(t):
 class Plan:
     """A single-system or batched plan (esp_plan_create_ex / esp_batch_create)."""
 
-    def __init__(self, L, N, tol, **req):
+    def __init__(self, L, N, tol, per_system=None, **req):
+        """Single system (scalar L, N) or batch (sequences). per_system: one
+        dict of requested parameters per system of a batch (overrides req)."""
         self._h = C.c_void_p()
         if np.ndim(L) == 0:
             _check(lib().esp_plan_create_ex(_box(float(L)), int(N), float(tol), C.byref(_req(**req)),
@@ -196,7 +198,8 @@ class Plan:
             Ls = np.ascontiguousarray(L, dtype=np.float64)
             Ns = np.ascontiguousarray(N, dtype=np.int64)
             tols = np.ascontiguousarray(np.broadcast_to(tol, Ls.shape), dtype=np.float64)
-            reqs = (esp_params * len(Ls))(*[_req(**req) for _ in range(len(Ls))])
+            kws = per_system if per_system is not None else [req] * len(Ls)
+            reqs = (esp_params * len(Ls))(*[_req(**kw) for kw in kws])
             _check(lib().esp_batch_create(len(Ls), Ls.ctypes.data_as(_P(C.c_double)),
                                           Ns.ctypes.data_as(_P(C.c_int64)), tols.ctypes.data_as(_P(C.c_double)),
                                           reqs, C.byref(self._h)))

@@ -13,7 +13,7 @@ import pytest
 
 import workloads as W
 from oracle.ewald import ewald
-from oracle.fivestep import five_step, dft3, influence, spread
+from oracle.fivestep import five_step, five_step_ik, dft3, influence, spread
 from oracle.metrics import rel_rms
 from oracle.split import PSWFSplit
 from oracle.spectral import local_sum
@@ -300,3 +300,50 @@ def test_graph_replay_matches_eager():
         assert torch.allclose(F1, F0, rtol=1e-4, atol=1e-6 * F0.abs().max().item())
         assert abs(E1[0] - E0[0]) < 1e-6 * abs(E0[0])
     plan.close()
+
+
+# ---------------------------------------------------------------- ik forces
+
+@pytest.mark.parametrize("prec,bar_F,bar_E,bar_p", [(64, 1e-9, 1e-10, 1e-10), (32, 1e-4, 1e-5, 1e-5)])
+def test_ik_forces_match_reference(prec, bar_F, bar_E, bar_p):
+    """Forces by spectral derivatives (force_method 1) against the
+    reference's ik route; the net force vanishes (momentum conservation of the
+    ik route); potentials and energy are those of the AD plan."""
+    pos, q = W.water_box(700, 20.0, seed=31)
+    L = 20.0
+    kw = dict(precision=prec, degree=16) if prec == 64 else dict(precision=prec)
+    plan = Plan(L, len(q), 1e-4, force_method=1, **kw)
+    phi, F, E = run(plan, pos, q)
+    p = plan.params[0]
+    assert p.force_method == 1
+    ref = five_step_ik(pos, q, L, p.nf, p.P, p.c, p.rc, p.c1)
+    eF, ephi = rel_rms(F, ref["F"]), rel_rms(phi, ref["phi"])
+    eE = abs(E[0] - ref["E"]) / abs(ref["E"])
+    net = np.max(np.abs(F.sum(axis=0))) / (len(q) * np.sqrt(np.mean(F ** 2)))
+    print(f"ik prec={prec}: relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e} net={net:.1e}")
+    assert eF < bar_F and ephi < bar_F and eE < bar_E
+    assert net < bar_p
+    ad = Plan(L, len(q), 1e-4, **kw)
+    phi_ad, F_ad, E_ad = run(ad, pos, q)
+    assert rel_rms(phi, phi_ad) < 1e-6 and abs(E[0] - E_ad[0]) < 1e-7 * abs(E_ad[0])
+    assert rel_rms(F, F_ad) < 1e-3
+    ad.close()
+    plan.close()
+
+
+def test_ik_and_ad_systems_share_a_batch():
+    s1 = W.water_box(400, 17.0, seed=41) + (17.0,)
+    s2 = W.water_box(300, 15.0, seed=42) + (15.0,)
+    systems = [s1, s2]
+    Ls = [s[2] for s in systems]
+    Ns = [len(s[1]) for s in systems]
+    batch = Plan(Ls, Ns, 1e-4, per_system=[dict(force_method=0), dict(force_method=1)])
+    phi, F, E = run(batch, np.concatenate([s1[0], s2[0]]), np.concatenate([s1[1], s2[1]]))
+    off = np.cumsum([0] + Ns)
+    for s, (ps, qs, L) in enumerate(systems):
+        single = Plan(L, len(qs), 1e-4, force_method=s)
+        phi1, F1, E1 = run(single, ps, qs)
+        sl = slice(off[s], off[s + 1])
+        assert np.array_equal(F[sl], F1) and np.array_equal(phi[sl], phi1) and E[s] == E1[0]
+        single.close()
+    batch.close()
