@@ -24,7 +24,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2505_09727_amd.esp import Plan, EspError  # noqa: E402
+from paper_2505_09727_amd.esp import EspError, Plan, Server, esp_plan_query  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -257,6 +257,35 @@ def test_large_water_fp32_tol1e5():
     assert (p.nf, p.P) == (96, 8)
     _check_vs_five_step(plan, pos, q, 1e-5, 1e-6)
     plan.close()
+
+
+def test_large_water_served_steps_0_and_99():
+    # the same box served for 100 steps with the seeded 0.01 drift, positions
+    # resident on the device; the reference runs on the positions the host
+    # reproduces for the first and the last step
+    from serving_jobs import positions_at_step
+    cfg = W.WATER_300K
+    pos, q = W.water_box(cfg["n_mol"], cfg["L"], cfg["seed"])
+    L, tol, steps = cfg["L"], cfg["tol"], cfg["steps"]
+    pos32, q32 = pos.astype(np.float32), q.astype(np.float32)
+    srv = Server(keep_outputs=True)
+    rid = srv.submit(pos32, q32, L, tol, nsteps=steps, drift=0.01, seed=cfg["seed"])
+    srv.wait(300)
+    r = srv.poll()[0]
+    phi, F = srv.fetch(rid, len(q))
+    srv.close()
+    assert r["status"] == 0 and r["nsteps"] == steps
+    p = esp_plan_query(L, len(q), tol)
+    ref0 = five_step(pos32.astype(np.float64), q, L, p.nf, p.P, p.c, p.rc, p.c1)
+    assert abs(r["E_first"] - ref0["E"]) < 1e-6 * abs(ref0["E"])
+    pfin = positions_at_step(pos32, L, steps - 1, cfg["seed"], 0.01)
+    assert np.abs(pfin - pos32).max() > 0.05
+    ref = five_step(pfin.astype(np.float64), q, L, p.nf, p.P, p.c, p.rc, p.c1)
+    eF = rel_rms(F.astype(np.float64), ref["F"])
+    print(f"step {steps - 1}: relF={eF:.2e} E={r['E_last']:.8g} ref={ref['E']:.8g}")
+    assert eF < 1e-5
+    assert abs(r["E_last"] - ref["E"]) < 1e-6 * abs(ref["E"])
+    assert rel_rms(phi.astype(np.float64), ref["phi"]) < 1e-5
 
 
 def test_batch_matches_single_and_reference():

@@ -1,0 +1,106 @@
+"""Served requests against the CPU reference, sampled from the serving stream.
+
+Workload: the Poisson request stream of the serving benchmark (seed 5, sizes
+log-uniform in [1000, 200000], water at 1 g/cm^3 or +-1 melt, tol drawn from
+{1e-3, 1e-4, 1e-5}). The sample takes the first three requests of every
+(tolerance, size band) cell in arrival order, with six log-spaced size bands:
+54 requests. Each is served twice in one mix through the continuous-batching
+server: once for one step (step 0, positions as submitted) and once for ten
+steps with the seeded 0.01 drift (step 9). Both results are compared with the
+reference five-step method at the library's parameters on the positions the
+host reproduces for that step: relative RMS force error below the request's
+tolerance, and an energy error below 1e-5 of (1/2) sum |q_i phi_i|. The
+energy of a neutral melt can be a small difference of large terms (E_k
+against the self term), so its rounding error scales with that sum of
+magnitudes, not with |E|."""
+import math
+import multiprocessing as mp
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.metrics import rel_rms
+from serving_jobs import limit_threads, positions_at_step, reference
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_09727_amd.esp import Server, esp_plan_query  # noqa: E402
+
+TOLS = (1e-3, 1e-4, 1e-5)
+BANDS = 6
+PER_CELL = 3
+LO, HI = 1000, 200000
+DRIFT = 0.01
+WORKERS = 8
+
+
+def _band(n):
+    return min(BANDS - 1, int(BANDS * math.log(n / LO) / math.log(HI / LO)))
+
+
+def _sample():
+    cells = {(t, b): [] for t in TOLS for b in range(BANDS)}
+    for r in W.request_stream(duration_s=10.0, rate_hz=2000.0, seed=5):
+        cell = cells[(r.tol, _band(r.n_atoms))]
+        if len(cell) < PER_CELL:
+            cell.append(r)
+    assert all(len(v) == PER_CELL for v in cells.values())
+    return cells
+
+
+@pytest.fixture(scope="module")
+def served():
+    cells = _sample()
+    srv = Server(hbm_budget_bytes=8 << 30, keep_outputs=True)
+    sub = []
+    for (tol, band), reqs in cells.items():
+        for r in reqs:
+            pos, q, L = r.system()
+            pos32, q32 = pos.astype(np.float32), q.astype(np.float32)
+            for nsteps in (1, 10):
+                rid = srv.submit(pos32, q32, L, tol, nsteps=nsteps, drift=DRIFT, seed=r.seed, tag=r.rid)
+                sub.append(((tol, band), r, nsteps, rid, pos32, q, L))
+    srv.wait(300)
+    res = {x["id"]: x for x in srv.poll(len(sub) + 16)}
+    out = {}
+    for cell, r, nsteps, rid, pos32, q, L in sub:
+        assert res[rid]["status"] == 0 and res[rid]["nsteps"] == nsteps
+        phi, F = srv.fetch(rid, len(q))
+        out.setdefault(cell, []).append((r, nsteps, res[rid]["E_last"], F, phi, pos32, q, L))
+    srv.close()
+    # the reference evaluations run on host cores, in the order the cells are checked
+    ex = ProcessPoolExecutor(WORKERS, mp_context=mp.get_context("spawn"), initializer=limit_threads)
+    jobs = {}
+    for cell in sorted(out, key=lambda c: (c[1], c[0])):
+        for r, nsteps, E, F, phi, pos32, q, L in out[cell]:
+            p = esp_plan_query(L, len(q), r.tol)
+            pfin = positions_at_step(pos32, L, nsteps - 1, r.seed, DRIFT)
+            fut = ex.submit(reference, pfin, q, L, p.nf, p.P, p.c, p.rc, p.c1)
+            jobs.setdefault(cell, []).append((r, nsteps, E, F, phi, fut))
+    yield jobs
+    ex.shutdown(cancel_futures=True)
+
+
+@pytest.mark.parametrize("band", range(BANDS))
+@pytest.mark.parametrize("tol", TOLS)
+def test_sampled_request_vs_reference(served, tol, band):
+    for r, nsteps, E, F, phi, fut in served[(tol, band)]:
+        F_ref, phi_ref, E_ref, E_mag = fut.result(timeout=110)
+        eF = rel_rms(F.astype(np.float64), F_ref)
+        eE = abs(E - E_ref) / E_mag
+        print(f"req {r.rid} {r.kind} N={r.n_atoms} tol={tol} step {nsteps - 1}: relF={eF:.2e} relE={eE:.2e}")
+        assert eF < tol, (r.rid, nsteps, eF)
+        assert eE < 1e-5, (r.rid, nsteps, E, E_ref)
+        assert rel_rms(phi.astype(np.float64), phi_ref) < tol
+
+
+def test_sample_spans_the_stream(served):
+    sizes = [r.n_atoms for v in served.values() for r, *_ in v]
+    assert len(sizes) == 2 * len(TOLS) * BANDS * PER_CELL
+    assert min(sizes) < 2500 and max(sizes) > 100000
