@@ -430,7 +430,7 @@ def main():
     parity = dict(rel_rms_F=rel_rms(F0, ref["F"]), rel_E=abs(E0[0] - ref["E"]) / abs(ref["E"]))
 
     # per-phase timing (HIP events between phases on the plan's stream)
-    nph = 9
+    nph = lib().esp_num_phases()
     ms = (C.c_double * nph)()
     st = lib().esp_plan_profile(plan._h, C.c_void_p(pos.data_ptr()), C.c_void_p(q.data_ptr()),
                                 C.c_void_p(phi.data_ptr()), C.c_void_p(F.data_ptr()), args.profile_reps, ms)

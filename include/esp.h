@@ -94,6 +94,10 @@ typedef struct {
                              the window in the interpolation ("AD", default); 1 spectral
                              derivatives of the scaled spectrum ("ik": three more
                              gradient grids, each interpolated with the window) */
+    int    local;         /* 1: also evaluate the local part u^l of the split (eq.
+                             localpart, kernel L(r) inside rc) on the device, so that
+                             phi, F and E are the full Coulomb values of eq. task
+                             (needs rc <= L/2); 0: the long-range part only */
 } esp_params;
 
 typedef struct esp_plan esp_plan;
@@ -122,6 +126,16 @@ esp_status esp_influence_tables(const esp_params* resolved, double* TS, double* 
  * short-range code: L(r) and dL/dr at the n radii r[] (r > 0). */
 esp_status esp_local_kernel(const esp_params* resolved, const double* r, int64_t n,
                             double* Lr, double* dLr);
+
+/* Piecewise polynomials the device evaluates for the local part, in grid
+ * units (lengths divided by h; rho = rc/h). For 0 < r < rho, with
+ * x = r^2/rho^2, piece k = min(floor(K x), K-1) and y = K x - k - 1/2:
+ *   h L(h r)          = 1/(4 pi r) - sum_m A[k*(degree+1) + m] y^m,
+ *   h^2 L'(h r) / r   = -1/(4 pi r^3) - sum_m B[k*(degree+1) + m] y^m.
+ * A and B must hold ESP_LOCAL_COEF_MAX doubles each; *pieces = K and
+ * *degree are written. Host only. */
+#define ESP_LOCAL_COEF_MAX 104
+esp_status esp_local_coeffs(const esp_params* resolved, double* A, double* B, int* pieces, int* degree);
 
 /* Precompute (host, process-wide cache) the parameter classes of every grid
  * size 8..nf_max (even 2^a 3^b) for the default rules at each tolerance in
@@ -208,6 +222,7 @@ esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q,
 #define ESP_NUM_PHASES 9
 esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void* phi, void* F,
                             int reps, double* ms);
+int         esp_num_phases(void);
 const char* esp_phase_name(int phase);
 
 /* ---- serving: continuous batching of independent long-range solves ----

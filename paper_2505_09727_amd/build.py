@@ -39,6 +39,7 @@ def build(verbose: bool = False) -> str:
     jobs = [
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(OUT_DIR, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "fft.hip"), "-o", os.path.join(OUT_DIR, "fft.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "local.hip"), "-o", os.path.join(OUT_DIR, "local.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "runtime.cpp"), "-o", os.path.join(OUT_DIR, "runtime.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "assembly.cpp"), "-o", os.path.join(OUT_DIR, "assembly.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "server.cpp"), "-o", os.path.join(OUT_DIR, "server.o")],

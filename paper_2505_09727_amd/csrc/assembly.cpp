@@ -48,9 +48,11 @@ esp_status TableStore::get(const esp_params& p, const DeviceClass** out, std::st
     }
     DeviceClass d;
     d.host = t.get();
-    const std::vector<double>* src[4] = {&t->TS, &t->Tphi, &t->poly, &t->tw};
-    void** dst[4] = {&d.TS, &d.Tphi, &d.poly, &d.tw};
-    for (int i = 0; i < 4; ++i) {
+    std::vector<double> lcoef(t->lA);
+    lcoef.insert(lcoef.end(), t->lB.begin(), t->lB.end());
+    const std::vector<double>* src[5] = {&t->TS, &t->Tphi, &t->poly, &t->tw, &lcoef};
+    void** dst[5] = {&d.TS, &d.Tphi, &d.poly, &d.tw, &d.lcoef};
+    for (int i = 0; i < 5; ++i) {
         auto b = to_prec(*src[i], p.precision);
         void* q = nullptr;
         hipError_t e = hipMalloc(&q, std::max<size_t>(b.size(), 16));
@@ -111,6 +113,12 @@ size_t tiles_region(size_t tile_bytes, int64_t N, size_t rb) {
     return align256(std::max(tile_bytes, stage));
 }
 
+void local_cells(const esp_params& p, int& lcs, int& R) {
+    const double rho = grid_rho(p);
+    lcs = std::max(1, std::min(8, (int)std::floor(2.0 * p.tile / rho)));
+    R = std::max(1, (int)std::ceil(rho * (1.0 + 1e-4) * lcs / p.tile));
+}
+
 size_t scratch_bytes(const esp_params& p, int64_t N) {
     const size_t rb = p.precision == 64 ? 8 : 4;
     const size_t nb = nbins(p), E = tile_edge(p), n = p.nf;
@@ -123,6 +131,14 @@ size_t scratch_bytes(const esp_params& p, int64_t N) {
     s += align256(n * n * (n + 2) * rb);         // grid
     if (p.force_method == 1) s += align256(3 * n * n * (n + 2) * rb);  // gradient grids
     s += tiles_region(nb * E * E * E * rb, N, rb);  // tiles / staging of the scatter
+    if (p.local) {
+        int lcs, R;
+        local_cells(p, lcs, R);
+        s += align256(N * 4 * rb);               // cpos
+        s += align256(N * 4);                    // cidx
+        s += align256((nb * lcs * lcs * lcs + 1) * 4);  // cstart
+        s += align256(N * 4 * rb);               // loc
+    }
     s += align256(kOutDoubles * 8);              // out
     return s;
 }
@@ -151,12 +167,26 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
     }
     s.tiles = base + o;
     o += tiles_region(nb * E * E * E * rb, N, rb);
+    s.cpos = s.loc = nullptr;
+    s.cidx = s.cstart = nullptr;
+    if (p.local) {
+        int lcs, R;
+        local_cells(p, lcs, R);
+        s.cpos = base + o;
+        o += align256(N * 4 * rb);
+        s.cidx = reinterpret_cast<int*>(base + o);
+        o += align256(N * 4);
+        s.cstart = reinterpret_cast<int*>(base + o);
+        o += align256((nb * lcs * lcs * lcs + 1) * 4);
+        s.loc = base + o;
+        o += align256(N * 4 * rb);
+    }
     s.out = reinterpret_cast<double*>(base + o);
     return s;
 }
 
 LaunchSet::~LaunchSet() {
-    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_, d_cols_, d_bpart_, d_epart_};
+    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_, d_cols_, d_bpart_, d_epart_, d_lpart_};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -199,7 +229,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     bsys_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
     int nb_max = 1, nb_small_max = 1, n_eligible = 0;
-    bool any_ik = false;
+    bool any_ik = false, any_local = false;
     for (int s = 0; s < nsys; ++s) {
         const SystemSlot& sl = systems[s];
         const esp_params& r = sl.prm;
@@ -235,6 +265,29 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.grad = sl.scr.grad;
         d.ik = r.force_method == 1;
         any_ik = any_ik || d.ik;
+        d.local = r.local == 1;
+        any_local = any_local || d.local;
+        if (d.local) {
+            local_cells(r, d.lcs, d.lR);
+            const double rho = grid_rho(r);
+            d.lpieces = kLocalPieces;
+            d.ldeg = ct.ldeg;
+            d.lsT = (double)d.lcs / d.T;
+            d.lrho2 = rho * rho;
+            d.lcoef = sl.cls->lcoef;
+            d.cpos = sl.scr.cpos;
+            d.cidx = sl.scr.cidx;
+            d.cstart = sl.scr.cstart;
+            d.loc = sl.scr.loc;
+            if (d.lR > d.tiles1 * d.lcs) {  // one periodic wrap per axis reaches every image
+                msg = "local-part stencil wider than the box";
+                return ESP_E_UNSUPPORTED;
+            }
+            if (2 * kLocalPieces * (ct.ldeg + 1) > kLocalCoefMax) {
+                msg = "local-part polynomials exceed their LDS table";
+                return ESP_E_UNSUPPORTED;
+            }
+        }
         d.tiles = sl.scr.tiles;
         d.out = sl.scr.out;
         d.seed = sl.seed;
@@ -335,8 +388,12 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         titems_.insert(titems_.end(), titems_by_P[P].begin(), titems_by_P[P].end());
         groups_.push_back(g);
     }
+    // first bin of every system in the launch's bin list (a system's bins are
+    // contiguous): the local part's energy partials are per bin
+    for (int k = (int)titems_.size() - 1; k >= 0; --k) hsys_[titems_[k].x].tbin_off = k;
     L_.prec = prec;
     L_.nsys = nsys;
+    L_.any_local = any_local;
     L_.stream = stream;
     L_.n_pitems = (int)pitems_.size();
     L_.n_titems = (int)titems_.size();
@@ -375,6 +432,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     };
     if ((st = reserve(&d_bpart_, &cap_bpart_, 4 * pitems_.size())) != ESP_OK) return st;
     if ((st = reserve(&d_epart_, &cap_epart_, (size_t)n_eslots)) != ESP_OK) return st;
+    if ((st = reserve(&d_lpart_, &cap_lpart_, titems_.size())) != ESP_OK) return st;
     L_.sys = d_sys_;
     L_.pitems = d_pitems_;
     L_.titems = d_titems_;
@@ -384,6 +442,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.bsys = d_bsys_;
     L_.bpart = d_bpart_;
     L_.epart = d_epart_;
+    L_.lpart = d_lpart_;
     return ESP_OK;
 }
 

@@ -23,6 +23,7 @@ struct DeviceClass {
     void* Tphi = nullptr;
     void* poly = nullptr;
     void* tw = nullptr;
+    void* lcoef = nullptr;  // local-part polynomials A then B
 };
 
 // Uploads each table class once per precision and keeps it until destroyed.
@@ -55,8 +56,14 @@ struct SysScratch {
     void* grid;
     void* grad;   // ik: three more grids (null otherwise)
     void* tiles;
+    void* cpos;   // local part only (null otherwise): sub-cell ordered copy,
+    int* cidx;    // its sorted indices,
+    int* cstart;  // sub-cell starts,
+    void* loc;    // and the per-particle local results
     double* out;
 };
+// Local part: sub-cells per bin side and stencil radius for resolved params.
+void local_cells(const esp_params& p, int& lcs, int& R);
 size_t scratch_bytes(const esp_params& p, int64_t N);
 SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N);
 
@@ -105,10 +112,9 @@ class LaunchSet {
     SysDesc* d_sys_ = nullptr;
     int2 *d_pitems_ = nullptr, *d_titems_ = nullptr, *d_planes_ = nullptr, *d_fsys_ = nullptr, *d_bsys_ = nullptr;
     int4* d_cols_ = nullptr;
-    double *d_bpart_ = nullptr, *d_epart_ = nullptr;
+    double *d_bpart_ = nullptr, *d_epart_ = nullptr, *d_lpart_ = nullptr;
     size_t cap_sys_ = 0, cap_pitems_ = 0, cap_titems_ = 0, cap_planes_ = 0, cap_fsys_ = 0, cap_bsys_ = 0, cap_cols_ = 0,
-           cap_bpart_ = 0,
-           cap_epart_ = 0;
+           cap_bpart_ = 0, cap_epart_ = 0, cap_lpart_ = 0;
 };
 
 constexpr int kMaxLds = 160 * 1024;

@@ -25,15 +25,24 @@ struct SysDesc {
     int mT;           // ceil(2^20 / T): x / T == (x mT) >> 20 for 0 <= x < 2^20 / T
     int mt1;          // ceil(2^20 / tiles1), likewise
     int ik;           // 1: forces by spectral derivatives (three gradient grids)
+    int local;        // 1: local part of the split on the device (k_cellsort, k_local)
+    int lcs;          // local: sub-cells per bin side (edge T / lcs >= rho / 2)
+    int lR;           // local: stencil radius in sub-cells
+    int lpieces;      // local: polynomial pieces over x = r^2 / rho^2 in [0, 1)
+    int ldeg;         // local: polynomial degree
+    int tbin_off;     // index of the system's first bin in the launch's bin list
     double inv_L;     // 1/L
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
     double wmax3;     // cube of the window's peak value (fixed-point range)
+    double lsT;       // local: lcs / T (sub-cell coordinate per grid unit)
+    double lrho2;     // local: (rc / h)^2
     // tables shared by the systems of one parameter class
     const void* TS;   // radial influence table, 3 (n/2)^2 + 1 entries
     const void* Tphi; // per-axis influence table, n/2 + 1 entries
     const void* poly; // window polynomials, P * (degree + 1)
     const void* tw;   // twiddles exp(2 pi i t/n), n complex
+    const void* lcoef;  // local: polynomials A then B, lpieces x (ldeg + 1) each
     // particles in the caller's order (this system's slice) and outputs
     const void* pos;  // N x 3
     const void* q;    // N
@@ -50,6 +59,12 @@ struct SysDesc {
                       // (N 4-vectors, then N ints at the next 256-byte boundary)
     void* grad;       // ik only: three grids like `grid` (d/dx, d/dy, d/dz), each
                       // n x n x (n + 2) reals, one after another
+    // local part (null unless local): particles reordered by sub-cell within
+    // each bin, canonical order by caller index inside a sub-cell
+    void* cpos;       // N x (u_x, u_y, u_z, q), sub-cell order
+    int* cidx;        // N: sorted index of each sub-cell-ordered particle
+    int* cstart;      // nbins lcs^3 + 1: first particle of every sub-cell
+    void* loc;        // N x (u^l, F^l_x, F^l_y, F^l_z) in sorted order (the gather adds it)
     double* out;      // 8 doubles: E, sum q, sum |q|, sum q^2, fixed-point scale
     // serving: per-step drift of the resident positions (k_drift)
     unsigned long long seed;  // drift stream of the request
@@ -73,5 +88,8 @@ constexpr int kSmallMinSystems = 64;  // one-block binning pays only with this m
 constexpr int kParticleChunk = 1024;  // particles per chunk work item
 constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
 constexpr int kOutDoubles = 8;
+constexpr int kLocalCoefMax = 2 * 8 * 13;  // LDS reals for the local polynomials (A and B)
+constexpr int kLocalThreads = 256;          // threads of a local-part block
+constexpr int kCellSortCap = 4096;          // particles of a bin sorted in LDS
 
 }  // namespace esp

@@ -652,10 +652,12 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __rest
                 u += su * w[0][a];
             }
             const int o = S.perm[k];
+            R l = 0;  // local part (k_local), component `pass`
+            if (S.local) l = reinterpret_cast<const R*>(S.loc)[4LL * k + pass];
             if (pass == 0)
-                phi[o] = u - v.w * s0;
+                phi[o] = u - v.w * s0 + l;
             else
-                F[3LL * o + (pass - 1)] = -v.w * u;
+                F[3LL * o + (pass - 1)] = -v.w * u + l;
         }
     }
 }
@@ -729,23 +731,31 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
             gzs += sdz * wx[a];
         }
         const int o = S.perm[k];
-        if (phi) phi[o] = u - v.w * s0;
+        typename Vec4<R>::type l = {0, 0, 0, 0};  // local part (k_local)
+        if (S.local) l = reinterpret_cast<const typename Vec4<R>::type*>(S.loc)[k];
+        if (phi) phi[o] = u - v.w * s0 + l.x;
         if (F) {
             const R f = -v.w * sc;
-            F[3LL * o + 0] = f * gxs;
-            F[3LL * o + 1] = f * gys;
-            F[3LL * o + 2] = f * gzs;
+            F[3LL * o + 0] = f * gxs + l.y;
+            F[3LL * o + 1] = f * gys + l.z;
+            F[3LL * o + 2] = f * gzs + l.w;
         }
     }
 }
 
-// Energy per system: E = E_k - S(0)/2 sum q^2, plus the charge sums.
+// Energy per system: E = E_k - S(0)/2 sum q^2 (plus (1/2) sum q u^l with the
+// local part), and the charge sums.
 __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
-                                                  const double* __restrict__ bpart, double* __restrict__ E_dev) {
+                                                  const double* __restrict__ bpart, const double* __restrict__ lpart,
+                                                  double* __restrict__ E_dev) {
     __shared__ double red[16];
     const SysDesc& S = sys[blockIdx.x];
     double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < S.ncol; i += blockDim.x) ek += epart[S.col_off + i];
+    if (S.local) {
+        const int nb = S.tiles1 * S.tiles1 * S.tiles1;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) ek += 0.5 * lpart[S.tbin_off + i];
+    }
     for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) {
         sq += bpart[4 * (S.pitem_off + i) + 0];
         sa += bpart[4 * (S.pitem_off + i) + 1];
@@ -1105,7 +1115,7 @@ hipError_t launch_drift(const Launch& L) {
 }
 
 hipError_t launch_finalize(const Launch& L, double* E_dev) {
-    k_finalize<<<L.nsys, 256, 0, L.stream>>>(L.sys, L.epart, L.bpart, E_dev);
+    k_finalize<<<L.nsys, 256, 0, L.stream>>>(L.sys, L.epart, L.bpart, L.lpart, E_dev);
     return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ struct Launch {
     int small_lds;        // LDS bytes of the one-block binning
     double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
     double* epart;        // per x-column item: k-space energy partial
+    double* lpart;        // per bin item: local-part energy partial, sum q u^l
+    int any_local;        // some system evaluates the local part
 };
 
 // Systems sharing one grid size n: one launch per FFT pass.
@@ -91,6 +93,10 @@ hipError_t launch_fold(const Launch& L);
 hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode);
 hipError_t launch_gather(const Launch& L, const Group& G);
 hipError_t launch_finalize(const Launch& L, double* E_dev);
+// Local part of the split (systems with local = 1): sub-cell order, then the
+// pair sums into the per-particle buffer the gather adds and the per-bin
+// energy partials k_finalize adds.
+hipError_t launch_local(const Launch& L);
 // Serving: apply each system's drift step to its resident FP32 positions.
 hipError_t launch_drift(const Launch& L);
 

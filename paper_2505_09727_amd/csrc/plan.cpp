@@ -331,6 +331,11 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.tile != 0 && (r.tile < 8 || r.tile > 16)) { msg = "tile must lie in [8, 16]"; return ESP_E_UNSUPPORTED; }
     if (r.fft_passes != 0 && r.fft_passes != 1) { msg = "fft_passes must be 0 or 1"; return ESP_E_INVALID; }
     if (r.force_method != 0 && r.force_method != 1) { msg = "force_method must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.local != 0 && r.local != 1) { msg = "local must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.local && rho > 0.5 * r.nf) {
+        msg = "the local part needs rc <= L/2 (nearest images only)";
+        return ESP_E_UNSUPPORTED;
+    }
     if (r.c1 <= 0) {
         // E_A depends on L only through rc/h; memoise per (n, P, c, rc/h).
         // Evaluated in the reference box L = n (h = 1, rc = rho).
@@ -493,11 +498,98 @@ void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, d
     }
 }
 
+// Local part in grid units (h = 1, rc = rho), for the device's short-range
+// pass: L(r) = 1/(4 pi r) - s(r) for r < rho, with s(r) = G(r/rho)/(4 pi r)
+// the smooth part of the split (eq. kernelsplitting), G(t) = int_0^t chi.
+// With t = r/rho, substituting u = t v in the integrals gives
+//   s(r)    = (1/(4 pi rho))     int_0^1 chi(t v) dv,
+//   s'(r)/r = (1/(4 pi rho^3 t)) int_0^1 v chi'(t v) dv,
+// smooth functions of x = t^2 without cancellation at small t. Each is fitted
+// by Chebyshev interpolation on kLocalPieces equal intervals of x, at the
+// smallest degree whose error stays below 1e-12 of the function's largest
+// value. Memoised per (c, rho).
+void local_polynomials(double c, double rho, int& degree, std::vector<double>& A, std::vector<double>& B) {
+    static std::mutex mu;
+    static std::map<std::pair<double, double>, std::tuple<int, std::vector<double>, std::vector<double>>> cache;
+    const auto key = std::make_pair(c, rho);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            std::tie(degree, A, B) = it->second;
+            return;
+        }
+    }
+    Prolate psi(c);
+    const double I1 = psi.integral(1.0);
+    std::vector<double> gx, gw;
+    gauss_legendre(40, gx, gw);
+    auto sfun = [&](double x) {
+        const double t = std::sqrt(std::max(x, 0.0));
+        double a = 0.0;
+        for (size_t i = 0; i < gx.size(); ++i) a += 0.5 * gw[i] * psi(t * 0.5 * (gx[i] + 1.0));
+        return a / (I1 * 4.0 * kPi * rho);
+    };
+    auto bfun = [&](double x) {
+        const double t = std::sqrt(x);
+        double a = 0.0;
+        for (size_t i = 0; i < gx.size(); ++i) {
+            const double v = 0.5 * (gx[i] + 1.0);
+            a += 0.5 * gw[i] * v * psi.deriv(t * v);
+        }
+        return a / (I1 * 4.0 * kPi * rho * rho * rho * t);
+    };
+    const int K = kLocalPieces, nchk = 33;
+    std::vector<double> chk_x, chk_s, chk_b;
+    double ms = 0.0, mb = 0.0;
+    for (int k = 0; k < K; ++k)
+        for (int i = 0; i < nchk; ++i) {
+            const double x = (k + (i + 0.5) / nchk) / K;
+            chk_x.push_back(x);
+            chk_s.push_back(sfun(x));
+            chk_b.push_back(bfun(x));
+            ms = std::max(ms, std::fabs(chk_s.back()));
+            mb = std::max(mb, std::fabs(chk_b.back()));
+        }
+    auto eval = [](const double* a, int d, double y) {
+        double v = 0.0;
+        for (int m = d; m >= 0; --m) v = v * y + a[m];
+        return v;
+    };
+    int d = 4;
+    for (;; ++d) {
+        A.assign((size_t)K * (d + 1), 0.0);
+        B.assign((size_t)K * (d + 1), 0.0);
+        for (int k = 0; k < K; ++k) {
+            const std::vector<double> a = cheb_fit([&](double y) { return sfun((k + 0.5 + y) / K); }, d);
+            const std::vector<double> b = cheb_fit([&](double y) { return bfun((k + 0.5 + y) / K); }, d);
+            std::copy(a.begin(), a.end(), A.begin() + (size_t)k * (d + 1));
+            std::copy(b.begin(), b.end(), B.begin() + (size_t)k * (d + 1));
+        }
+        double es = 0.0, eb = 0.0;
+        for (size_t i = 0; i < chk_x.size(); ++i) {
+            const int k = std::min((int)(chk_x[i] * K), K - 1);
+            const double y = chk_x[i] * K - k - 0.5;
+            es = std::max(es, std::fabs(eval(&A[(size_t)k * (d + 1)], d, y) - chk_s[i]));
+            eb = std::max(eb, std::fabs(eval(&B[(size_t)k * (d + 1)], d, y) - chk_b[i]));
+        }
+        if ((es <= 1e-12 * ms && eb <= 1e-12 * mb) || d == kLocalMaxDegree) break;
+    }
+    degree = d;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = std::make_tuple(d, A, B);
+}
+
+double grid_rho(const esp_params& p) {
+    double rho = p.kappa * p.c / kPi;  // the default rule's exact rc/h
+    if (std::fabs(rho * p.h - p.rc) > 1e-12 * p.rc) rho = std::round(p.rc / p.h * 1e9) / 1e9;
+    return rho;
+}
+
 std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {
     static std::mutex mu;
     static std::map<std::tuple<int, int, int, double, double, double>, std::shared_ptr<const ClassTables>> cache;
-    double rho = p.kappa * p.c / kPi;  // the default rule's exact rc/h
-    if (std::fabs(rho * p.h - p.rc) > 1e-12 * p.rc) rho = std::round(p.rc / p.h * 1e9) / 1e9;
+    const double rho = grid_rho(p);
     const auto key = std::make_tuple(p.nf, p.P, p.degree, p.c, p.c1, rho);
     {
         std::lock_guard<std::mutex> g(mu);
@@ -524,6 +616,7 @@ std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {
     }
     Prolate chi(p.c);
     t->s0_ref = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * rho);
+    local_polynomials(p.c, rho, t->ldeg, t->lA, t->lB);
     double wm = 0.0;
     for (int j = 0; j < p.P; ++j)
         for (int s = 0; s <= 64; ++s) {

@@ -53,6 +53,13 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
 void window_polynomials(esp_params& p, std::vector<double>& coef);
 void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<double>& Tphi);
 void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, double* dLr);
+// Piecewise polynomials of the local part for the device (grid units):
+// pieces of x = r^2/rho^2 in [k/K, (k+1)/K), K = kLocalPieces, each in
+// y = K x - k - 1/2. A approximates the smooth part s(r), so that
+// L(r) = 1/(4 pi r) - A, and B approximates s'(r)/r.
+constexpr int kLocalPieces = 8;
+constexpr int kLocalMaxDegree = 12;
+void local_polynomials(double c, double rho, int& degree, std::vector<double>& A, std::vector<double>& B);
 
 // Tables of one parameter class. With rc proportional to h (the default
 // rule), the influence tables, window polynomials and c1 depend on
@@ -65,7 +72,11 @@ struct ClassTables {
     std::vector<double> TS, Tphi, poly, tw;  // tw interleaved (cos, sin)
     double s0_ref;                // S(0) for L = n
     double wmax3;                 // cube of the window polynomials' peak
+    int ldeg;                     // local-part polynomials (local_polynomials)
+    std::vector<double> lA, lB;
 };
+// rc/h of resolved params as the table classes key it.
+double grid_rho(const esp_params& p);
 std::shared_ptr<const ClassTables> class_tables(const esp_params& p);
 
 }  // namespace esp

@@ -186,8 +186,8 @@ esp_status bind_io(esp_plan* p, const void* pos, const void* q, void* phi, void*
 }
 
 // Pipeline phases (one kernel launch each, or one per window-width group).
-enum Phase { kHist, kScan, kScatter, kSpread, kFftZY, kFftX, kFftYZ, kGather, kFinalize, kNumPhases };
-const char* const kPhaseNames[kNumPhases] = {"hist", "scan", "scatter", "spread", "fft_zy",
+enum Phase { kHist, kScan, kScatter, kLocal, kSpread, kFftZY, kFftX, kFftYZ, kGather, kFinalize, kNumPhases };
+const char* const kPhaseNames[kNumPhases] = {"hist", "scan", "scatter", "local", "spread", "fft_zy",
                                              "fft_x_scale", "fft_yz", "gather", "finalize"};
 
 esp_status run_phase(esp_plan* p, int ph, double* E_dev, int fft_mode) {
@@ -197,6 +197,9 @@ esp_status run_phase(esp_plan* p, int ph, double* E_dev, int fft_mode) {
         case kScan:
         case kScatter:
             HIP_TRY(launch_prepare(L, ph - kHist));
+            break;
+        case kLocal:
+            HIP_TRY(launch_local(L));
             break;
         case kSpread:
             for (const Group& G : p->ls.groups()) HIP_TRY(launch_spread(L, G));
@@ -287,6 +290,24 @@ esp_status esp_window_coeffs(const esp_params* resolved, double* coef) {
     window_polynomials(r, c);
     std::memcpy(coef, c.data(), c.size() * sizeof(double));
     return ESP_OK;
+}
+
+esp_status esp_local_coeffs(const esp_params* resolved, double* A, double* B, int* pieces, int* degree) {
+    if (!resolved || !A || !B || !pieces || !degree) return fail(ESP_E_INVALID, "NULL argument");
+    if (!(resolved->h > 0) || !(resolved->rc > 0) || !(resolved->c > 0))
+        return fail(ESP_E_INVALID, "parameters are not resolved (use esp_plan_query)");
+    try {
+        std::vector<double> a, b;
+        int d = 0;
+        local_polynomials(resolved->c, grid_rho(*resolved), d, a, b);
+        std::memcpy(A, a.data(), a.size() * sizeof(double));
+        std::memcpy(B, b.data(), b.size() * sizeof(double));
+        *pieces = kLocalPieces;
+        *degree = d;
+        return ESP_OK;
+    } catch (const std::exception& e) {
+        return fail(ESP_E_INVALID, e.what());
+    }
 }
 
 esp_status esp_influence_tables(const esp_params* resolved, double* TS, double* Tphi) {
@@ -548,6 +569,8 @@ esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void
     for (int ph = 0; ph < kNumPhases; ++ph) ms[ph] = acc[ph] / reps;
     return s;
 }
+
+int esp_num_phases(void) { return kNumPhases; }
 
 const char* esp_phase_name(int phase) { return (phase >= 0 && phase < kNumPhases) ? kPhaseNames[phase] : ""; }
 

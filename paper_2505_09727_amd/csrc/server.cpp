@@ -319,6 +319,7 @@ void esp_server::loop() {
         // one step of every active request
         hipError_t e = hipSuccess;
         for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) e = launch_prepare(L, ph);
+        if (e == hipSuccess) e = launch_local(L);
         for (const Group& G : ls.groups())
             if (e == hipSuccess) e = launch_spread(L, G);
         for (int pass = 0; pass < 3; ++pass)

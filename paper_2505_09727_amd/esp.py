@@ -31,7 +31,7 @@ class esp_params(C.Structure):
                 ("tile", C.c_int), ("fft_passes", C.c_int),
                 ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
-                ("s0", C.c_double), ("force_method", C.c_int)]
+                ("s0", C.c_double), ("force_method", C.c_int), ("local", C.c_int)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +76,8 @@ _SIGS = {
     "esp_influence_tables": (C.c_int, [_P(esp_params), _P(C.c_double), _P(C.c_double)]),
     "esp_local_kernel": (C.c_int, [_P(esp_params), _P(C.c_double), C.c_int64, _P(C.c_double), _P(C.c_double)]),
     "esp_warm_tables": (C.c_int, [_P(C.c_double), C.c_int, C.c_int, C.c_int]),
+    "esp_local_coeffs": (C.c_int, [_P(esp_params), _P(C.c_double), _P(C.c_double), _P(C.c_int), _P(C.c_int)]),
+    "esp_num_phases": (C.c_int, []),
     "esp_plan_create": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(_vp)]),
     "esp_plan_create_ex": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(esp_params), _P(_vp)]),
     "esp_batch_create": (C.c_int, [C.c_int, _P(C.c_double), _P(C.c_int64), _P(C.c_double), _P(esp_params),
@@ -171,6 +173,22 @@ def esp_local_kernel(params: esp_params, r):
     _check(lib().esp_local_kernel(C.byref(params), r.ctypes.data_as(dp), len(r), Lr.ctypes.data_as(dp),
                                   dLr.ctypes.data_as(dp)))
     return Lr, dLr
+
+
+ESP_LOCAL_COEF_MAX = 104
+
+
+def esp_local_coeffs(params: esp_params):
+    """Piecewise polynomials (A, B), each pieces x (degree + 1), that the
+    device evaluates for the local part in grid units (esp.h)."""
+    A = np.zeros(ESP_LOCAL_COEF_MAX)
+    B = np.zeros(ESP_LOCAL_COEF_MAX)
+    K, d = C.c_int(0), C.c_int(0)
+    dp = _P(C.c_double)
+    _check(lib().esp_local_coeffs(C.byref(params), A.ctypes.data_as(dp), B.ctypes.data_as(dp), C.byref(K),
+                                  C.byref(d)))
+    m = K.value * (d.value + 1)
+    return A[:m].reshape(K.value, d.value + 1), B[:m].reshape(K.value, d.value + 1)
 
 
 def esp_warm_tables(tols, nf_max: int = 144, threads: int = 0) -> None:

@@ -102,6 +102,45 @@ def test_local_kernel_matches_reference():
     assert np.all(Lr[r >= p.rc] == 0)
 
 
+@pytest.mark.parametrize("tol,L", [(1e-3, 31.0), (1e-4, 31.0), (1e-5, 100.0), (1e-4, 22.56)])
+def test_local_polynomials_match_reference_kernel(tol, L):
+    # the device's piecewise polynomials in grid units against the reference
+    # L(r) = (1 - G(r/rc))/(4 pi r) and L'(r) of an independent PSWF evaluation
+    _lib_or_skip()
+    p = esp.esp_plan_query(L, 9000, tol)
+    A, B = esp.esp_local_coeffs(p)
+    K, d1 = A.shape
+    assert K == 8 and 5 <= d1 <= 13
+    h, rho = p.h, p.rc / p.h
+    r = np.linspace(1e-3, 1.0 - 1e-9, 4001) * p.rc
+    rg = r / h
+    x = (rg / rho) ** 2
+    k = np.minimum((x * K).astype(int), K - 1)
+    y = x * K - k - 0.5
+    Av = np.zeros_like(y)
+    Bv = np.zeros_like(y)
+    for m in range(d1 - 1, -1, -1):
+        Av = Av * y + A[k, m]
+        Bv = Bv * y + B[k, m]
+    L_dev = (1.0 / (4 * math.pi * rg) - Av) / h
+    dL_dev = (-1.0 / (4 * math.pi * rg ** 3) - Bv) * rg / h ** 2
+    L_ref, dL_ref = L_and_dL(PSWFSplit(p.c, p.rc), r)
+    # pointwise, against the larger of the value and the Coulomb magnitude at
+    # the cutoff (1/(4 pi rc), 1/(4 pi rc^2))
+    assert np.all(np.abs(L_dev - L_ref) < 1e-10 * np.maximum(np.abs(L_ref), 1 / (4 * math.pi * p.rc)))
+    assert np.all(np.abs(dL_dev - dL_ref) < 1e-10 * np.maximum(np.abs(dL_ref), 1 / (4 * math.pi * p.rc ** 2)))
+    # L vanishes at the cutoff
+    assert abs(L_dev[-1]) < 1e-10 / (4 * math.pi * p.rc)
+
+
+def test_local_part_needs_half_box_cutoff():
+    _lib_or_skip()
+    with pytest.raises(esp.EspError) as ei:
+        esp.esp_plan_query(8.0, 100, 1e-4, local=1)
+    assert ei.value.status == -2
+    assert esp.esp_plan_query(22.56, 512, 1e-4, local=1).local == 1
+
+
 def test_table2_through_the_library():
     _lib_or_skip()
     for eps, c_tab, P_tab in [(1e-3, 9.5392, 5), (5e-4, 10.290, 5), (1e-4, 12.024, 6), (5e-5, 12.762, 7),
