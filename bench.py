@@ -233,6 +233,73 @@ def ik_run(pos, q, L, B, N, steps, F_ad, box0):
             "net_force_rel": {"ik": float(net), "ad": float(net_ad)}}
 
 
+def _pairs_within(pos, L, rc, chunk=512):
+    """Ordered pairs (i, j), j != i, closer than rc over nearest images."""
+    n, cnt = len(pos), 0
+    for s in range(0, n, chunk):
+        d = pos[s:s + chunk, None, :] - pos[None, :, :]
+        d -= L * np.round(d / L)
+        r2 = np.einsum("abk,abk->ab", d, d)
+        cnt += int(np.count_nonzero(r2 < rc * rc)) - min(chunk, n - s)
+    return cnt
+
+
+def local_run(pos, q, L, B, N, steps, box0, reps):
+    """The same batch with the local part of the split on the device (full
+    Coulomb phi, F, E): cost beside the long-range step, the local phase's
+    time and ALU roofline, and box 0 against classical Ewald (the paper's
+    Delta) and against the reference five-step plus local sum."""
+    import ctypes as C
+    import torch
+    from oracle.ewald import ewald
+    from oracle.fivestep import five_step
+    from oracle.metrics import rel_rms
+    from oracle.split import PSWFSplit
+    from oracle.spectral import local_sum
+    from paper_2505_09727_amd.esp import Plan, esp_local_coeffs, lib
+    dev = torch.device("cuda:0")
+    plan = Plan([L] * B, [N] * B, 1e-4, local=1)
+    phi = torch.empty(B * N, dtype=torch.float32, device=dev)
+    F = torch.empty((B * N, 3), dtype=torch.float32, device=dev)
+    ext = torch.cuda.ExternalStream(plan.stream)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange_async(pos, q, phi, F)
+    ms = _time_plan(plan, ext, pos, q, phi, F, steps)
+    E = plan.longrange(pos, q, phi, F)
+    F0 = F[:N].cpu().double().numpy()
+    nph = lib().esp_num_phases()
+    msp = (C.c_double * nph)()
+    st = lib().esp_plan_profile(plan._h, C.c_void_p(pos.data_ptr()), C.c_void_p(q.data_ptr()),
+                                C.c_void_p(phi.data_ptr()), C.c_void_p(F.data_ptr()), reps, msp)
+    assert st == 0, lib().esp_last_error()
+    phases = {lib().esp_phase_name(i).decode(): msp[i] for i in range(nph)}
+    p = plan.params[0]
+    plan.close()
+    q0 = box0[1]
+    pos0 = box0[0].astype(np.float32).astype(np.float64)
+    ref = five_step(pos0, q0, L, p.nf, p.P, p.c, p.rc, p.c1)
+    ul, gl = local_sum(pos0, q0, L, PSWFSplit(p.c, p.rc))
+    F_ref = ref["F"] - q0[:, None] * gl
+    E_ref = 0.5 * float(np.dot(q0, ref["phi"] + ul))
+    _, F_e, E_e = ewald(box0[0], q0, L)
+    pairs = _pairs_within(pos0, L, p.rc)
+    deg = esp_local_coeffs(p)[0].shape[1] - 1
+    fpp = 27 + 4 * deg
+    flops = B * pairs * fpp
+    t = phases["local"] / 1e3
+    tfl = flops / t / 1e12
+    return {"particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms, "phases_ms": phases,
+            "rel_rms_F_vs_reference": rel_rms(F0, F_ref), "rel_E_vs_reference": abs(E[0] - E_ref) / abs(E_ref),
+            "delta_F_vs_ewald": rel_rms(F0, F_e), "rel_E_vs_ewald": abs(E[0] - E_e) / abs(E_e),
+            "roofline_local": {"kernel": "k_cellsort + k_local", "bound": "alu", "achieved": tfl,
+                               "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": tfl / PEAK_FP32_VALU_TFLOPS,
+                               "traffic": None, "avg_launch_ms": phases["local"],
+                               "algorithmic_flops_per_launch": flops, "pairs_per_particle": pairs / N,
+                               "flops_per_pair": fpp, "rc": p.rc},
+            "what": "full Coulomb (long-range + local part within rc) on the same batch"}
+
+
 def ensemble_run(steps, seed=4):
     """256 water-like boxes at 1 g/cm^3 with log-uniform sizes in one FP32 plan
     (autotuned bin edges, graph replay) against the FP64 plain path run one
@@ -361,6 +428,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-system ensemble section")
     ap.add_argument("--no-ik", action="store_true", help="skip the ik-forces section")
     ap.add_argument("--no-large", action="store_true", help="skip the 300,000-atom section")
+    ap.add_argument("--no-local", action="store_true", help="skip the full-Coulomb (local part) section")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -467,6 +535,8 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(boxes[0][0], boxes[0][1], L, prm)
     serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_budget_gb) if args.serve_seconds > 0 else None
     ik = None if args.no_ik else ik_run(pos, q, L, B, N, max(10, args.steps // 4), F_all, boxes[0])
+    full = None if args.no_local else local_run(pos, q, L, B, N, max(10, args.steps // 4), boxes[0],
+                                                   args.profile_reps)
     ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
     large = None if args.no_large else large_run(max(10, args.steps // 10))
 
@@ -499,6 +569,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "ik_forces": ik,
+        "full_coulomb": full,
         "ensemble": ensemble,
         "large_system": large,
     }

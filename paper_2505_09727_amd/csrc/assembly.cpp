@@ -48,8 +48,10 @@ esp_status TableStore::get(const esp_params& p, const DeviceClass** out, std::st
     }
     DeviceClass d;
     d.host = t.get();
-    std::vector<double> lcoef(t->lA);
-    lcoef.insert(lcoef.end(), t->lB.begin(), t->lB.end());
+    // local-part polynomials zero-padded to kLocalMaxDegree: A then B
+    std::vector<double> lcoef(2 * (kLocalMaxDegree + 1), 0.0);
+    std::copy(t->lA.begin(), t->lA.end(), lcoef.begin());
+    std::copy(t->lB.begin(), t->lB.end(), lcoef.begin() + kLocalMaxDegree + 1);
     const std::vector<double>* src[5] = {&t->TS, &t->Tphi, &t->poly, &t->tw, &lcoef};
     void** dst[5] = {&d.TS, &d.Tphi, &d.poly, &d.tw, &d.lcoef};
     for (int i = 0; i < 5; ++i) {
@@ -113,10 +115,23 @@ size_t tiles_region(size_t tile_bytes, int64_t N, size_t rb) {
     return align256(std::max(tile_bytes, stage));
 }
 
+static_assert(kLocalCoefStride == kLocalMaxDegree + 1, "device table stride of the local polynomials");
+
 void local_cells(const esp_params& p, int& lcs, int& R) {
     const double rho = grid_rho(p);
     lcs = std::max(1, std::min(8, (int)std::floor(2.0 * p.tile / rho)));
     R = std::max(1, (int)std::ceil(rho * (1.0 + 1e-4) * lcs / p.tile));
+}
+
+static double halo_particles(int a, int R, int lcs, int T, int n, long long N) {
+    const double edge = (double)(a + 2 * R) * T / lcs;  // grid units
+    return (double)N / ((double)n * n * n) * edge * edge * edge;
+}
+
+int local_block(int lcs, int R, int T, int n, long long N, double limit) {
+    for (int a = lcs; a > 1; --a)
+        if (lcs % a == 0 && halo_particles(a, R, lcs, T, n, N) <= limit) return a;
+    return 1;
 }
 
 size_t scratch_bytes(const esp_params& p, int64_t N) {
@@ -186,7 +201,8 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
 }
 
 LaunchSet::~LaunchSet() {
-    void* ps[] = {d_sys_, d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_, d_cols_, d_bpart_, d_epart_, d_lpart_};
+    void* ps[] = {d_sys_,  d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_,
+                  d_cols_, d_bpart_,  d_epart_,  d_lpart_,  d_litems_};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
@@ -227,6 +243,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     fgroups_.clear();
     fsys_.clear();
     bsys_.clear();
+    litems_.clear();
     std::vector<std::vector<int2>> titems_by_P(13);
     int nb_max = 1, nb_small_max = 1, n_eligible = 0;
     bool any_ik = false, any_local = false;
@@ -269,8 +286,13 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         any_local = any_local || d.local;
         if (d.local) {
             local_cells(r, d.lcs, d.lR);
+            d.lsa = local_block(d.lcs, d.lR, d.T, d.n, d.N, kLocalHaloTarget);
+            const int nsb = d.lcs / d.lsa, nb = d.tiles1 * d.tiles1 * d.tiles1;
+            d.litem_off = (int)litems_.size();
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < nsb * nsb * nsb; ++k) litems_.push_back(make_int2(s, b * nsb * nsb * nsb + k));
+            d.nlitem = (int)litems_.size() - d.litem_off;
             const double rho = grid_rho(r);
-            d.lpieces = kLocalPieces;
             d.ldeg = ct.ldeg;
             d.lsT = (double)d.lcs / d.T;
             d.lrho2 = rho * rho;
@@ -283,10 +305,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
                 msg = "local-part stencil wider than the box";
                 return ESP_E_UNSUPPORTED;
             }
-            if (2 * kLocalPieces * (ct.ldeg + 1) > kLocalCoefMax) {
-                msg = "local-part polynomials exceed their LDS table";
-                return ESP_E_UNSUPPORTED;
-            }
+
         }
         d.tiles = sl.scr.tiles;
         d.out = sl.scr.out;
@@ -388,12 +407,30 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         titems_.insert(titems_.end(), titems_by_P[P].begin(), titems_by_P[P].end());
         groups_.push_back(g);
     }
-    // first bin of every system in the launch's bin list (a system's bins are
-    // contiguous): the local part's energy partials are per bin
-    for (int k = (int)titems_.size() - 1; k >= 0; --k) hsys_[titems_[k].x].tbin_off = k;
     L_.prec = prec;
     L_.nsys = nsys;
     L_.any_local = any_local;
+    // LDS staging of a bin's halo for the local pass: the expected particle
+    // count of the largest halo with 30% headroom (a bin whose halo holds more
+    // takes the global-memory path), within 64 KB
+    L_.local_cap = 0;
+    L_.local_cells = 0;
+    L_.local_deg = 0;
+    if (any_local) {
+        double want = 0.0;
+        for (const SysDesc& d : hsys_) {
+            if (!d.local) continue;
+            const int W = d.lsa + 2 * d.lR;
+            L_.local_cells = std::max(L_.local_cells, W * W * W);
+            want = std::max(want, halo_particles(d.lsa, d.lR, d.lcs, d.T, d.n, d.N));
+        }
+        const int vb = 4 * rb;
+        const int capmax = (65536 - (L_.local_cells + 1) * 4) / vb;
+        const int cap = ((int)(1.3 * want) + 64 + 63) / 64 * 64;
+        L_.local_cap = std::max(64, std::min(cap, capmax));
+        for (const SysDesc& d : hsys_)
+            if (d.local) L_.local_deg = std::max(L_.local_deg, d.ldeg);
+    }
     L_.stream = stream;
     L_.n_pitems = (int)pitems_.size();
     L_.n_titems = (int)titems_.size();
@@ -416,6 +453,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     if ((st = put(&d_cols_, &cap_cols_, cols_, msg)) != ESP_OK) return st;
     if ((st = put(&d_fsys_, &cap_fsys_, fsys_, msg)) != ESP_OK) return st;
     if ((st = put(&d_bsys_, &cap_bsys_, bsys_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_litems_, &cap_litems_, litems_, msg)) != ESP_OK) return st;
     // partial sums are written before they are read: capacity only
     auto reserve = [&](double** dev, size_t* cap, size_t need) {
         if (need <= *cap && *dev) return ESP_OK;
@@ -432,7 +470,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     };
     if ((st = reserve(&d_bpart_, &cap_bpart_, 4 * pitems_.size())) != ESP_OK) return st;
     if ((st = reserve(&d_epart_, &cap_epart_, (size_t)n_eslots)) != ESP_OK) return st;
-    if ((st = reserve(&d_lpart_, &cap_lpart_, titems_.size())) != ESP_OK) return st;
+    if ((st = reserve(&d_lpart_, &cap_lpart_, litems_.size())) != ESP_OK) return st;
     L_.sys = d_sys_;
     L_.pitems = d_pitems_;
     L_.titems = d_titems_;
@@ -443,6 +481,8 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.bpart = d_bpart_;
     L_.epart = d_epart_;
     L_.lpart = d_lpart_;
+    L_.litems = d_litems_;
+    L_.n_litems = (int)litems_.size();
     return ESP_OK;
 }
 

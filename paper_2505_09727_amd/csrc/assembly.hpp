@@ -64,6 +64,10 @@ struct SysScratch {
 };
 // Local part: sub-cells per bin side and stencil radius for resolved params.
 void local_cells(const esp_params& p, int& lcs, int& R);
+// Local part: sub-cells per side of one work item's block (a divisor of lcs
+// whose halo, (a + 2R)^3 sub-cells, is expected to hold at most `limit`
+// particles; 1 if none does) for N particles on grid n.
+int local_block(int lcs, int R, int T, int n, long long N, double limit);
 size_t scratch_bytes(const esp_params& p, int64_t N);
 SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N);
 
@@ -107,14 +111,15 @@ class LaunchSet {
     std::vector<Group> groups_;
     std::vector<FftGroup> fgroups_;
     std::vector<SysDesc> hsys_;
-    std::vector<int2> pitems_, titems_, planes_, fsys_, bsys_;
+    std::vector<int2> pitems_, titems_, planes_, fsys_, bsys_, litems_;
     std::vector<int4> cols_;
     SysDesc* d_sys_ = nullptr;
-    int2 *d_pitems_ = nullptr, *d_titems_ = nullptr, *d_planes_ = nullptr, *d_fsys_ = nullptr, *d_bsys_ = nullptr;
+    int2 *d_pitems_ = nullptr, *d_titems_ = nullptr, *d_planes_ = nullptr, *d_fsys_ = nullptr, *d_bsys_ = nullptr,
+         *d_litems_ = nullptr;
     int4* d_cols_ = nullptr;
     double *d_bpart_ = nullptr, *d_epart_ = nullptr, *d_lpart_ = nullptr;
     size_t cap_sys_ = 0, cap_pitems_ = 0, cap_titems_ = 0, cap_planes_ = 0, cap_fsys_ = 0, cap_bsys_ = 0, cap_cols_ = 0,
-           cap_bpart_ = 0, cap_epart_ = 0, cap_lpart_ = 0;
+           cap_bpart_ = 0, cap_epart_ = 0, cap_lpart_ = 0, cap_litems_ = 0;
 };
 
 constexpr int kMaxLds = 160 * 1024;

@@ -28,9 +28,10 @@ struct SysDesc {
     int local;        // 1: local part of the split on the device (k_cellsort, k_local)
     int lcs;          // local: sub-cells per bin side (edge T / lcs >= rho / 2)
     int lR;           // local: stencil radius in sub-cells
-    int lpieces;      // local: polynomial pieces over x = r^2 / rho^2 in [0, 1)
-    int ldeg;         // local: polynomial degree
-    int tbin_off;     // index of the system's first bin in the launch's bin list
+    int ldeg;         // local: polynomial degree in x = r^2 / rho^2 (one piece on [0, 1))
+    int lsa;          // local: sub-cells per side of a local work item's block (divides lcs)
+    int litem_off;    // local: first local work item of the system in the launch's list ...
+    int nlitem;       // ... and their count (bins x (lcs / lsa)^3)
     double inv_L;     // 1/L
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
@@ -42,7 +43,7 @@ struct SysDesc {
     const void* Tphi; // per-axis influence table, n/2 + 1 entries
     const void* poly; // window polynomials, P * (degree + 1)
     const void* tw;   // twiddles exp(2 pi i t/n), n complex
-    const void* lcoef;  // local: polynomials A then B, lpieces x (ldeg + 1) each
+    const void* lcoef;  // local: polynomials A then B, each zero-padded to 17 coefficients
     // particles in the caller's order (this system's slice) and outputs
     const void* pos;  // N x 3
     const void* q;    // N
@@ -88,8 +89,9 @@ constexpr int kSmallMinSystems = 64;  // one-block binning pays only with this m
 constexpr int kParticleChunk = 1024;  // particles per chunk work item
 constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
 constexpr int kOutDoubles = 8;
-constexpr int kLocalCoefMax = 2 * 8 * 13;  // LDS reals for the local polynomials (A and B)
+constexpr int kLocalCoefStride = 17;       // padded coefficients per local polynomial (degree <= 16)
 constexpr int kLocalThreads = 256;          // threads of a local-part block
 constexpr int kCellSortCap = 4096;          // particles of a bin sorted in LDS
+constexpr double kLocalHaloTarget = 2600.0; // expected halo particles a local work item stages
 
 }  // namespace esp

@@ -752,10 +752,8 @@ __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sy
     const SysDesc& S = sys[blockIdx.x];
     double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < S.ncol; i += blockDim.x) ek += epart[S.col_off + i];
-    if (S.local) {
-        const int nb = S.tiles1 * S.tiles1 * S.tiles1;
-        for (int i = threadIdx.x; i < nb; i += blockDim.x) ek += 0.5 * lpart[S.tbin_off + i];
-    }
+    if (S.local)
+        for (int i = threadIdx.x; i < S.nlitem; i += blockDim.x) ek += 0.5 * lpart[S.litem_off + i];
     for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) {
         sq += bpart[4 * (S.pitem_off + i) + 0];
         sa += bpart[4 * (S.pitem_off + i) + 1];

@@ -40,8 +40,13 @@ struct Launch {
     int small_lds;        // LDS bytes of the one-block binning
     double* bpart;        // per particle chunk: sum q, sum |q|, sum q^2, max |q|
     double* epart;        // per x-column item: k-space energy partial
-    double* lpart;        // per bin item: local-part energy partial, sum q u^l
+    const int2* litems;   // local pass: (sys, bin x (lcs/lsa)^3 + block within the bin)
+    int n_litems;
+    double* lpart;        // per local item: local-part energy partial, sum q u^l
     int any_local;        // some system evaluates the local part
+    int local_cap;        // particles of a bin's halo the local pass stages in LDS
+    int local_cells;      // largest halo sub-cell count, (lcs + 2 lR)^3
+    int local_deg;        // largest local-part polynomial degree
 };
 
 // Systems sharing one grid size n: one launch per FFT pass.

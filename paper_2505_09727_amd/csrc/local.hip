@@ -16,9 +16,9 @@
 // rc <= L/2 at most one image of a particle lies within rc.
 //
 // Kernel. Inside rc, L(r) = 1/(4 pi r) - s(r) with s(r) = G(r/rc)/(4 pi r)
-// smooth. In grid units s and s'(r)/r are piecewise polynomials A, B in
-// x = r^2/rho^2 (fitted on the host), so a pair costs one reciprocal square
-// root and two Horner evaluations:
+// smooth. In grid units s and s'(r)/r are polynomials A, B in x = r^2/rho^2
+// (fitted on the host; the same coefficients for every lane), so a pair costs
+// one reciprocal square root and two Horner evaluations:
 //   u^l_i = (1/h)     sum_j q_j (1/(4 pi r) - A(x)),
 //   F^l_i = (q_i/h^2) sum_j q_j (1/(4 pi r^3) + B(x)) (u_i - u_j),
 // with r and u in grid units. The results go to a per-particle buffer in bin
@@ -190,27 +190,91 @@ __global__ void __launch_bounds__(kLocalThreads) k_cellsort(const SysDesc* __res
     }
 }
 
-template <typename R>
+// One pair's contribution to i's sums; d = u_i - u_j in grid units. The
+// polynomials A, B of degree D in y = x - 1/2 (x = r^2/rho^2) have the same
+// coefficients for every lane (scalar registers).
+template <typename R, int D>
+__device__ __forceinline__ void pair_term(R dx, R dy, R dz, R qj, R rho2, R inv_rho2, const R (&cA)[D + 1],
+                                          const R (&cB)[D + 1], R& up, R& fx, R& fy, R& fz) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rho2 && r2 > R(0)) {
+        const R y = r2 * inv_rho2 - R(0.5);
+        R A = cA[D], B = cB[D];
+#pragma unroll
+        for (int m = D - 1; m >= 0; --m) {
+            A = A * y + cA[m];
+            B = B * y + cB[m];
+        }
+        const R ri = rsqrt_r<R>(r2);
+        const R rc4 = R(0.079577471545947667884) * ri;  // 1/(4 pi r)
+        up += qj * (rc4 - A);
+        const R g = qj * (rc4 * ri * ri + B);
+        fx += g * dx;
+        fy += g * dy;
+        fz += g * dz;
+    }
+}
+
+// Exclusive scan of a[0..n) in LDS by the whole block; a[n] gets the total.
+__device__ void block_exclusive_scan(int* a, int n, int* wsum) {
+    const int BD = blockDim.x, per = (n + BD - 1) / BD;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += a[i];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += u;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wid; ++w) base += wsum[w];
+    int run = base + inc - sum;
+    for (int i = lo; i < hi; ++i) {
+        const int c = a[i];
+        a[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == BD - 1) a[n] = run;
+    __syncthreads();
+}
+
+// The pair sums of one block of lsa^3 sub-cells of a bin (a local work
+// item). The particles of the (lsa + 2 lR)^3 sub-cells around the block (its
+// halo) are staged in LDS, shifted into the bin's frame, in halo sub-cell order
+// (z fastest): for every (dx, dy) of the stencil the 2 lR + 1 sub-cells along z
+// form one contiguous run. A block whose halo exceeds the LDS staging walks
+// the sub-cells in global memory instead. The block's own particles are lsa^2
+// runs of consecutive sub-cells along z in the bin's sub-cell order.
+template <typename R, int D>
 __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restrict__ sys,
-                                                         const int2* __restrict__ items, double* __restrict__ lpart) {
+                                                         const int2* __restrict__ items, double* __restrict__ lpart,
+                                                         int cap) {
     using V = typename Vec4<R>::type;
-    __shared__ R coef[kLocalCoefMax];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[16];
+    __shared__ int wsum[kLocalThreads / 64];
+    __shared__ int roff[65], rglob[64];  // own runs (lsa^2 <= 64): first index in the block, in cpos
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
     if (!S.local) return;  // uniform over the block
-    const int t = wi.y, s = S.lcs, nc = s * s * s, LR = S.lR, K = S.lpieces, d1 = S.ldeg + 1;
+    const int s = S.lcs, nc = s * s * s, LR = S.lR, a = S.lsa, nsb = s / a, nsb3 = nsb * nsb * nsb;
+    const int t = wi.y / nsb3, sub = wi.y - t * nsb3;
+    const int ox = (sub / (nsb * nsb)) * a, oy = ((sub / nsb) % nsb) * a, oz = (sub % nsb) * a;
     const int t1 = S.tiles1, T = S.T, G = t1 * s;
-    const int beg = S.bin_start[t], count = S.bin_start[t + 1] - beg;
+    // degree <= D: the table is zero-padded beyond the system's degree
     const R* gc = reinterpret_cast<const R*>(S.lcoef);
-    for (int i = threadIdx.x; i < 2 * K * d1; i += blockDim.x) coef[i] = gc[i];
-    __syncthreads();
-    const R* cA = coef;
-    const R* cB = coef + K * d1;
+    R cA[D + 1], cB[D + 1];
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+        cA[m] = gc[m];
+        cB[m] = gc[kLocalCoefStride + m];
+    }
     int tx, ty, tz;
     bin_coords_l(t, S, tx, ty, tz);
-    const R rho2 = R(S.lrho2), inv_rho2 = R(1.0 / S.lrho2), Kf = R(K);
-    const R c4 = R(0.079577471545947667884);  // 1/(4 pi)
+    const R rho2 = R(S.lrho2), inv_rho2 = R(1.0 / S.lrho2);
     const R lsT = R(S.lsT);
     const R sc = R(S.n * S.inv_L);  // 1/h
     // separable sub-cell index: cell(gx, gy, gz) = X(gx) + Y(gy) + Z(gz) with
@@ -220,75 +284,154 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
     const V* cpos = reinterpret_cast<const V*>(S.cpos);
     const int* cst = S.cstart;
     V* loc = reinterpret_cast<V*>(S.loc);
-    double e = 0.0;
-    for (int k = threadIdx.x; k < count; k += blockDim.x) {
-        const V vi = cpos[beg + k];
-        const int cx = tx * s + sub_cell<R>(vi.x, 0, s, lsT);
-        const int cy = ty * s + sub_cell<R>(vi.y, 0, s, lsT);
-        const int cz = tz * s + sub_cell<R>(vi.z, 0, s, lsT);
-        R up = 0, fx = 0, fy = 0, fz = 0;
-        // i's coordinates in the frame of the neighbour's bin: each stored
-        // coordinate is relative to its own bin's origin, so the frames differ
-        // by whole bins (exact), periodic images included
-        for (int dx = -LR; dx <= LR; ++dx) {
-            int gx = cx + dx, wx = 0;
-            if (gx < 0) {
-                gx += G;
-                wx = -t1;
-            } else if (gx >= G) {
-                gx -= G;
-                wx = t1;
+    const int W = a + 2 * LR, W3 = W * W * W;
+    V* hp = reinterpret_cast<V*>(smem_raw);
+    int* hs = reinterpret_cast<int*>(smem_raw + (size_t)cap * sizeof(V));
+    // halo row h along one axis of a block starting at sub-cell o of bin row
+    // b: its global sub-cell and the shift into the bin's frame (grid units)
+    auto halo_axis = [&](int h, int b, int o, int& g, int& shift) {
+        g = b * s + o - LR + h;
+        int w = 0;
+        if (g < 0) {
+            g += G;
+            w = -t1;
+        } else if (g >= G) {
+            g -= G;
+            w = t1;
+        }
+        shift = (g / s + w - b) * T;
+    };
+    auto halo_cell = [&](int c, int& cell, R& sx, R& sy, R& sz) {
+        const int hz = c % W, hy = (c / W) % W, hx = c / (W * W);
+        int gx, gy, gz, ix, iy, iz;
+        halo_axis(hx, tx, ox, gx, ix);
+        halo_axis(hy, ty, oy, gy, iy);
+        halo_axis(hz, tz, oz, gz, iz);
+        cell = (gx / s) * xq + s * s * gx + (gy / s) * yq + s * gy + (gz / s) * zq + gz;
+        sx = R(ix);
+        sy = R(iy);
+        sz = R(iz);
+    };
+    for (int c = threadIdx.x; c < W3; c += blockDim.x) {
+        int cell;
+        R sx, sy, sz;
+        halo_cell(c, cell, sx, sy, sz);
+        hs[c] = cst[cell + 1] - cst[cell];
+    }
+    // own runs: sub-cells (ox + i, oy + j, oz .. oz + a - 1) of this bin
+    if (threadIdx.x < a * a) {
+        const int r = threadIdx.x;
+        const int c0 = t * nc + ((ox + r / a) * s + (oy + r % a)) * s + oz;
+        rglob[r] = cst[c0];
+        roff[r] = cst[c0 + a] - cst[c0];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int r = 0; r < a * a; ++r) {
+            const int c = roff[r];
+            roff[r] = run;
+            run += c;
+        }
+        roff[a * a] = run;
+    }
+    block_exclusive_scan(hs, W3, wsum);  // synchronises, so roff is complete too
+    const bool staged = hs[W3] <= cap;  // uniform over the block
+    if (staged) {
+        for (int c = threadIdx.x; c < W3; c += blockDim.x) {
+            int cell;
+            R sx, sy, sz;
+            halo_cell(c, cell, sx, sy, sz);
+            const int j0 = cst[cell], nj = cst[cell + 1] - j0;
+            V* dst = hp + hs[c];
+            for (int j = 0; j < nj; ++j) {
+                V v = cpos[j0 + j];
+                v.x += sx;
+                v.y += sy;
+                v.z += sz;
+                dst[j] = v;
             }
-            const int bx = gx / s;
-            const R xs = vi.x + R((tx - bx - wx) * T);
-            const int X = bx * xq + s * s * gx;
-            for (int dy = -LR; dy <= LR; ++dy) {
-                int gy = cy + dy, wy = 0;
-                if (gy < 0) {
-                    gy += G;
-                    wy = -t1;
-                } else if (gy >= G) {
-                    gy -= G;
-                    wy = t1;
-                }
-                const int by = gy / s;
-                const R ys = vi.y + R((ty - by - wy) * T);
-                const int XY = X + by * yq + s * gy;
-                for (int dz = -LR; dz <= LR; ++dz) {
-                    int gz = cz + dz, wz = 0;
-                    if (gz < 0) {
-                        gz += G;
-                        wz = -t1;
-                    } else if (gz >= G) {
-                        gz -= G;
-                        wz = t1;
-                    }
-                    const int bz = gz / s;
-                    const R zs = vi.z + R((tz - bz - wz) * T);
-                    const int cell = XY + bz * zq + gz;
-                    const int ja = cst[cell], jb = cst[cell + 1];
+        }
+        __syncthreads();
+    }
+    const int nown = roff[a * a];
+    double e = 0.0;
+    for (int k = threadIdx.x; k < nown; k += blockDim.x) {
+        int lo = 0, hi = a * a;  // run r with roff[r] <= k < roff[r + 1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (roff[mid] <= k)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int gi = rglob[lo] + (k - roff[lo]);
+        const V vi = cpos[gi];
+        const int lx = sub_cell<R>(vi.x, 0, s, lsT);
+        const int ly = sub_cell<R>(vi.y, 0, s, lsT);
+        const int lz = sub_cell<R>(vi.z, 0, s, lsT);
+        R up = 0, fx = 0, fy = 0, fz = 0;
+        if (staged) {
+            // halo rows hx .. hx + 2 lR around halo row hx + lR of the particle
+            const int hx = min(max(lx - ox, 0), a - 1), hy = min(max(ly - oy, 0), a - 1),
+                      hz = min(max(lz - oz, 0), a - 1);
+            for (int u = 0; u <= 2 * LR; ++u) {
+                for (int v = 0; v <= 2 * LR; ++v) {
+                    const int row = ((hx + u) * W + (hy + v)) * W + hz;
+                    const int ja = hs[row], jb = hs[row + 2 * LR + 1];
                     for (int j = ja; j < jb; ++j) {
-                        const V vj = cpos[j];
-                        const R ddx = xs - vj.x, ddy = ys - vj.y, ddz = zs - vj.z;
-                        const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                        if (r2 < rho2 && r2 > R(0)) {
-                            const R x = r2 * inv_rho2;
-                            const int pc = min((int)(x * Kf), K - 1);
-                            const R y = x * Kf - R(pc) - R(0.5);
-                            const R* a = cA + pc * d1;
-                            const R* b = cB + pc * d1;
-                            R A = a[d1 - 1], B = b[d1 - 1];
-                            for (int m = d1 - 2; m >= 0; --m) {
-                                A = A * y + a[m];
-                                B = B * y + b[m];
-                            }
-                            const R ri = rsqrt_r<R>(r2);
-                            const R rc4 = c4 * ri;
-                            up += vj.w * (rc4 - A);
-                            const R g = vj.w * (rc4 * ri * ri + B);
-                            fx += g * ddx;
-                            fy += g * ddy;
-                            fz += g * ddz;
+                        const V vj = hp[j];
+                        pair_term<R, D>(vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, vj.w, rho2, inv_rho2, cA, cB, up,
+                                        fx, fy, fz);
+                    }
+                }
+            }
+        } else {
+            const int cx = tx * s + lx, cy = ty * s + ly, cz = tz * s + lz;
+            // i's coordinates in the frame of the neighbour's bin: each stored
+            // coordinate is relative to its own bin's origin, so the frames
+            // differ by whole bins (exact), periodic images included
+            for (int dx = -LR; dx <= LR; ++dx) {
+                int gx = cx + dx, wx = 0;
+                if (gx < 0) {
+                    gx += G;
+                    wx = -t1;
+                } else if (gx >= G) {
+                    gx -= G;
+                    wx = t1;
+                }
+                const int bx = gx / s;
+                const R xs = vi.x + R((tx - bx - wx) * T);
+                const int X = bx * xq + s * s * gx;
+                for (int dy = -LR; dy <= LR; ++dy) {
+                    int gy = cy + dy, wy = 0;
+                    if (gy < 0) {
+                        gy += G;
+                        wy = -t1;
+                    } else if (gy >= G) {
+                        gy -= G;
+                        wy = t1;
+                    }
+                    const int by = gy / s;
+                    const R ys = vi.y + R((ty - by - wy) * T);
+                    const int XY = X + by * yq + s * gy;
+                    for (int dz = -LR; dz <= LR; ++dz) {
+                        int gz = cz + dz, wz = 0;
+                        if (gz < 0) {
+                            gz += G;
+                            wz = -t1;
+                        } else if (gz >= G) {
+                            gz -= G;
+                            wz = t1;
+                        }
+                        const int bz = gz / s;
+                        const R zs = vi.z + R((tz - bz - wz) * T);
+                        const int cell = XY + bz * zq + gz;
+                        const int ja = cst[cell], jb = cst[cell + 1];
+                        for (int j = ja; j < jb; ++j) {
+                            const V vj = cpos[j];
+                            pair_term<R, D>(xs - vj.x, ys - vj.y, zs - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
+                                            fy, fz);
                         }
                     }
                 }
@@ -301,23 +444,42 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
         o.y = fq * fx;
         o.z = fq * fy;
         o.w = fq * fz;
-        loc[S.cidx[beg + k]] = o;
+        loc[S.cidx[gi]] = o;
         e += (double)vi.w * (double)pot;
     }
     e = block_sum(e, red);
     if (threadIdx.x == 0) lpart[blockIdx.x] = e;
 }
 
-hipError_t launch_local(const Launch& L) {
-    if (!L.any_local || L.n_titems == 0) return hipSuccess;
-    if (L.prec == 64) {
-        k_cellsort<double><<<L.n_titems, kLocalThreads, 0, L.stream>>>(L.sys, L.titems);
-        k_local<double><<<L.n_titems, kLocalThreads, 0, L.stream>>>(L.sys, L.titems, L.lpart);
-    } else {
-        k_cellsort<float><<<L.n_titems, kLocalThreads, 0, L.stream>>>(L.sys, L.titems);
-        k_local<float><<<L.n_titems, kLocalThreads, 0, L.stream>>>(L.sys, L.titems, L.lpart);
+template <typename R, int D>
+static hipError_t local_d(const Launch& L) {
+    const int lds = L.local_cap * (int)sizeof(typename Vec4<R>::type) + (L.local_cells + 1) * 4;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_local<R, D>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
     }
+    k_cellsort<R><<<L.n_titems, kLocalThreads, 0, L.stream>>>(L.sys, L.titems);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_local<R, D><<<L.n_litems, kLocalThreads, lds, L.stream>>>(L.sys, L.litems, L.lpart, L.local_cap);
     return hipGetLastError();
+}
+
+// the launch's largest degree, rounded up to an even kernel instance
+template <typename R>
+static hipError_t local_t(const Launch& L) {
+    if (L.local_deg <= 8) return local_d<R, 8>(L);
+    if (L.local_deg <= 10) return local_d<R, 10>(L);
+    if (L.local_deg <= 12) return local_d<R, 12>(L);
+    if (L.local_deg <= 14) return local_d<R, 14>(L);
+    if (L.local_deg <= kLocalCoefStride - 1) return local_d<R, 16>(L);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_local(const Launch& L) {
+    if (!L.any_local || L.n_titems == 0 || L.n_litems == 0) return hipSuccess;
+    return L.prec == 64 ? local_t<double>(L) : local_t<float>(L);
 }
 
 }  // namespace esp

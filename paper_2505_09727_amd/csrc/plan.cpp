@@ -506,8 +506,8 @@ void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, d
 //   s'(r)/r = (1/(4 pi rho^3 t)) int_0^1 v chi'(t v) dv,
 // smooth functions of x = t^2 without cancellation at small t. Each is fitted
 // by Chebyshev interpolation on kLocalPieces equal intervals of x, at the
-// smallest degree whose error stays below 1e-12 of the function's largest
-// value. Memoised per (c, rho).
+// smallest degree (kLocalMinDegree .. kLocalMaxDegree) whose error stays
+// below 1e-12 of the function's largest value. Memoised per (c, rho).
 void local_polynomials(double c, double rho, int& degree, std::vector<double>& A, std::vector<double>& B) {
     static std::mutex mu;
     static std::map<std::pair<double, double>, std::tuple<int, std::vector<double>, std::vector<double>>> cache;
@@ -539,7 +539,7 @@ void local_polynomials(double c, double rho, int& degree, std::vector<double>& A
         }
         return a / (I1 * 4.0 * kPi * rho * rho * rho * t);
     };
-    const int K = kLocalPieces, nchk = 33;
+    const int K = kLocalPieces, nchk = 257;
     std::vector<double> chk_x, chk_s, chk_b;
     double ms = 0.0, mb = 0.0;
     for (int k = 0; k < K; ++k)
@@ -556,7 +556,7 @@ void local_polynomials(double c, double rho, int& degree, std::vector<double>& A
         for (int m = d; m >= 0; --m) v = v * y + a[m];
         return v;
     };
-    int d = 4;
+    int d = kLocalMinDegree;
     for (;; ++d) {
         A.assign((size_t)K * (d + 1), 0.0);
         B.assign((size_t)K * (d + 1), 0.0);

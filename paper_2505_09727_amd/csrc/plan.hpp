@@ -53,12 +53,14 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
 void window_polynomials(esp_params& p, std::vector<double>& coef);
 void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<double>& Tphi);
 void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, double* dLr);
-// Piecewise polynomials of the local part for the device (grid units):
-// pieces of x = r^2/rho^2 in [k/K, (k+1)/K), K = kLocalPieces, each in
-// y = K x - k - 1/2. A approximates the smooth part s(r), so that
-// L(r) = 1/(4 pi r) - A, and B approximates s'(r)/r.
-constexpr int kLocalPieces = 8;
-constexpr int kLocalMaxDegree = 12;
+// Polynomials of the local part for the device (grid units), in
+// y = K x - k - 1/2 on pieces [k/K, (k+1)/K) of x = r^2/rho^2 (K =
+// kLocalPieces: one piece, so a pair's coefficients are the same for every
+// lane). A approximates the smooth part s(r), so that L(r) = 1/(4 pi r) - A,
+// and B approximates s'(r)/r.
+constexpr int kLocalPieces = 1;
+constexpr int kLocalMinDegree = 8;
+constexpr int kLocalMaxDegree = 16;
 void local_polynomials(double c, double rho, int& degree, std::vector<double>& A, std::vector<double>& B);
 
 // Tables of one parameter class. With rc proportional to h (the default

@@ -110,7 +110,7 @@ def test_local_polynomials_match_reference_kernel(tol, L):
     p = esp.esp_plan_query(L, 9000, tol)
     A, B = esp.esp_local_coeffs(p)
     K, d1 = A.shape
-    assert K == 8 and 5 <= d1 <= 13
+    assert K == 1 and 9 <= d1 <= 17
     h, rho = p.h, p.rc / p.h
     r = np.linspace(1e-3, 1.0 - 1e-9, 4001) * p.rc
     rg = r / h

@@ -165,6 +165,22 @@ def test_ragged_positions_and_edges():
     plan.close()
 
 
+def test_dense_cluster_takes_the_global_paths():
+    # 4500 of 6000 atoms packed into one bin: that bin's sub-cell sort runs
+    # beyond its LDS staging and the halos around it exceed the pair pass's
+    # LDS staging, so both take their global-memory paths; the rest of the box
+    # stays on the staged paths
+    pos, q = W.water_box(2000, 24.0, seed=11)
+    rng = np.random.default_rng(11)
+    pos = pos.copy()
+    pos[:4500] = rng.uniform(0.5, 7.5, size=(4500, 3))
+    plan = Plan(24.0, len(q), 1e-4, precision=64, degree=16, local=1)
+    p = plan.params[0]
+    assert p.tile * p.h >= 7.5
+    check(plan, pos, q, 1e-9, 1e-10)
+    plan.close()
+
+
 def test_batch_alone_and_binning_paths_bitwise():
     # 70 small systems take the one-block binning in a batch and the chunked
     # kernels alone; the local sums run in the canonical sub-cell order either
