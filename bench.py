@@ -244,14 +244,13 @@ def _pairs_within(pos, L, rc, chunk=512):
     return cnt
 
 
-def local_run(pos, q, L, B, N, steps, box0, reps):
+def local_run(pos, q, L, B, N, steps, box0, reps, ewald0):
     """The same batch with the local part of the split on the device (full
     Coulomb phi, F, E): cost beside the long-range step, the local phase's
     time and ALU roofline, and box 0 against classical Ewald (the paper's
     Delta) and against the reference five-step plus local sum."""
     import ctypes as C
     import torch
-    from oracle.ewald import ewald
     from oracle.fivestep import five_step
     from oracle.metrics import rel_rms
     from oracle.split import PSWFSplit
@@ -282,7 +281,7 @@ def local_run(pos, q, L, B, N, steps, box0, reps):
     ul, gl = local_sum(pos0, q0, L, PSWFSplit(p.c, p.rc))
     F_ref = ref["F"] - q0[:, None] * gl
     E_ref = 0.5 * float(np.dot(q0, ref["phi"] + ul))
-    _, F_e, E_e = ewald(box0[0], q0, L)
+    F_e, E_e = ewald0
     pairs = _pairs_within(pos0, L, p.rc)
     deg = esp_local_coeffs(p)[0].shape[1] - 1
     fpp = 27 + 4 * deg
@@ -298,6 +297,57 @@ def local_run(pos, q, L, B, N, steps, box0, reps):
                                "algorithmic_flops_per_launch": flops, "pairs_per_particle": pairs / N,
                                "flops_per_pair": fpp, "rc": p.rc},
             "what": "full Coulomb (long-range + local part within rc) on the same batch"}
+
+
+FFT_SIZES = (8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72, 96, 108, 128, 144)
+
+
+def classical_run(pos, q, L, B, N, steps, box0, ewald0, ms_esp, ms_esp_full, delta_esp, tol=1e-4):
+    """The classical method (Gaussian split, B-spline window of order 5, the
+    ESP cutoff) on the same batch: the smallest grid whose full-Coulomb force
+    error on box 0 against Ewald meets the tolerance (eq. cemparameters' grid
+    pushed up for aliasing), then the batch at that grid beside ESP."""
+    import torch
+    from oracle.metrics import rel_rms
+    from paper_2505_09727_amd.esp import Plan, esp_plan_query
+    dev = torch.device("cuda:0")
+    F_e, E_e = ewald0
+    p0 = esp_plan_query(L, N, tol, method=1)
+    p_esp = esp_plan_query(L, N, tol)
+    t0 = torch.tensor(box0[0], dtype=torch.float32, device=dev)
+    q0 = torch.tensor(box0[1], dtype=torch.float32, device=dev)
+    trials = []
+    chosen = None
+    for n in [m for m in FFT_SIZES if m >= min(p0.nf, 24)]:
+        pl = Plan(L, N, tol, method=1, nf=n, local=1)
+        ph = torch.empty(N, dtype=torch.float32, device=dev)
+        F = torch.empty((N, 3), dtype=torch.float32, device=dev)
+        pl.longrange(t0, q0, ph, F)
+        pl.close()
+        d = rel_rms(F.cpu().double().numpy(), F_e)
+        trials.append({"grid": n, "delta_F_vs_ewald": d})
+        if d <= tol:
+            chosen = n
+            break
+    out = {"P": p0.P, "alpha": p0.c, "rc": p0.rc, "grid_formula": p0.nf, "calibration": trials, "grid": chosen,
+           "grid_esp": p_esp.nf, "delta_F_vs_ewald_esp": delta_esp}
+    if chosen is None:
+        return out
+    out["grid_ratio_R"] = (chosen / p_esp.nf) ** 3
+    for local, key in ((0, "longrange"), (1, "full_coulomb")):
+        plan = Plan([L] * B, [N] * B, tol, method=1, nf=chosen, local=local)
+        phi = torch.empty(B * N, dtype=torch.float32, device=dev)
+        F = torch.empty((B * N, 3), dtype=torch.float32, device=dev)
+        ext = torch.cuda.ExternalStream(plan.stream)
+        plan.set_graph(True)
+        for _ in range(3):
+            plan.longrange_async(pos, q, phi, F)
+        ms = _time_plan(plan, ext, pos, q, phi, F, steps)
+        plan.close()
+        ref = ms_esp if local == 0 else ms_esp_full
+        out[key] = {"ms_per_step": ms, "particle_steps_per_s": B * N / (ms / 1e3),
+                    "esp_ms_per_step": ref, "esp_speedup": (ms / ref) if ref else None}
+    return out
 
 
 def ensemble_run(steps, seed=4):
@@ -429,6 +479,7 @@ def main():
     ap.add_argument("--no-ik", action="store_true", help="skip the ik-forces section")
     ap.add_argument("--no-large", action="store_true", help="skip the 300,000-atom section")
     ap.add_argument("--no-local", action="store_true", help="skip the full-Coulomb (local part) section")
+    ap.add_argument("--no-classical", action="store_true", help="skip the classical-method (PME) comparison")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -535,8 +586,18 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(boxes[0][0], boxes[0][1], L, prm)
     serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_budget_gb) if args.serve_seconds > 0 else None
     ik = None if args.no_ik else ik_run(pos, q, L, B, N, max(10, args.steps // 4), F_all, boxes[0])
+    ewald0 = None
+    if not (args.no_local and args.no_classical):
+        from oracle.ewald import ewald
+        _, F_e0, E_e0 = ewald(boxes[0][0], boxes[0][1], L)
+        ewald0 = (F_e0, E_e0)
     full = None if args.no_local else local_run(pos, q, L, B, N, max(10, args.steps // 4), boxes[0],
-                                                   args.profile_reps)
+                                                   args.profile_reps, ewald0)
+    classical = None
+    if not args.no_classical:
+        classical = classical_run(pos, q, L, B, N, max(10, args.steps // 4), boxes[0], ewald0, ms_per_step,
+                                  full["ms_per_step"] if full else None,
+                                  full["delta_F_vs_ewald"] if full else None)
     ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
     large = None if args.no_large else large_run(max(10, args.steps // 10))
 
@@ -570,6 +631,7 @@ def main():
         "serving": serving,
         "ik_forces": ik,
         "full_coulomb": full,
+        "classical_method": classical,
         "ensemble": ensemble,
         "large_system": large,
     }

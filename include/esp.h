@@ -80,8 +80,9 @@ typedef struct {
                              the half spectrum fits in LDS (nf <= 32 in FP32,
                              <= 24 in FP64), three passes otherwise. Both are
                              deterministic; esp_plan_autotune may pick either. */
-    double c;             /* splitting-kernel PSWF shape parameter */
-    double c1;            /* window PSWF shape parameter */
+    double c;             /* splitting-kernel shape parameter: PSWF c (method 0) or the
+                             Gaussian's alpha (method 1, default log(1/tol)) */
+    double c1;            /* window PSWF shape parameter (method 0; 0 for method 1) */
     double rc;            /* cutoff radius of the local part */
     double h_max;         /* default-grid spacing bound (0: 1.25, length units) */
     double kappa;         /* default-cutoff margin (0: 1.2) */
@@ -98,6 +99,15 @@ typedef struct {
                              localpart, kernel L(r) inside rc) on the device, so that
                              phi, F and E are the full Coulomb values of eq. task
                              (needs rc <= L/2); 0: the long-range part only */
+    int    method;        /* 0: ESP (PSWF splitting kernel and PSWF window, default);
+                             1: the classical method (Methods, classical fast Ewald
+                             methods, eq. cem): Gaussian splitting kernel
+                             chi(t) = 2 sqrt(alpha/pi) exp(-alpha t^2), t = r/rc, and the
+                             cardinal B-spline of order P as window, with the defaults
+                             alpha = log(1/tol) and nf = 2 ceil(alpha L/(pi rc)) of eq.
+                             cemparameters (rounded up to a supported grid), P = 5 and
+                             rc the ESP cutoff at the same tolerance. Same kernels and
+                             outputs; a baseline on the same hardware. */
 } esp_params;
 
 typedef struct esp_plan esp_plan;

@@ -92,6 +92,6 @@ constexpr int kOutDoubles = 8;
 constexpr int kLocalCoefStride = 17;       // padded coefficients per local polynomial (degree <= 16)
 constexpr int kLocalThreads = 256;          // threads of a local-part block
 constexpr int kCellSortCap = 4096;          // particles of a bin sorted in LDS
-constexpr double kLocalHaloTarget = 2600.0; // expected halo particles a local work item stages
+constexpr double kLocalHaloTarget = 3000.0; // expected halo particles a local work item stages
 
 }  // namespace esp

@@ -297,6 +297,75 @@ static double chi0_over_I1(double c) {
     return v;
 }
 
+// Classical method (Methods, classical fast Ewald methods, eq. cem): Gaussian
+// splitting kernel chi(t) = 2 sqrt(alpha/pi) exp(-alpha t^2) (t = r/rc; its
+// transform chi^(w) = exp(-w^2/(4 alpha)), classical Ewald with
+// beta = sqrt(alpha)/rc) and the cardinal B-spline of order P as window,
+// phi^_1(xi) = h (sin(xi h/2)/(xi h/2))^P.
+static double gauss_chi(double alpha, double t) { return 2.0 * std::sqrt(alpha / kPi) * std::exp(-alpha * t * t); }
+
+// Centred cardinal B-spline of order P (support [-P/2, P/2]) by the
+// Cox-de Boor recursion M_k(x) = (x M_{k-1}(x) + (k - x) M_{k-1}(x - 1))/(k - 1).
+static double bspline(int P, double x) {
+    x += 0.5 * P;
+    if (x <= 0.0 || x >= P) return 0.0;
+    double M[16];
+    for (int j = 0; j < P; ++j) M[j] = (x >= j && x < j + 1) ? 1.0 : 0.0;  // M_1(x - j)
+    for (int k = 2; k <= P; ++k)
+        for (int j = 0; j + k <= P; ++j) {
+            const double xj = x - j;
+            M[j] = (xj * M[j] + (k - xj) * M[j + 1]) / (k - 1);
+        }
+    return M[0];
+}
+
+static double sinc(double x) { return std::fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : std::sin(x) / x; }
+
+// Parameters of the classical method: alpha = log(1/eps) and
+// n_f = 2 ceil(alpha L/(pi rc)) (eq. cemparameters), rounded up to a grid size
+// with FFT kernels; P = 5 (the default of common MD codes); rc the ESP cutoff
+// at the same tolerance unless given.
+static esp_status resolve_classical(double L, int64_t N, double tol, esp_params r, esp_params* out,
+                                    std::string& msg) {
+    if (r.c <= 0) r.c = std::log(1.0 / tol);
+    if (r.P <= 0) r.P = 5;
+    if (r.P < 4 || r.P > 12) { msg = "window width P must lie in [4, 12]"; return ESP_E_UNSUPPORTED; }
+    if (r.h_max <= 0) r.h_max = 1.25;
+    if (r.kappa <= 0) r.kappa = 1.2;
+    if (r.rc <= 0) {
+        const int n_esp = grid_size(L, r.h_max);
+        r.rc = r.kappa * c_for_tolerance(tol) / kPi * (L / n_esp);
+    }
+    if (r.nf <= 0) {
+        int n = 2 * (int)std::ceil(r.c * L / (kPi * r.rc) - 1e-12);
+        while (n <= 144 && !is_smooth(n)) n += 2;
+        r.nf = std::max(n, 8);
+    }
+    if (!is_smooth(r.nf) || r.nf < 8 || r.nf > 144) {
+        msg = "grid size must be even, of the form 2^a 3^b, within [8, 144]";
+        return ESP_E_UNSUPPORTED;
+    }
+    if (r.nf < r.P) { msg = "grid size must be at least P"; return ESP_E_UNSUPPORTED; }
+    r.h = L / r.nf;
+    const double rho = std::round(r.rc / r.h * 1e9) / 1e9;
+    if (r.precision == 0) r.precision = 32;
+    if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
+    if (r.tile != 0 && (r.tile < 8 || r.tile > 16)) { msg = "tile must lie in [8, 16]"; return ESP_E_UNSUPPORTED; }
+    if (r.fft_passes != 0 && r.fft_passes != 1) { msg = "fft_passes must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.force_method != 0 && r.force_method != 1) { msg = "force_method must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.local != 0 && r.local != 1) { msg = "local must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.local && rho > 0.5 * r.nf) {
+        msg = "the local part needs rc <= L/2 (nearest images only)";
+        return ESP_E_UNSUPPORTED;
+    }
+    r.c1 = 0.0;                       // the window is the B-spline: no shape parameter
+    r.degree = std::max(4, r.P - 1);  // exact piecewise polynomial
+    r.s0 = gauss_chi(r.c, 0.0) / (4.0 * kPi * r.rc);
+    (void)N;
+    *out = r;
+    return ESP_OK;
+}
+
 esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req, esp_params* out,
                           std::string& msg) {
     esp_params r{};
@@ -306,6 +375,8 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (!(tol >= 1e-8 && tol <= 1e-2)) { msg = "tol must lie in [1e-8, 1e-2]"; return ESP_E_INVALID; }
     r.L = L;
     r.tol = tol;
+    if (r.method != 0 && r.method != 1) { msg = "method must be 0 (ESP) or 1 (classical)"; return ESP_E_INVALID; }
+    if (r.method == 1) return resolve_classical(L, N, tol, r, out, msg);
     if (r.c <= 0) r.c = c_for_tolerance(tol);
     if (r.P <= 0) r.P = order_for_tol(tol);
     if (r.P < 4 || r.P > 12) { msg = "window width P must lie in [4, 12]"; return ESP_E_UNSUPPORTED; }
@@ -428,6 +499,18 @@ static std::vector<double> cheb_fit(F f, int d) {
 }
 
 void window_polynomials(esp_params& p, std::vector<double>& coef) {
+    if (p.method == 1) {
+        // B-spline: weight of point l0 + j is B_P(y + 1/2 + P/2 - 1 - j), a
+        // polynomial of degree P - 1 in y on [-1/2, 1/2)
+        const int P = p.P, d = std::max(4, P - 1);
+        coef.assign((size_t)P * (d + 1), 0.0);
+        for (int j = 0; j < P; ++j) {
+            const std::vector<double> a = cheb_fit([&](double y) { return bspline(P, y + 0.5 + 0.5 * P - 1.0 - j); }, d);
+            for (int m = 0; m <= d; ++m) coef[(size_t)j * (d + 1) + m] = a[m];
+        }
+        p.degree = d;
+        return;
+    }
     Prolate win(p.c1);
     const int P = p.P;
     const double peak = win(0.0);
@@ -463,6 +546,21 @@ void window_polynomials(esp_params& p, std::vector<double>& coef) {
 }
 
 void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<double>& Tphi) {
+    if (p.method == 1) {
+        const int n = p.nf, h2 = n / 2, P = p.P;
+        const double L = p.L, h = p.h, pref = std::pow(h, 6) / (L * L * L);
+        TS.assign(3 * h2 * h2 + 1, 0.0);
+        for (int m2 = 1; m2 <= 3 * h2 * h2; ++m2) {
+            const double k = 2 * kPi * std::sqrt((double)m2) / L, w = p.rc * k;
+            TS[m2] = pref * std::exp(-w * w / (4.0 * p.c)) / (k * k);
+        }
+        Tphi.assign(h2 + 1, 0.0);
+        for (int m = 0; m <= h2; ++m) {
+            const double ph = h * std::pow(sinc(kPi * m / n), P);  // xi h / 2 = pi m / n
+            Tphi[m] = 1.0 / (ph * ph);
+        }
+        return;
+    }
     Prolate chi(p.c), win(p.c1);
     const int n = p.nf, h2 = n / 2, P = p.P;
     const double L = p.L, h = p.h, I1 = chi.integral(1.0);
@@ -482,6 +580,20 @@ void influence_tables(const esp_params& p, std::vector<double>& TS, std::vector<
 }
 
 void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, double* dLr) {
+    if (p.method == 1) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double t = r[i] / p.rc;
+            if (t >= 1.0) {
+                Lr[i] = 0.0;
+                dLr[i] = 0.0;
+                continue;
+            }
+            const double Gc = std::erfc(std::sqrt(p.c) * t);
+            Lr[i] = Gc / (4 * kPi * r[i]);
+            dLr[i] = -Gc / (4 * kPi * r[i] * r[i]) - gauss_chi(p.c, t) / (p.rc * 4 * kPi * r[i]);
+        }
+        return;
+    }
     Prolate chi(p.c);
     const double I1 = chi.integral(1.0);
     for (int64_t i = 0; i < n; ++i) {
@@ -508,10 +620,11 @@ void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, d
 // by Chebyshev interpolation on kLocalPieces equal intervals of x, at the
 // smallest degree (kLocalMinDegree .. kLocalMaxDegree) whose error stays
 // below 1e-12 of the function's largest value. Memoised per (c, rho).
-void local_polynomials(double c, double rho, int& degree, std::vector<double>& A, std::vector<double>& B) {
+void local_polynomials(int method, double c, double rho, int& degree, std::vector<double>& A,
+                       std::vector<double>& B) {
     static std::mutex mu;
-    static std::map<std::pair<double, double>, std::tuple<int, std::vector<double>, std::vector<double>>> cache;
-    const auto key = std::make_pair(c, rho);
+    static std::map<std::tuple<int, double, double>, std::tuple<int, std::vector<double>, std::vector<double>>> cache;
+    const auto key = std::make_tuple(method, c, rho);
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = cache.find(key);
@@ -520,24 +633,27 @@ void local_polynomials(double c, double rho, int& degree, std::vector<double>& A
             return;
         }
     }
-    Prolate psi(c);
-    const double I1 = psi.integral(1.0);
+    // chi and chi' of the split on [0, 1]: PSWF psi/int_0^1 psi, or Gaussian
+    Prolate psi(method == 1 ? 1.0 : c);
+    const double I1 = method == 1 ? 1.0 : psi.integral(1.0);
+    auto chi = [&](double t) { return method == 1 ? gauss_chi(c, t) : psi(t) / I1; };
+    auto dchi = [&](double t) { return method == 1 ? -2.0 * c * t * gauss_chi(c, t) : psi.deriv(t) / I1; };
     std::vector<double> gx, gw;
     gauss_legendre(40, gx, gw);
     auto sfun = [&](double x) {
         const double t = std::sqrt(std::max(x, 0.0));
         double a = 0.0;
-        for (size_t i = 0; i < gx.size(); ++i) a += 0.5 * gw[i] * psi(t * 0.5 * (gx[i] + 1.0));
-        return a / (I1 * 4.0 * kPi * rho);
+        for (size_t i = 0; i < gx.size(); ++i) a += 0.5 * gw[i] * chi(t * 0.5 * (gx[i] + 1.0));
+        return a / (4.0 * kPi * rho);
     };
     auto bfun = [&](double x) {
         const double t = std::sqrt(x);
         double a = 0.0;
         for (size_t i = 0; i < gx.size(); ++i) {
             const double v = 0.5 * (gx[i] + 1.0);
-            a += 0.5 * gw[i] * v * psi.deriv(t * v);
+            a += 0.5 * gw[i] * v * dchi(t * v);
         }
-        return a / (I1 * 4.0 * kPi * rho * rho * rho * t);
+        return a / (4.0 * kPi * rho * rho * rho * t);
     };
     const int K = kLocalPieces, nchk = 257;
     std::vector<double> chk_x, chk_s, chk_b;
@@ -581,6 +697,7 @@ void local_polynomials(double c, double rho, int& degree, std::vector<double>& A
 }
 
 double grid_rho(const esp_params& p) {
+    if (p.method == 1) return std::round(p.rc / p.h * 1e9) / 1e9;
     double rho = p.kappa * p.c / kPi;  // the default rule's exact rc/h
     if (std::fabs(rho * p.h - p.rc) > 1e-12 * p.rc) rho = std::round(p.rc / p.h * 1e9) / 1e9;
     return rho;
@@ -588,9 +705,9 @@ double grid_rho(const esp_params& p) {
 
 std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, double, double, double>, std::shared_ptr<const ClassTables>> cache;
+    static std::map<std::tuple<int, int, int, int, double, double, double>, std::shared_ptr<const ClassTables>> cache;
     const double rho = grid_rho(p);
-    const auto key = std::make_tuple(p.nf, p.P, p.degree, p.c, p.c1, rho);
+    const auto key = std::make_tuple(p.method, p.nf, p.P, p.degree, p.c, p.c1, rho);
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = cache.find(key);
@@ -614,9 +731,13 @@ std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {
         t->tw.push_back(std::cos(a));
         t->tw.push_back(std::sin(a));
     }
-    Prolate chi(p.c);
-    t->s0_ref = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * rho);
-    local_polynomials(p.c, rho, t->ldeg, t->lA, t->lB);
+    if (p.method == 1) {
+        t->s0_ref = gauss_chi(p.c, 0.0) / (4.0 * kPi * rho);
+    } else {
+        Prolate chi(p.c);
+        t->s0_ref = chi(0.0) / (chi.integral(1.0) * 4.0 * kPi * rho);
+    }
+    local_polynomials(p.method, p.c, rho, t->ldeg, t->lA, t->lB);
     double wm = 0.0;
     for (int j = 0; j < p.P; ++j)
         for (int s = 0; s <= 64; ++s) {

@@ -61,7 +61,8 @@ void local_kernel(const esp_params& p, const double* r, int64_t n, double* Lr, d
 constexpr int kLocalPieces = 1;
 constexpr int kLocalMinDegree = 8;
 constexpr int kLocalMaxDegree = 16;
-void local_polynomials(double c, double rho, int& degree, std::vector<double>& A, std::vector<double>& B);
+void local_polynomials(int method, double c, double rho, int& degree, std::vector<double>& A,
+                       std::vector<double>& B);
 
 // Tables of one parameter class. With rc proportional to h (the default
 // rule), the influence tables, window polynomials and c1 depend on

@@ -299,7 +299,7 @@ esp_status esp_local_coeffs(const esp_params* resolved, double* A, double* B, in
     try {
         std::vector<double> a, b;
         int d = 0;
-        local_polynomials(resolved->c, grid_rho(*resolved), d, a, b);
+        local_polynomials(resolved->method, resolved->c, grid_rho(*resolved), d, a, b);
         std::memcpy(A, a.data(), a.size() * sizeof(double));
         std::memcpy(B, b.data(), b.size() * sizeof(double));
         *pieces = kLocalPieces;

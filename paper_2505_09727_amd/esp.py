@@ -31,7 +31,8 @@ class esp_params(C.Structure):
                 ("tile", C.c_int), ("fft_passes", C.c_int),
                 ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
-                ("s0", C.c_double), ("force_method", C.c_int), ("local", C.c_int)]
+                ("s0", C.c_double), ("force_method", C.c_int), ("local", C.c_int),
+                ("method", C.c_int)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1,0 +1,110 @@
+"""The classical method (method = 1: Gaussian splitting kernel, B-spline window)
+through the same kernels, against the classical reference five-step method
+(oracle.classical) at the library's parameters, with and without the local
+part, and mixed with ESP systems in one batch.
+
+Workloads: the 9000-atom water-like box (L = 31) at the default parameters of
+eq. cemparameters (alpha = log(1/eps), P = 5, the ESP cutoff), a 2100-atom box
+at P = 4, 6 and 8, and a batch of ESP and classical systems."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.classical import five_step_classical
+from oracle.ewald import ewald
+from oracle.metrics import rel_rms
+from oracle.split import GaussianSplit
+from oracle.spectral import local_sum
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_09727_amd.esp import Plan  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def run(plan, pos, q):
+    dt = torch.float64 if plan.precision == 64 else torch.float32
+    tp = torch.tensor(np.ascontiguousarray(pos), dtype=dt, device=DEV)
+    tq = torch.tensor(np.ascontiguousarray(q), dtype=dt, device=DEV)
+    phi = torch.empty(len(q), dtype=dt, device=DEV)
+    F = torch.empty((len(q), 3), dtype=dt, device=DEV)
+    E = plan.longrange(tp, tq, phi, F)
+    torch.cuda.synchronize()
+    return phi.cpu().double().numpy(), F.cpu().double().numpy(), np.asarray(E)
+
+
+def reference(pos, q, p, local):
+    r = five_step_classical(pos, q, p.L, p.nf, p.P, p.c, p.rc)
+    phi, F = r["phi"], r["F"]
+    if local:
+        ul, gl = local_sum(pos, q, p.L, GaussianSplit(p.c, p.rc, support=p.rc))
+        phi, F = phi + ul, F - q[:, None] * gl
+    return phi, F, 0.5 * float(np.dot(q, phi))
+
+
+def check(plan, pos, q, local, bar_F, bar_E):
+    phi, F, E = run(plan, pos, q)
+    p = plan.params[0]
+    assert p.method == 1
+    pr = pos if plan.precision == 64 else pos.astype(np.float32).astype(np.float64)
+    phi_r, F_r, E_r = reference(pr, q, p, local)
+    eF, ephi, eE = rel_rms(F, F_r), rel_rms(phi, phi_r), abs(E[0] - E_r) / abs(E_r)
+    print(f"classical N={len(q)} n={p.nf} P={p.P} alpha={p.c:.3f} local={local} prec={plan.precision}: "
+          f"relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
+    assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    return phi, F, E
+
+
+@pytest.fixture(scope="module")
+def water9k():
+    pos, q = W.water_box(3000, 31.0, seed=2)
+    _, F, E = ewald(pos, q, 31.0)
+    return pos, q, 31.0, F, E
+
+
+@pytest.mark.parametrize("prec,bar_F,bar_E", [(64, 1e-10, 1e-10), (32, 1e-5, 1e-6)])
+@pytest.mark.parametrize("local", [0, 1])
+def test_water9k_default_parameters(water9k, prec, bar_F, bar_E, local):
+    pos, q, L, F_e, E_e = water9k
+    plan = Plan(L, len(q), 1e-4, method=1, precision=prec, local=local)
+    p = plan.params[0]
+    assert (p.P, p.degree) == (5, 4) and abs(p.c - np.log(1e4)) < 1e-12
+    phi, F, E = check(plan, pos, q, local, bar_F, bar_E)
+    if local:
+        print(f"classical water9k n={p.nf} prec={prec}: Delta={rel_rms(F, F_e):.2e}")
+        assert rel_rms(F, F_e) < 1e-3
+    plan.close()
+
+
+@pytest.mark.parametrize("P,n", [(4, 24), (6, 36), (8, 24)])
+def test_other_window_orders(P, n):
+    pos, q = W.water_box(700, 20.0, seed=P)
+    for prec, bar in ((64, 1e-10), (32, 1e-5)):
+        plan = Plan(20.0, len(q), 1e-4, method=1, P=P, nf=n, precision=prec, local=1)
+        check(plan, pos, q, 1, bar, bar / 10)
+        plan.close()
+
+
+def test_classical_and_esp_share_a_batch():
+    systems = [W.water_box_at_density(3 * (400 + 150 * i), seed=300 + i) for i in range(6)]
+    Ls = [s[2] for s in systems]
+    Ns = [len(s[1]) for s in systems]
+    off = np.cumsum([0] + Ns)
+    per = [{"method": i % 2, "local": 1} for i in range(6)]
+    pos = np.concatenate([s[0] for s in systems])
+    q = np.concatenate([s[1] for s in systems])
+    batch = Plan(Ls, Ns, 1e-4, per_system=per)
+    phi_b, F_b, E_b = run(batch, pos, q)
+    assert [p.method for p in batch.params] == [0, 1, 0, 1, 0, 1]
+    batch.close()
+    for i in range(6):
+        single = Plan(Ls[i], Ns[i], 1e-4, **per[i])
+        phi_s, F_s, E_s = run(single, systems[i][0], systems[i][1])
+        single.close()
+        sl = slice(off[i], off[i + 1])
+        assert np.array_equal(F_s, F_b[sl]) and np.array_equal(phi_s, phi_b[sl]) and E_s[0] == E_b[i], i
