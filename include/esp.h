@@ -108,14 +108,20 @@ typedef struct {
                              cemparameters (rounded up to a supported grid), P = 5 and
                              rc the ESP cutoff at the same tolerance. Same kernels and
                              outputs; a baseline on the same hardware. */
+    double Ly, Lz;        /* box sides along y and z (0: equal to L, a cubic box).
+                             A non-cubic (orthorhombic) box keeps a cubic index grid
+                             nf^3 with spacing L_d/nf per axis; nf follows the longest
+                             side and rc the coarsest spacing; the influence function
+                             becomes a per-system table. Set by esp_plan_create from
+                             box[1], box[2]; outputs always hold the three sides. */
 } esp_params;
 
 typedef struct esp_plan esp_plan;
 
 /* ---- host-only queries (no device use; safe on machines without a GPU) ---- */
 
-/* Resolve parameters for a cubic box of side box[0] (box[1], box[2] must equal
- * it), N particles and tolerance tol in [1e-8, 1e-2]. req may be NULL. */
+/* Resolve parameters for a box of sides box[0..2] (cubic or orthorhombic), N
+ * particles and tolerance tol in [1e-8, 1e-2]. req may be NULL. */
 esp_status esp_plan_query(const double box[3], int64_t N, double tol,
                           const esp_params* req, esp_params* out);
 

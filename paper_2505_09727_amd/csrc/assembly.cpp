@@ -8,10 +8,6 @@
 
 namespace esp {
 
-namespace {
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
 std::vector<unsigned char> to_prec(const std::vector<double>& v, int prec) {
     std::vector<unsigned char> out(v.size() * (prec == 64 ? 8 : 4));
     if (prec == 64) {
@@ -22,6 +18,10 @@ std::vector<unsigned char> to_prec(const std::vector<double>& v, int prec) {
     }
     return out;
 }
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int nbins(const esp_params& p) {
     const int t1 = p.nf / p.tile;
@@ -118,7 +118,8 @@ size_t tiles_region(size_t tile_bytes, int64_t N, size_t rb) {
 static_assert(kLocalCoefStride == kLocalMaxDegree + 1, "device table stride of the local polynomials");
 
 void local_cells(const esp_params& p, int& lcs, int& R) {
-    const double rho = grid_rho(p);
+    // in grid units along the finest axis (the largest rc/h_d)
+    const double rho = grid_rho(p) * p.L / std::min(p.L, std::min(p.Ly, p.Lz));
     lcs = std::max(1, std::min(8, (int)std::floor(2.0 * p.tile / rho)));
     R = std::max(1, (int)std::ceil(rho * (1.0 + 1e-4) * lcs / p.tile));
 }
@@ -146,6 +147,7 @@ size_t scratch_bytes(const esp_params& p, int64_t N) {
     s += align256(n * n * (n + 2) * rb);         // grid
     if (p.force_method == 1) s += align256(3 * n * n * (n + 2) * rb);  // gradient grids
     s += tiles_region(nb * E * E * E * rb, N, rb);  // tiles / staging of the scatter
+    if (non_cubic(p)) s += align256((size_t)n * n * (n / 2 + 1) * rb);  // influence table
     if (p.local) {
         int lcs, R;
         local_cells(p, lcs, R);
@@ -182,6 +184,11 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
     }
     s.tiles = base + o;
     o += tiles_region(nb * E * E * E * rb, N, rb);
+    s.p3 = nullptr;
+    if (non_cubic(p)) {
+        s.p3 = base + o;
+        o += align256((size_t)n * n * (n / 2 + 1) * rb);
+    }
     s.cpos = s.loc = nullptr;
     s.cidx = s.cstart = nullptr;
     if (p.local) {
@@ -262,8 +269,13 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.E = tile_edge(r);
         d.degree = r.degree;
         d.inv_L = 1.0 / r.L;
+        d.inv_Ly = 1.0 / r.Ly;
+        d.inv_Lz = 1.0 / r.Lz;
+        d.lay = r.Ly / r.L;  // h_y / h_x
+        d.laz = r.Lz / r.L;
+        d.p3 = sl.scr.p3;
         d.pscale = r.nf / r.L;
-        d.s0 = ct.s0_ref * r.nf / r.L;
+        d.s0 = non_cubic(r) ? r.s0 : ct.s0_ref * r.nf / r.L;
         d.wmax3 = ct.wmax3;
         d.TS = sl.cls->TS;
         d.Tphi = sl.cls->Tphi;
@@ -349,7 +361,8 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     std::map<std::pair<int, int>, std::vector<int>> by_n;
     for (int s = 0; s < nsys; ++s) {
         const int n = hsys_[s].n;
-        const int fused = systems[s].prm.fft_passes == 1 && !hsys_[s].ik && fft_fused_lds(n, prec) <= kMaxLds;
+        const int fused = systems[s].prm.fft_passes == 1 && !hsys_[s].ik && !hsys_[s].p3 &&
+                          fft_fused_lds(n, prec) <= kMaxLds;
         by_n[{n, fused}].push_back(s);
     }
     const int C = fft_x_columns(prec);

@@ -32,7 +32,10 @@ struct SysDesc {
     int lsa;          // local: sub-cells per side of a local work item's block (divides lcs)
     int litem_off;    // local: first local work item of the system in the launch's list ...
     int nlitem;       // ... and their count (bins x (lcs / lsa)^3)
-    double inv_L;     // 1/L
+    double inv_L;     // 1/L (x side)
+    double inv_Ly;    // 1/Ly
+    double inv_Lz;    // 1/Lz
+    double lay, laz;  // local: h_y/h_x, h_z/h_x (1 for a cubic box)
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
     double wmax3;     // cube of the window's peak value (fixed-point range)
@@ -44,6 +47,8 @@ struct SysDesc {
     const void* poly; // window polynomials, P * (degree + 1)
     const void* tw;   // twiddles exp(2 pi i t/n), n complex
     const void* lcoef;  // local: polynomials A then B, each zero-padded to 17 coefficients
+    const void* p3;   // orthorhombic box: influence table p over the half spectrum,
+                      // (x, ky, kz) like the grid; null for a cubic box (factored tables)
     // particles in the caller's order (this system's slice) and outputs
     const void* pos;  // N x 3
     const void* q;    // N

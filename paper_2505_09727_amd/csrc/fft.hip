@@ -306,19 +306,18 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __
     for (int i = threadIdx.x; i < N; i += BD) tw[i] = tw_g[i];
     const long long off = (long long)wi.y * N * RL;
     R* plane = reinterpret_cast<R*>(S.grid) + off;
-    const R inv_L = R(S.inv_L);
     if (S.ik) {  // uniform over the block
         R* g = reinterpret_cast<R*>(S.grad);
         const long long G = (long long)N * N * RL;
-        inv_yz_plane<R, N, BD>(buf, tw, plane, g + G + off, 2, inv_L);
+        inv_yz_plane<R, N, BD>(buf, tw, plane, g + G + off, 2, R(S.inv_Ly));
         __syncthreads();
-        inv_yz_plane<R, N, BD>(buf, tw, plane, g + 2 * G + off, 3, inv_L);
+        inv_yz_plane<R, N, BD>(buf, tw, plane, g + 2 * G + off, 3, R(S.inv_Lz));
         __syncthreads();
-        inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, inv_L);
+        inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, R(0));
         __syncthreads();
-        inv_yz_plane<R, N, BD>(buf, tw, g + off, g + off, 0, inv_L);
+        inv_yz_plane<R, N, BD>(buf, tw, g + off, g + off, 0, R(0));
     } else {
-        inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, inv_L);
+        inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, R(0));
     }
 }
 
@@ -357,6 +356,7 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
     if (mode != 1) {
         const R* TS = reinterpret_cast<const R*>(S.TS);
         const R* Tp = reinterpret_cast<const R*>(S.Tphi);
+        const R* p3 = reinterpret_cast<const R*>(S.p3);  // non-cubic box: the whole table
         const R ps = R(S.pscale);
         for (int idx = threadIdx.x; idx < N * C; idx += BD) {
             const int x = idx / C, l = idx - x * C;
@@ -365,7 +365,8 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
             const int ky = col / HS, kz = col - ky * HS;
             const int mx = x <= HALF ? x : N - x;
             const int my = ky <= HALF ? ky : N - ky;
-            const R p = TS[mx * mx + my * my + kz * kz] * Tp[mx] * (Tp[my] * ps) * Tp[kz];
+            const R p = p3 ? p3[(long long)x * ROW + col]
+                           : TS[mx * mx + my * my + kz * kz] * Tp[mx] * (Tp[my] * ps) * Tp[kz];
             const cplx<R> b = buf[idx];
             const double wgt = (kz == 0 || kz == HALF) ? 1.0 : 2.0;
             e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);

@@ -85,14 +85,14 @@ __global__ void __launch_bounds__(kChunkThreads) k_hist(const SysDesc* __restric
     double sq = 0.0, sa = 0.0, s2 = 0.0, qm = 0.0;
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R* q = reinterpret_cast<const R*>(S.q);
-    const R inv_L = R(S.inv_L);
+    const R inv_L = R(S.inv_L), inv_Ly = R(S.inv_Ly), inv_Lz = R(S.inv_Lz);
 #pragma unroll
     for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
         const int il = wi.y + threadIdx.x + k * kChunkThreads;
         if (il < S.N) {
             const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
-            const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
-            const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
+            const R uy = grid_coord(pos[3 * il + 1], inv_Ly, n);
+            const R uz = grid_coord(pos[3 * il + 2], inv_Lz, n);
             S.rank[il] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
             const double qq = (double)q[il];
             sq += qq;
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
     const SysDesc& S = sys[wi.x];
     if (S.small) return;  // uniform over the block
     const R* pos = reinterpret_cast<const R*>(S.pos);
-    const R inv_L = R(S.inv_L);
+    const R inv_L = R(S.inv_L), inv_Ly = R(S.inv_Ly), inv_Lz = R(S.inv_Lz);
     const int n = S.n;
     const int* hcol = S.hist + (blockIdx.x - S.pitem_off);
 #pragma unroll
@@ -212,8 +212,8 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
         const int il = wi.y + threadIdx.x + k * kChunkThreads;
         if (il < S.N) {
             const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
-            const R uy = grid_coord(pos[3 * il + 1], inv_L, n);
-            const R uz = grid_coord(pos[3 * il + 2], inv_L, n);
+            const R uy = grid_coord(pos[3 * il + 1], inv_Ly, n);
+            const R uz = grid_coord(pos[3 * il + 2], inv_Lz, n);
             const int bin = bin_of(ux, uy, uz, S);
             const int dst = S.bin_start[bin] + hcol[bin * S.npitem] + S.rank[il];
             typename Vec4<R>::type v;
@@ -688,7 +688,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     load_tile<R>(lds, reinterpret_cast<const R*>(S.grid), n, E, ox, oy, oz);
     __syncthreads();
     const int deg = S.degree;
-    const R sc = R(S.n) * R(S.inv_L);
+    const R scx = R(S.n) * R(S.inv_L), scy = R(S.n) * R(S.inv_Ly), scz = R(S.n) * R(S.inv_Lz);
     const R s0 = R(S.s0);
     const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
     R* phi = reinterpret_cast<R*>(S.phi);
@@ -735,10 +735,9 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
         if (S.local) l = reinterpret_cast<const typename Vec4<R>::type*>(S.loc)[k];
         if (phi) phi[o] = u - v.w * s0 + l.x;
         if (F) {
-            const R f = -v.w * sc;
-            F[3LL * o + 0] = f * gxs + l.y;
-            F[3LL * o + 1] = f * gys + l.z;
-            F[3LL * o + 2] = f * gzs + l.w;
+            F[3LL * o + 0] = -v.w * scx * gxs + l.y;
+            F[3LL * o + 1] = -v.w * scy * gys + l.z;
+            F[3LL * o + 2] = -v.w * scz * gzs + l.w;
         }
     }
 }
@@ -821,12 +820,12 @@ __global__ void __launch_bounds__(kChunkThreads) k_drift(const SysDesc* __restri
 constexpr int kSmallBatch = 8;
 
 template <typename R>
-__device__ __forceinline__ void small_bin_class(const SysDesc& S, R x, R y, R z, R inv_L, R hp, int lo, R& ux,
-                                                R& uy, R& uz, int& b, int& c) {
+__device__ __forceinline__ void small_bin_class(const SysDesc& S, R x, R y, R z, R inv_L, R inv_Ly, R inv_Lz, R hp,
+                                                int lo, R& ux, R& uy, R& uz, int& b, int& c) {
     const int n = S.n, T = S.T, t1 = S.tiles1, E = S.E;
     ux = grid_coord(x, inv_L, n);
-    uy = grid_coord(y, inv_L, n);
-    uz = grid_coord(z, inv_L, n);
+    uy = grid_coord(y, inv_Ly, n);
+    uz = grid_coord(z, inv_Lz, n);
     int tx, ty, tz;
     b = bin_of(ux, uy, uz, S, tx, ty, tz);
     const int bx = (int)floor(ux - hp) + 1 - (tx * T + lo);
@@ -851,7 +850,7 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
     unsigned* rmask = reinterpret_cast<unsigned*>(rstart + kSmallRounds);
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R* q = reinterpret_cast<const R*>(S.q);
-    const R inv_L = R(S.inv_L), hp = R(0.5) * R(S.P);
+    const R inv_L = R(S.inv_L), inv_Ly = R(S.inv_Ly), inv_Lz = R(S.inv_Lz), hp = R(0.5) * R(S.P);
     const int lo = -((S.P - 1) / 2);
     for (int i = threadIdx.x; i < nb * 32; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
@@ -876,7 +875,7 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
             if (i < N) {
                 R ux, uy, uz;
                 int b, c;
-                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, hp, lo, ux, uy, uz, b, c);
+                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, inv_Ly, inv_Lz, hp, lo, ux, uy, uz, b, c);
                 S.rank[i] = atomicAdd(&cnt[b * 32 + c], 1);
                 const double qq = (double)pq[k];
                 sq += qq;
@@ -989,7 +988,7 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
             if (i < N) {
                 R ux, uy, uz;
                 int b, c;
-                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, hp, lo, ux, uy, uz, b, c);
+                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, inv_Ly, inv_Lz, hp, lo, ux, uy, uz, b, c);
                 int p = binoff[b];
                 if (deal) {
                     const int j = rbase[b] + pr[k];

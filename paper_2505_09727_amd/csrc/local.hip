@@ -107,8 +107,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_cellsort(const SysDesc* __res
     auto local_coords = [&](int p, R qv) {
         V o;
         o.x = bin_local<R>(pos[3LL * p + 0], S.inv_L, n, tx * T, T);
-        o.y = bin_local<R>(pos[3LL * p + 1], S.inv_L, n, ty * T, T);
-        o.z = bin_local<R>(pos[3LL * p + 2], S.inv_L, n, tz * T, T);
+        o.y = bin_local<R>(pos[3LL * p + 1], S.inv_Ly, n, ty * T, T);
+        o.z = bin_local<R>(pos[3LL * p + 2], S.inv_Lz, n, tz * T, T);
         o.w = qv;
         return o;
     };
@@ -276,7 +276,10 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
     bin_coords_l(t, S, tx, ty, tz);
     const R rho2 = R(S.lrho2), inv_rho2 = R(1.0 / S.lrho2);
     const R lsT = R(S.lsT);
-    const R sc = R(S.n * S.inv_L);  // 1/h
+    const R sc = R(S.n * S.inv_L);  // 1/h_x
+    // pair geometry in units of h_x: y and z grid offsets scale by h_y/h_x,
+    // h_z/h_x (1 in a cubic box)
+    const R ay = R(S.lay), az = R(S.laz);
     // separable sub-cell index: cell(gx, gy, gz) = X(gx) + Y(gy) + Z(gz) with
     // Z(g) = (g/s)(nc - s) + g, Y(g) = (g/s)(t1 nc - s^2) + s g,
     // X(g) = (g/s)(t1^2 nc - s^3) + s^2 g
@@ -347,8 +350,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
             for (int j = 0; j < nj; ++j) {
                 V v = cpos[j0 + j];
                 v.x += sx;
-                v.y += sy;
-                v.z += sz;
+                v.y = (v.y + sy) * ay;
+                v.z = (v.z + sz) * az;
                 dst[j] = v;
             }
         }
@@ -372,6 +375,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
         const int lz = sub_cell<R>(vi.z, 0, s, lsT);
         R up = 0, fx = 0, fy = 0, fz = 0;
         if (staged) {
+            const R viy = vi.y * ay, viz = vi.z * az;
             // halo rows hx .. hx + 2 lR around halo row hx + lR of the particle
             const int hx = min(max(lx - ox, 0), a - 1), hy = min(max(ly - oy, 0), a - 1),
                       hz = min(max(lz - oz, 0), a - 1);
@@ -381,8 +385,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                     const int ja = hs[row], jb = hs[row + 2 * LR + 1];
                     for (int j = ja; j < jb; ++j) {
                         const V vj = hp[j];
-                        pair_term<R, D>(vi.x - vj.x, vi.y - vj.y, vi.z - vj.z, vj.w, rho2, inv_rho2, cA, cB, up,
-                                        fx, fy, fz);
+                        pair_term<R, D>(vi.x - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
+                                        fy, fz);
                     }
                 }
             }
@@ -430,8 +434,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                         const int ja = cst[cell], jb = cst[cell + 1];
                         for (int j = ja; j < jb; ++j) {
                             const V vj = cpos[j];
-                            pair_term<R, D>(xs - vj.x, ys - vj.y, zs - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
-                                            fy, fz);
+                            pair_term<R, D>(xs - vj.x, (ys - vj.y) * ay, (zs - vj.z) * az, vj.w, rho2, inv_rho2, cA,
+                                            cB, up, fx, fy, fz);
                         }
                     }
                 }

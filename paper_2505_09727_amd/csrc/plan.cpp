@@ -325,7 +325,7 @@ static double sinc(double x) { return std::fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : 
 // n_f = 2 ceil(alpha L/(pi rc)) (eq. cemparameters), rounded up to a grid size
 // with FFT kernels; P = 5 (the default of common MD codes); rc the ESP cutoff
 // at the same tolerance unless given.
-static esp_status resolve_classical(double L, int64_t N, double tol, esp_params r, esp_params* out,
+static esp_status resolve_classical(double L, double Lmax, double Lmin, double tol, esp_params r, esp_params* out,
                                     std::string& msg) {
     if (r.c <= 0) r.c = std::log(1.0 / tol);
     if (r.P <= 0) r.P = 5;
@@ -333,11 +333,11 @@ static esp_status resolve_classical(double L, int64_t N, double tol, esp_params 
     if (r.h_max <= 0) r.h_max = 1.25;
     if (r.kappa <= 0) r.kappa = 1.2;
     if (r.rc <= 0) {
-        const int n_esp = grid_size(L, r.h_max);
-        r.rc = r.kappa * c_for_tolerance(tol) / kPi * (L / n_esp);
+        const int n_esp = grid_size(Lmax, r.h_max);
+        r.rc = r.kappa * c_for_tolerance(tol) / kPi * (Lmax / n_esp);
     }
     if (r.nf <= 0) {
-        int n = 2 * (int)std::ceil(r.c * L / (kPi * r.rc) - 1e-12);
+        int n = 2 * (int)std::ceil(r.c * Lmax / (kPi * r.rc) - 1e-12);
         while (n <= 144 && !is_smooth(n)) n += 2;
         r.nf = std::max(n, 8);
     }
@@ -347,21 +347,21 @@ static esp_status resolve_classical(double L, int64_t N, double tol, esp_params 
     }
     if (r.nf < r.P) { msg = "grid size must be at least P"; return ESP_E_UNSUPPORTED; }
     r.h = L / r.nf;
-    const double rho = std::round(r.rc / r.h * 1e9) / 1e9;
+    const double rho = std::round(r.rc / r.h * 1e12) / 1e12;
     if (r.precision == 0) r.precision = 32;
     if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
     if (r.tile != 0 && (r.tile < 8 || r.tile > 16)) { msg = "tile must lie in [8, 16]"; return ESP_E_UNSUPPORTED; }
     if (r.fft_passes != 0 && r.fft_passes != 1) { msg = "fft_passes must be 0 or 1"; return ESP_E_INVALID; }
     if (r.force_method != 0 && r.force_method != 1) { msg = "force_method must be 0 or 1"; return ESP_E_INVALID; }
     if (r.local != 0 && r.local != 1) { msg = "local must be 0 or 1"; return ESP_E_INVALID; }
-    if (r.local && rho > 0.5 * r.nf) {
+    if (r.local && r.rc > 0.5 * Lmin * (1 + 1e-12)) {
         msg = "the local part needs rc <= L/2 (nearest images only)";
         return ESP_E_UNSUPPORTED;
     }
+    (void)rho;
     r.c1 = 0.0;                       // the window is the B-spline: no shape parameter
     r.degree = std::max(4, r.P - 1);  // exact piecewise polynomial
     r.s0 = gauss_chi(r.c, 0.0) / (4.0 * kPi * r.rc);
-    (void)N;
     *out = r;
     return ESP_OK;
 }
@@ -376,13 +376,19 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     r.L = L;
     r.tol = tol;
     if (r.method != 0 && r.method != 1) { msg = "method must be 0 (ESP) or 1 (classical)"; return ESP_E_INVALID; }
-    if (r.method == 1) return resolve_classical(L, N, tol, r, out, msg);
+    if (r.Ly < 0 || r.Lz < 0) { msg = "box sides must be positive"; return ESP_E_INVALID; }
+    if (r.Ly == 0) r.Ly = L;
+    if (r.Lz == 0) r.Lz = L;
+    if (!(std::isfinite(r.Ly) && std::isfinite(r.Lz))) { msg = "box sides must be finite"; return ESP_E_INVALID; }
+    // the longest side sets the grid, the coarsest spacing the cutoff
+    const double Lmax = std::max(L, std::max(r.Ly, r.Lz)), Lmin = std::min(L, std::min(r.Ly, r.Lz));
+    if (r.method == 1) return resolve_classical(L, Lmax, Lmin, tol, r, out, msg);
     if (r.c <= 0) r.c = c_for_tolerance(tol);
     if (r.P <= 0) r.P = order_for_tol(tol);
     if (r.P < 4 || r.P > 12) { msg = "window width P must lie in [4, 12]"; return ESP_E_UNSUPPORTED; }
     if (r.h_max <= 0) r.h_max = 1.25;
     if (r.kappa <= 0) r.kappa = 1.2;
-    if (r.nf <= 0) r.nf = grid_size(L, r.h_max);
+    if (r.nf <= 0) r.nf = grid_size(Lmax, r.h_max);
     if (!is_smooth(r.nf) || r.nf < 8 || r.nf > 144) {
         msg = "grid size must be even, of the form 2^a 3^b, within [8, 144]";
         return ESP_E_UNSUPPORTED;
@@ -390,12 +396,13 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.nf < r.P) { msg = "grid size must be at least P"; return ESP_E_UNSUPPORTED; }
     r.h = L / r.nf;
     // rho = rc/h keys every L-independent cache; exact under the default rule
+    // (along the coarsest axis, which the window's aliasing is chosen for)
     double rho;
     if (r.rc <= 0) {
         rho = r.kappa * r.c / kPi;
-        r.rc = rho * r.h;
+        r.rc = rho * Lmax / r.nf;
     } else {
-        rho = std::round(r.rc / r.h * 1e9) / 1e9;
+        rho = std::round(r.rc / (Lmax / r.nf) * 1e12) / 1e12;
     }
     if (r.precision == 0) r.precision = 32;
     if (r.precision != 32 && r.precision != 64) { msg = "precision must be 32 or 64"; return ESP_E_INVALID; }
@@ -403,7 +410,7 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.fft_passes != 0 && r.fft_passes != 1) { msg = "fft_passes must be 0 or 1"; return ESP_E_INVALID; }
     if (r.force_method != 0 && r.force_method != 1) { msg = "force_method must be 0 or 1"; return ESP_E_INVALID; }
     if (r.local != 0 && r.local != 1) { msg = "local must be 0 or 1"; return ESP_E_INVALID; }
-    if (r.local && rho > 0.5 * r.nf) {
+    if (r.local && r.rc > 0.5 * Lmin * (1 + 1e-12)) {
         msg = "the local part needs rc <= L/2 (nearest images only)";
         return ESP_E_UNSUPPORTED;
     }
@@ -697,10 +704,35 @@ void local_polynomials(int method, double c, double rho, int& degree, std::vecto
 }
 
 double grid_rho(const esp_params& p) {
-    if (p.method == 1) return std::round(p.rc / p.h * 1e9) / 1e9;
+    if (p.method == 1) return std::round(p.rc / p.h * 1e12) / 1e12;
     double rho = p.kappa * p.c / kPi;  // the default rule's exact rc/h
-    if (std::fabs(rho * p.h - p.rc) > 1e-12 * p.rc) rho = std::round(p.rc / p.h * 1e9) / 1e9;
+    if (std::fabs(rho * p.h - p.rc) > 1e-12 * p.rc) rho = std::round(p.rc / p.h * 1e12) / 1e12;
     return rho;
+}
+
+void box_influence(const esp_params& p, const ClassTables& ct, std::vector<double>& out) {
+    // p_m = S^(|k|)/V Tphi[|m_x|] Tphi[|m_y|] Tphi[|m_z|], k_d = 2 pi m_d/L_d: the
+    // window's transform in grid units is the same on every axis (Tphi of the
+    // class, h = 1), so the spacings cancel against the h^6 of eq. pk
+    const int n = p.nf, hs = n / 2 + 1;
+    const double box[3] = {p.L, p.Ly, p.Lz}, V = box[0] * box[1] * box[2];
+    Prolate chi(p.method == 1 ? 1.0 : p.c);
+    const double I1 = p.method == 1 ? 1.0 : chi.integral(1.0);
+    out.assign((size_t)n * n * hs, 0.0);
+    for (int x = 0; x < n; ++x) {
+        const int mx = x <= n / 2 ? x : x - n;
+        for (int y = 0; y < n; ++y) {
+            const int my = y <= n / 2 ? y : y - n;
+            for (int z = 0; z < hs; ++z) {
+                if (mx == 0 && my == 0 && z == 0) continue;
+                const double kx = 2 * kPi * mx / box[0], ky = 2 * kPi * my / box[1], kz = 2 * kPi * z / box[2];
+                const double k2 = kx * kx + ky * ky + kz * kz, w = p.rc * std::sqrt(k2);
+                const double chat = p.method == 1 ? std::exp(-w * w / (4.0 * p.c)) : 0.5 * chi.ft(w) / I1;
+                out[((size_t)x * n + y) * hs + z] =
+                    chat / k2 / V * ct.Tphi[std::abs(mx)] * ct.Tphi[std::abs(my)] * ct.Tphi[z];
+            }
+        }
+    }
 }
 
 std::shared_ptr<const ClassTables> class_tables(const esp_params& p) {

@@ -81,5 +81,8 @@ struct ClassTables {
 // rc/h of resolved params as the table classes key it.
 double grid_rho(const esp_params& p);
 std::shared_ptr<const ClassTables> class_tables(const esp_params& p);
+// Influence table of a non-cubic box over the half spectrum, (x, ky, kz) in
+// the grid's order: n x n x (n/2 + 1) doubles.
+void box_influence(const esp_params& p, const ClassTables& ct, std::vector<double>& out);
 
 }  // namespace esp

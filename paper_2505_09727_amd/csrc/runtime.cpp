@@ -50,6 +50,7 @@ struct esp_plan {
     TableStore tables;
     LaunchSet ls;
     std::vector<SystemSlot> slots;
+    std::vector<std::vector<double>> p3host;  // orthorhombic systems' influence tables
     unsigned char* scratch = nullptr;
     double* d_out = nullptr;   // kOutDoubles per system, contiguous
     hipStream_t stream = nullptr;
@@ -79,6 +80,15 @@ struct esp_plan {
 };
 
 namespace {
+
+// A request with the box's y and z sides (0 where they equal the x side).
+esp_params with_box(const double box[3], const esp_params* req) {
+    esp_params r{};
+    if (req) r = *req;
+    r.Ly = box[1] == box[0] ? 0.0 : box[1];
+    r.Lz = box[2] == box[0] ? 0.0 : box[2];
+    return r;
+}
 
 // (Re)allocate the systems' scratch for their current tiles, carve it, and
 // build the launch set. Drops a captured graph and the bound caller buffers.
@@ -110,6 +120,12 @@ esp_status assemble(esp_plan* p) {
         if (st != ESP_OK) return fail(st, msg);
         sl.scr = carve_scratch(p->scratch + off[s], sl.prm, p->Ns[s]);
         sl.scr.out = p->d_out + (size_t)kOutDoubles * s;
+        if (sl.scr.p3) {
+            // orthorhombic: the system's own influence table (host FP64, once)
+            if (p->p3host[s].empty()) box_influence(sl.prm, *sl.cls->host, p->p3host[s]);
+            const std::vector<unsigned char> b = to_prec(p->p3host[s], sl.prm.precision);
+            HIP_TRY(hipMemcpy(sl.scr.p3, b.data(), b.size(), hipMemcpyHostToDevice));
+        }
     }
     std::string msg;
     esp_status st = p->ls.build(p->slots, p->prec, p->stream, msg);
@@ -156,6 +172,7 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
     HIP_TRY(hipStreamCreate(&p->stream));
     p->own_stream = true;
     p->slots.resize(nsys);
+    p->p3host.resize(nsys);
     esp_status st = assemble(p);
     if (st != ESP_OK) return st;
     *out = holder.release();
@@ -273,9 +290,9 @@ const char* esp_version(void) { return "esp-mi355x 0.1 (gfx950)"; }
 esp_status esp_plan_query(const double box[3], int64_t N, double tol, const esp_params* req, esp_params* out) {
     try {
         if (!box || !out) return fail(ESP_E_INVALID, "NULL argument");
-        if (box[0] != box[1] || box[0] != box[2]) return fail(ESP_E_UNSUPPORTED, "only cubic boxes are supported");
+        const esp_params rq = with_box(box, req);
         std::string msg;
-        esp_status s = resolve_params(box[0], N, tol, req, out, msg);
+        esp_status s = resolve_params(box[0], N, tol, &rq, out, msg);
         if (s != ESP_OK) return fail(s, msg);
         return ESP_OK;
     } catch (const std::exception& e) {
@@ -366,8 +383,8 @@ esp_status esp_warm_tables(const double* tols, int ntol, int nf_max, int threads
 esp_status esp_plan_create_ex(const double box[3], int64_t N, double tol, const esp_params* req, esp_plan** out) {
     try {
         if (!box) return fail(ESP_E_INVALID, "box is NULL");
-        if (box[0] != box[1] || box[0] != box[2]) return fail(ESP_E_UNSUPPORTED, "only cubic boxes are supported");
-        return build_plan(1, box, &N, &tol, req, false, out);
+        const esp_params rq = with_box(box, req);
+        return build_plan(1, box, &N, &tol, &rq, false, out);
     } catch (const std::exception& e) {
         return fail(ESP_E_INVALID, e.what());
     }

@@ -32,7 +32,7 @@ class esp_params(C.Structure):
                 ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
                 ("s0", C.c_double), ("force_method", C.c_int), ("local", C.c_int),
-                ("method", C.c_int)]
+                ("method", C.c_int), ("Ly", C.c_double), ("Lz", C.c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -207,12 +207,15 @@ class Plan:
     """A single-system or batched plan (esp_plan_create_ex / esp_batch_create)."""
 
     def __init__(self, L, N, tol, per_system=None, **req):
-        """Single system (scalar L, N) or batch (sequences). per_system: one
-        dict of requested parameters per system of a batch (overrides req)."""
+        """Single system (scalar L, or a box (Lx, Ly, Lz), and scalar N) or batch
+        (sequences of x sides and sizes; per-system Ly, Lz through per_system).
+        per_system: one dict of requested parameters per system of a batch
+        (overrides req)."""
         self._h = C.c_void_p()
-        if np.ndim(L) == 0:
-            _check(lib().esp_plan_create_ex(_box(float(L)), int(N), float(tol), C.byref(_req(**req)),
-                                            C.byref(self._h)))
+        if np.ndim(L) == 0 or (np.ndim(N) == 0 and len(L) == 3):
+            # one system: side L, or an orthorhombic box (Lx, Ly, Lz)
+            box = _box(float(L)) if np.ndim(L) == 0 else (C.c_double * 3)(*[float(x) for x in L])
+            _check(lib().esp_plan_create_ex(box, int(N), float(tol), C.byref(_req(**req)), C.byref(self._h)))
         else:
             Ls = np.ascontiguousarray(L, dtype=np.float64)
             Ns = np.ascontiguousarray(N, dtype=np.int64)

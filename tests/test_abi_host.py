@@ -141,6 +141,18 @@ def test_local_part_needs_half_box_cutoff():
     assert esp.esp_plan_query(22.56, 512, 1e-4, local=1).local == 1
 
 
+def test_orthorhombic_parameters():
+    # the longest side sets the grid, the coarsest spacing the cutoff
+    _lib_or_skip()
+    p = esp.esp_plan_query((18.0, 21.0, 24.0), 1000, 1e-4)
+    c = esp.esp_plan_query(24.0, 1000, 1e-4)
+    assert (p.L, p.Ly, p.Lz) == (18.0, 21.0, 24.0)
+    assert p.nf == c.nf and abs(p.rc - c.rc) < 1e-12 and p.c1 == c.c1 and p.P == c.P
+    assert abs(p.h - 18.0 / p.nf) < 1e-15
+    with pytest.raises(esp.EspError):
+        esp.esp_plan_query((24.0, 24.0, 8.0), 1000, 1e-4, local=1)  # rc > 8/2
+
+
 def test_table2_through_the_library():
     _lib_or_skip()
     for eps, c_tab, P_tab in [(1e-3, 9.5392, 5), (5e-4, 10.290, 5), (1e-4, 12.024, 6), (5e-5, 12.762, 7),
@@ -150,7 +162,7 @@ def test_table2_through_the_library():
 
 
 @pytest.mark.parametrize("kw,box,tol,status", [
-    ({}, (10.0, 10.0, 11.0), 1e-4, -2),        # non-cubic
+    ({}, (10.0, 10.0, -1.0), 1e-4, -1),        # negative side
     ({}, 10.0, 0.5, -1),                        # tolerance out of range
     ({"nf": 10}, 10.0, 1e-4, -2),               # 10 is not 2^a 3^b
     ({"nf": 192}, 10.0, 1e-4, -2),              # beyond the built FFT range

@@ -1,0 +1,133 @@
+"""Orthorhombic boxes (sides Lx, Ly, Lz on a cubic index grid): the device
+path against the reference five-step method in a box (oracle.box), with the
+local part against orthorhombic Ewald, the ik forces against the AD forces,
+the cubic special case bitwise, and a batch mixing cubic and non-cubic
+systems.
+
+Workloads: random positions with the water charges (O, H, H repeated) at
+0.03 atoms/Å^3 in 18 x 21 x 24 Å and 24 x 24 x 16 Å boxes, and the 4 x 4 x 2
+rock-salt supercell (22.56 x 22.56 x 11.28 Å)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.box import ewald_box, five_step_box, local_sum_box
+from oracle.metrics import rel_rms
+from oracle.split import PSWFSplit
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_09727_amd.esp import Plan  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def run(plan, pos, q):
+    dt = torch.float64 if plan.precision == 64 else torch.float32
+    tp = torch.tensor(np.ascontiguousarray(pos), dtype=dt, device=DEV)
+    tq = torch.tensor(np.ascontiguousarray(q), dtype=dt, device=DEV)
+    phi = torch.empty(len(q), dtype=dt, device=DEV)
+    F = torch.empty((len(q), 3), dtype=dt, device=DEV)
+    E = plan.longrange(tp, tq, phi, F)
+    torch.cuda.synchronize()
+    return phi.cpu().double().numpy(), F.cpu().double().numpy(), np.asarray(E)
+
+
+def random_box(box, seed, density=0.03):
+    rng = np.random.default_rng(seed)
+    N = 3 * int(density * np.prod(box) / 3)
+    return rng.uniform(0, 1, (N, 3)) * np.asarray(box), np.tile([W.Q_O, W.Q_H, W.Q_H], N // 3)
+
+
+def reference(pos, q, p, local):
+    box = (p.L, p.Ly, p.Lz)
+    r = five_step_box(pos, q, box, p.nf, p.P, p.c, p.rc, p.c1)
+    phi, F = r["phi"], r["F"]
+    if local:
+        ul, gl = local_sum_box(pos, q, box, PSWFSplit(p.c, p.rc))
+        phi, F = phi + ul, F - q[:, None] * gl
+    return phi, F, 0.5 * float(np.dot(q, phi))
+
+
+@pytest.mark.parametrize("box", [(18.0, 21.0, 24.0), (24.0, 24.0, 16.0)])
+@pytest.mark.parametrize("prec,bar_F,bar_E", [(64, 1e-9, 1e-10), (32, 1e-5, 1e-6)])
+@pytest.mark.parametrize("local", [0, 1])
+def test_box_against_reference(box, prec, bar_F, bar_E, local):
+    pos, q = random_box(box, seed=int(sum(box)))
+    plan = Plan(box, len(q), 1e-4, precision=prec, local=local, degree=16 if prec == 64 else None)
+    p = plan.params[0]
+    assert (p.L, p.Ly, p.Lz) == box and p.nf == 24
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    pr = pos if prec == 64 else pos.astype(np.float32).astype(np.float64)
+    phi_r, F_r, E_r = reference(pr, q, p, local)
+    eF, ephi, eE = rel_rms(F, F_r), rel_rms(phi, phi_r), abs(E[0] - E_r) / abs(E_r)
+    print(f"box {box} prec={prec} local={local}: relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
+    assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    if local:
+        _, F_e, E_e = ewald_box(pr, q, box)
+        print(f"box {box} prec={prec}: Delta={rel_rms(F, F_e):.2e}")
+        assert rel_rms(F, F_e) < 1e-4 and abs(E[0] - E_e) < 1e-4 * abs(E_e)
+
+
+def test_madelung_constant_in_a_non_cubic_supercell():
+    pos, q, L = W.nacl_crystal(cells=4)
+    keep = pos[:, 2] < L / 2 - 1e-9
+    pos, q = pos[keep], q[keep]
+    plan = Plan((L, L, L / 2), len(q), 1e-4, precision=64, degree=16, local=1)
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    r0 = 5.64 / 2
+    M = -phi * q * 4 * math.pi * r0
+    assert np.max(np.abs(M - 1.747565)) < 1e-4 * 1.747565
+    # the forces vanish by symmetry; the grid (twice as fine along z as along
+    # x and y) breaks the symmetry at the tolerance level
+    f_nn = 1 / (4 * math.pi * r0 ** 2)
+    assert np.max(np.abs(F)) < 2e-4 * f_nn
+
+
+def test_ik_forces_in_a_box_agree_with_ad():
+    box = (18.0, 21.0, 24.0)
+    pos, q = random_box(box, seed=5)
+    out = []
+    for fm in (0, 1):
+        plan = Plan(box, len(q), 1e-4, precision=64, force_method=fm)
+        out.append(run(plan, pos, q))
+        plan.close()
+    (phi0, F0, E0), (phi1, F1, E1) = out
+    assert rel_rms(F1, F0) < 1e-3 and rel_rms(phi1, phi0) < 1e-12
+    # ik conserves momentum exactly
+    assert np.abs(F1.sum(0)).max() < 1e-10 * np.abs(F1).max() * len(q)
+
+
+def test_cubic_box_tuple_equals_scalar_side_bitwise():
+    pos, q = W.water_box(500, 18.0, seed=3)
+    a = Plan(18.0, len(q), 1e-4, local=1)
+    b = Plan((18.0, 18.0, 18.0), len(q), 1e-4, local=1)
+    ra, rb = run(a, pos, q), run(b, pos, q)
+    a.close()
+    b.close()
+    assert all(np.array_equal(x, y) for x, y in zip(ra, rb))
+
+
+def test_batch_of_cubic_and_orthorhombic_systems():
+    boxes = [(20.0, 20.0, 20.0), (18.0, 21.0, 24.0), (24.0, 24.0, 16.0), (16.0, 16.0, 16.0)]
+    systems = [random_box(b, seed=40 + i) for i, b in enumerate(boxes)]
+    Ns = [len(s[1]) for s in systems]
+    off = np.cumsum([0] + Ns)
+    per = [{"Ly": b[1], "Lz": b[2], "local": 1} for b in boxes]
+    batch = Plan([b[0] for b in boxes], Ns, 1e-4, per_system=per)
+    phi_b, F_b, E_b = run(batch, np.concatenate([s[0] for s in systems]), np.concatenate([s[1] for s in systems]))
+    batch.close()
+    for i, b in enumerate(boxes):
+        single = Plan(b, Ns[i], 1e-4, local=1)
+        phi_s, F_s, E_s = run(single, systems[i][0], systems[i][1])
+        single.close()
+        sl = slice(off[i], off[i + 1])
+        assert np.array_equal(F_s, F_b[sl]) and np.array_equal(phi_s, phi_b[sl]) and E_s[0] == E_b[i], i
