@@ -350,6 +350,44 @@ def classical_run(pos, q, L, B, N, steps, box0, ewald0, ms_esp, ms_esp_full, del
     return out
 
 
+def box_run(steps, B=128, n_mol=3000, tol=1e-4):
+    """Orthorhombic boxes: a batch of water-like boxes of the 9000-atom
+    workload's volume and density with the membrane system's aspect ratio
+    (10.79 : 10.18 : 9.55, Methods, experimental design), timed beside the
+    cubic batch; box 0 with the local part against orthorhombic Ewald."""
+    import torch
+    import workloads as W
+    from oracle.box import ewald_box
+    from oracle.metrics import rel_rms
+    from paper_2505_09727_amd.esp import Plan
+    dev = torch.device("cuda:0")
+    ratios = np.array([10.79, 10.18, 9.55])
+    box = ratios * (31.0 ** 3 / np.prod(ratios)) ** (1.0 / 3.0)
+    boxes = [W.water_box(n_mol, box, seed=2000 + b) for b in range(B)]
+    N = 3 * n_mol
+    pos = torch.tensor(np.concatenate([b[0] for b in boxes]), dtype=torch.float32, device=dev)
+    q = torch.tensor(np.concatenate([b[1] for b in boxes]), dtype=torch.float32, device=dev)
+    plan = Plan([box[0]] * B, [N] * B, tol, per_system=[{"Ly": box[1], "Lz": box[2]}] * B)
+    p = plan.params[0]
+    phi = torch.empty(B * N, dtype=torch.float32, device=dev)
+    F = torch.empty((B * N, 3), dtype=torch.float32, device=dev)
+    ext = torch.cuda.ExternalStream(plan.stream)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange_async(pos, q, phi, F)
+    ms = _time_plan(plan, ext, pos, q, phi, F, steps)
+    plan.close()
+    one = Plan(tuple(box), N, tol, local=1)
+    F0 = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    one.longrange(pos[:N].contiguous(), q[:N].contiguous(), phi[:N].contiguous(), F0)
+    one.close()
+    _, F_e, _ = ewald_box(boxes[0][0].astype(np.float32).astype(np.float64), boxes[0][1], box)
+    return {"box": [float(x) for x in box], "grid": p.nf, "P": p.P, "rc": p.rc,
+            "particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms,
+            "delta_F_vs_ewald_full_coulomb": rel_rms(F0.cpu().double().numpy(), F_e),
+            "workload": f"batch of {B} orthorhombic water-like boxes, {N} atoms each, FP32, tol {tol}"}
+
+
 def ensemble_run(steps, seed=4):
     """256 water-like boxes at 1 g/cm^3 with log-uniform sizes in one FP32 plan
     (autotuned bin edges, graph replay) against the FP64 plain path run one
@@ -480,6 +518,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 300,000-atom section")
     ap.add_argument("--no-local", action="store_true", help="skip the full-Coulomb (local part) section")
     ap.add_argument("--no-classical", action="store_true", help="skip the classical-method (PME) comparison")
+    ap.add_argument("--no-box", action="store_true", help="skip the orthorhombic-box section")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -598,6 +637,7 @@ def main():
         classical = classical_run(pos, q, L, B, N, max(10, args.steps // 4), boxes[0], ewald0, ms_per_step,
                                   full["ms_per_step"] if full else None,
                                   full["delta_F_vs_ewald"] if full else None)
+    ortho = None if args.no_box else box_run(max(10, args.steps // 4))
     ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
     large = None if args.no_large else large_run(max(10, args.steps // 10))
 
@@ -632,6 +672,7 @@ def main():
         "ik_forces": ik,
         "full_coulomb": full,
         "classical_method": classical,
+        "orthorhombic": ortho,
         "ensemble": ensemble,
         "large_system": large,
     }

@@ -85,9 +85,10 @@ def _random_rotations(rng: np.random.Generator, m: int) -> np.ndarray:
     return R
 
 
-def water_box(n_mol: int, L: float, seed: int):
+def water_box(n_mol: int, L, seed: int):
     """n_mol rigid three-site waters with uniform O positions in [0,L)^3 and
-    uniform random orientations. Atom order per molecule: O, H, H.
+    uniform random orientations. Atom order per molecule: O, H, H. L may also
+    be the three sides of an orthorhombic box.
     Returns (pos[3*n_mol,3], q[3*n_mol])."""
     rng = _rng(seed)
     o = rng.random((n_mol, 3)) * L
