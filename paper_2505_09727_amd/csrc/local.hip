@@ -383,7 +383,21 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                 for (int v = 0; v <= 2 * LR; ++v) {
                     const int row = ((hx + u) * W + (hy + v)) * W + hz;
                     const int ja = hs[row], jb = hs[row + 2 * LR + 1];
-                    for (int j = ja; j < jb; ++j) {
+                    // four candidates loaded before any is used: the LDS
+                    // latency overlaps instead of stalling every pair
+                    int j = ja;
+                    for (; j + 3 < jb; j += 4) {
+                        const V v0 = hp[j], v1 = hp[j + 1], v2 = hp[j + 2], v3 = hp[j + 3];
+                        pair_term<R, D>(vi.x - v0.x, viy - v0.y, viz - v0.z, v0.w, rho2, inv_rho2, cA, cB, up, fx,
+                                        fy, fz);
+                        pair_term<R, D>(vi.x - v1.x, viy - v1.y, viz - v1.z, v1.w, rho2, inv_rho2, cA, cB, up, fx,
+                                        fy, fz);
+                        pair_term<R, D>(vi.x - v2.x, viy - v2.y, viz - v2.z, v2.w, rho2, inv_rho2, cA, cB, up, fx,
+                                        fy, fz);
+                        pair_term<R, D>(vi.x - v3.x, viy - v3.y, viz - v3.z, v3.w, rho2, inv_rho2, cA, cB, up, fx,
+                                        fy, fz);
+                    }
+                    for (; j < jb; ++j) {
                         const V vj = hp[j];
                         pair_term<R, D>(vi.x - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
                                         fy, fz);
