@@ -223,3 +223,50 @@ def test_translation_invariance_of_the_local_part():
     phi2, F2, E2 = run(plan, pos + h * np.array([3, -5, 11]), q)
     plan.close()
     assert rel_rms(F2, F) < 1e-11 and abs(E2[0] - E[0]) < 1e-12 * abs(E[0])
+
+
+def test_graph_replay_with_the_local_part():
+    # a batch with the local part captured as one HIP graph: every replay,
+    # with eager work and synchronisations between replays, equals the eager
+    # result bitwise
+    systems = [W.water_box_at_density(3 * (900 + 200 * i), seed=500 + i) for i in range(4)]
+    Ls = [s[2] for s in systems]
+    Ns = [len(s[1]) for s in systems]
+    pos = torch.tensor(np.concatenate([s[0] for s in systems]), dtype=torch.float32, device=DEV)
+    q = torch.tensor(np.concatenate([s[1] for s in systems]), dtype=torch.float32, device=DEV)
+    plan = Plan(Ls, Ns, 1e-4, local=1)
+    phi = torch.empty(sum(Ns), dtype=torch.float32, device=DEV)
+    F = torch.empty((sum(Ns), 3), dtype=torch.float32, device=DEV)
+    E0 = np.asarray(plan.longrange(pos, q, phi, F))
+    F0, phi0 = F.clone(), phi.clone()
+    plan.set_graph(True)
+    for rep in range(4):
+        F.zero_()
+        phi.zero_()
+        torch.cuda.synchronize()
+        E = np.asarray(plan.longrange(pos, q, phi, F))
+        torch.cuda.synchronize()
+        assert torch.equal(F, F0) and torch.equal(phi, phi0) and np.array_equal(E, E0), rep
+    plan.close()
+
+
+def test_autotune_keeps_the_local_part():
+    # the autotuner rebuilds the plan (new bin edges, new local-part scratch):
+    # results before and after agree with each other and with the reference
+    pos, q = W.water_box(1500, 24.0, seed=8)
+    plan = Plan(24.0, len(q), 1e-4, local=1)
+    tp = torch.tensor(pos, dtype=torch.float32, device=DEV)
+    tq = torch.tensor(q, dtype=torch.float32, device=DEV)
+    phi = torch.empty(len(q), dtype=torch.float32, device=DEV)
+    F = torch.empty((len(q), 3), dtype=torch.float32, device=DEV)
+    E0 = plan.longrange(tp, tq, phi, F)[0]
+    F0 = F.cpu().double().numpy()
+    tiles = plan.autotune(tp, tq, phi, F, reps=2)
+    E1 = plan.longrange(tp, tq, phi, F)[0]
+    F1 = F.cpu().double().numpy()
+    p = plan.params[0]
+    plan.close()
+    assert p.tile == tiles[0] and p.local == 1
+    assert rel_rms(F1, F0) < 1e-5 and abs(E1 - E0) < 1e-6 * abs(E0)
+    _, F_r, E_r = full_reference(pos.astype(np.float32).astype(np.float64), q, p)
+    assert rel_rms(F1, F_r) < 1e-5 and abs(E1 - E_r) < 1e-6 * abs(E_r)
