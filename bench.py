@@ -120,21 +120,56 @@ def roofline(phase, ms, B, N, n, P, deg):
     return r
 
 
-def cpu_baseline(pos, q, L, prm, budget_s=12.0):
+def _one_thread():
     from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def _oracle_box(args):
+    """One evaluation of the reference five-step on one box (a pool job)."""
     from oracle.fivestep import five_step
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            five_step(pos, q, L, prm.nf, prm.P, prm.c, prm.rc, prm.c1)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= budget_s or reps >= 50:
+    pos, q, L, nf, P, c, rc, c1 = args
+    five_step(pos, q, L, nf, P, c, rc, c1)
+    return len(q)
+
+
+def _host():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
                 break
-    return dict(value=reps * len(q) / el, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"{reps} evaluations of one 9000-atom box by the FP64 reference five-step "
-                       f"(exact window, matrix DFT), numpy with 1 thread, {el:.1f} s")
+    except OSError:
+        pass
+    return {"cpus_available": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(boxes, L, prm, budget_s=12.0, max_workers=16):
+    """The reference five-step (FP64, exact window, matrix DFT) on the host's
+    cores: independent boxes of the batch, one per worker process (one thread
+    each), in rounds until about budget_s seconds have passed."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    host = _host()
+    workers = max(1, min(max_workers, host["cpus_available"]))
+    jobs = [(b[0], b[1], L, prm.nf, prm.P, prm.c, prm.rc, prm.c1) for b in boxes]
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"), initializer=_one_thread) as ex:
+        list(ex.map(_oracle_box, jobs[:workers]))  # imports and first-touch outside the timed window
+        t0 = time.perf_counter()
+        done, k = 0, 0
+        while True:
+            batch = [jobs[(k + i) % len(jobs)] for i in range(workers)]
+            k += workers
+            done += sum(ex.map(_oracle_box, batch))
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    return dict(value=done / el, unit="particle-steps/s", cores=workers, kind="oracle",
+                sample=f"{done // len(boxes[0][1])} evaluations of 9000-atom boxes of the batch by the FP64 "
+                       f"reference five-step (exact window, matrix DFT), {workers} worker processes of one "
+                       f"thread each, {el:.1f} s",
+                host=host)
 
 
 def serving_run(seconds, rate, budget_gb, seed=5):
@@ -622,7 +657,7 @@ def main():
                 rel_rms_F_vs_fp32=rel_rms(F0, F64.cpu().numpy()))
     p64.close()
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(boxes[0][0], boxes[0][1], L, prm)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(boxes, L, prm)
     serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_budget_gb) if args.serve_seconds > 0 else None
     ik = None if args.no_ik else ik_run(pos, q, L, B, N, max(10, args.steps // 4), F_all, boxes[0])
     ewald0 = None
