@@ -385,6 +385,46 @@ def classical_run(pos, q, L, B, N, steps, box0, ewald0, ms_esp, ms_esp_full, del
     return out
 
 
+def nacl_run(steps=200):
+    """The 512-ion rock-salt crystal (a = 5.64 A, 4 x 4 x 4 cells, perturbed by
+    U(-0.1, 0.1) A, n = 16, P = 6, tol 1e-4): launch-latency bound, so
+    microseconds per step in FP64 and FP32 (autotuned, graph replay), and the exact
+    lattice's Madelung constant from the FP64 potentials with the local part."""
+    import torch
+    import workloads as W
+    from paper_2505_09727_amd.esp import Plan
+    dev = torch.device("cuda:0")
+    cfg = W.NACL
+    out = {"workload": "512-ion rock-salt crystal, L = 22.56, n = 16, P = 6, tol 1e-4"}
+    pos, q, L = W.nacl_crystal(cells=cfg["cells"], a=cfg["a"], perturb=0.1, seed=1)
+    for prec, dt in ((64, torch.float64), (32, torch.float32)):
+        plan = Plan(L, len(q), cfg["tol"], nf=cfg["n"], P=cfg["P"], precision=prec)
+        tp = torch.tensor(pos, dtype=dt, device=dev)
+        tq = torch.tensor(q, dtype=dt, device=dev)
+        ph = torch.empty(len(q), dtype=dt, device=dev)
+        F = torch.empty((len(q), 3), dtype=dt, device=dev)
+        ext = torch.cuda.ExternalStream(plan.stream)
+        plan.autotune(tp, tq, ph, F, reps=5)
+        plan.set_graph(True)
+        for _ in range(5):
+            plan.longrange_async(tp, tq, ph, F)
+        out[f"fp{prec}_us_per_step"] = 1e3 * _time_plan(plan, ext, tp, tq, ph, F, steps)
+        out[f"fp{prec}_fft_passes"] = plan.params[0].fft_passes
+        plan.close()
+    pos0, q0, _ = W.nacl_crystal(cells=cfg["cells"], a=cfg["a"])
+    plan = Plan(L, len(q0), cfg["tol"], nf=cfg["n"], P=cfg["P"], precision=64, local=1)
+    tp = torch.tensor(pos0, dtype=torch.float64, device=dev)
+    tq = torch.tensor(q0, dtype=torch.float64, device=dev)
+    ph = torch.empty(len(q0), dtype=torch.float64, device=dev)
+    F = torch.empty((len(q0), 3), dtype=torch.float64, device=dev)
+    E = plan.longrange(tp, tq, ph, F)[0]
+    plan.close()
+    r0 = cfg["a"] / 2
+    out["madelung_from_energy"] = -E * 4 * math.pi * r0 / (len(q0) / 2)
+    out["madelung_reference"] = 1.747565
+    return out
+
+
 def box_run(steps, B=128, n_mol=3000, tol=1e-4):
     """Orthorhombic boxes: a batch of water-like boxes of the 9000-atom
     workload's volume and density with the membrane system's aspect ratio
@@ -554,6 +594,7 @@ def main():
     ap.add_argument("--no-local", action="store_true", help="skip the full-Coulomb (local part) section")
     ap.add_argument("--no-classical", action="store_true", help="skip the classical-method (PME) comparison")
     ap.add_argument("--no-box", action="store_true", help="skip the orthorhombic-box section")
+    ap.add_argument("--no-nacl", action="store_true", help="skip the 512-ion crystal section")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -673,6 +714,7 @@ def main():
                                   full["ms_per_step"] if full else None,
                                   full["delta_F_vs_ewald"] if full else None)
     ortho = None if args.no_box else box_run(max(10, args.steps // 4))
+    nacl = None if args.no_nacl else nacl_run()
     ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
     large = None if args.no_large else large_run(max(10, args.steps // 10))
 
@@ -708,6 +750,7 @@ def main():
         "full_coulomb": full,
         "classical_method": classical,
         "orthorhombic": ortho,
+        "nacl_512": nacl,
         "ensemble": ensemble,
         "large_system": large,
     }

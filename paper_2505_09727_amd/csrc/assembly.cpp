@@ -340,13 +340,15 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             return ESP_E_UNSUPPORTED;
         }
     }
-    // one block per system bins a system faster than the chunked kernels only
-    // when enough systems share the launch to fill the GPU (the particle order
-    // within a bin, which is all the path changes, affects no result)
+    // one block per system bins a system faster than the chunked kernels when
+    // enough systems share the launch to fill the GPU, or when the system is
+    // small enough that one launch beats the chunked path's five (the
+    // particle order within a bin, which is all the path changes, affects no
+    // result)
     for (int s = 0; s < nsys; ++s) {
         SysDesc& d = hsys_[s];
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
-        if (n_eligible < kSmallMinSystems) d.small = 0;
+        if (n_eligible < kSmallMinSystems && d.N > kSmallAlwaysN) d.small = 0;
         if (d.small) {
             bsys_.push_back(make_int2(s, 0));
             nb_small_max = std::max(nb_small_max, nb);

@@ -90,7 +90,8 @@ struct SysDesc {
 constexpr int kSmallMaxN = ESP_SMALL_MAX_N;  // systems up to this size ...
 constexpr int kSmallMaxBins = 512;    // ... and bin count are binned by one block
 constexpr int kSmallRounds = 8192;    // deal rounds a one-block binning can hold
-constexpr int kSmallMinSystems = 64;  // one-block binning pays only with this many systems
+constexpr int kSmallMinSystems = 64;  // one-block binning pays only with this many systems,
+constexpr int kSmallAlwaysN = 4096;   // or for systems this small (one launch instead of five)
 constexpr int kParticleChunk = 1024;  // particles per chunk work item
 constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
 constexpr int kOutDoubles = 8;
