@@ -3,8 +3,9 @@
  * prolate spheroidal wave functions (ESP), on one AMD Instinct MI355X (gfx950).
  *
  * Problem (Methods, "A general Ewald split", eq. task): N point charges q_i at
- * r_i in a cubic periodic box of side L, sum q_i = 0, kernel 1/(4 pi r)
- * (nondimensionalised; multiply by the Coulomb constant of your unit system).
+ * r_i in a periodic box (cubic of side L, or orthorhombic with sides L, Ly,
+ * Lz), sum q_i = 0, kernel 1/(4 pi r) (nondimensionalised; multiply by the
+ * Coulomb constant of your unit system).
  * The library evaluates the spectral (smooth, long-range) part of the split
  * 1/(4 pi r) = S(r) + L(r) (eq. kernelsplitting) with the PSWF splitting kernel
  * (eq. pswf), using the five-step method (eqs. spread, FFT, diagonal scaling,
@@ -14,8 +15,11 @@
  *     F_i   = -q_i grad u~^s(r_i)                (AD forces),
  *     E     = (1/2) sum_i q_i phi_i              (computed in k-space, FP64).
  * Adding the local part u^l_i (eq. localpart, kernel L(r) for r < rc, zero
- * beyond; see esp_local_kernel) gives the full Coulomb potential of eq. task.
- * The m = 0 Fourier mode is dropped (tin-foil boundary).
+ * beyond; see esp_local_kernel) gives the full Coulomb potential of eq. task;
+ * with esp_params.local = 1 the library adds it on the device, and
+ * esp_params.method = 1 selects the classical method (Gaussian split,
+ * B-spline window) on the same kernels. The m = 0 Fourier mode is dropped
+ * (tin-foil boundary).
  *
  * Conventions shared by every entry point
  *   - Status codes: every call returns ESP_OK or a negative esp_status and
@@ -48,7 +52,7 @@ extern "C" {
 typedef enum {
     ESP_OK = 0,
     ESP_E_INVALID = -1,      /* bad argument (NULL, N < 1, box <= 0, tol out of range) */
-    ESP_E_UNSUPPORTED = -2,  /* non-cubic box, grid or window outside the built range */
+    ESP_E_UNSUPPORTED = -2,  /* grid, window or cutoff outside the built range */
     ESP_E_NOT_NEUTRAL = -3,  /* |sum q| > 1e-6 sum |q|: results computed but meaningless */
     ESP_E_NOMEM = -4,        /* device allocation failed */
     ESP_E_DEVICE = -5,       /* HIP runtime error (message in esp_last_error) */
@@ -167,7 +171,8 @@ esp_status esp_plan_create(const double box[3], int64_t N, double tol, esp_plan*
 esp_status esp_plan_create_ex(const double box[3], int64_t N, double tol,
                               const esp_params* req, esp_plan** out);
 
-/* Batched plan: nsys independent cubic systems of sides L[s], N[s] particles and
+/* Batched plan: nsys independent systems of sides L[s] (with reqs[s].Ly, Lz for
+ * orthorhombic ones), N[s] particles and
  * tolerances tol[s]; req (may be NULL) applies to every system, or reqs[s]
  * (may be NULL) per system. One call evaluates all systems with one launch per
  * pipeline phase (systems grouped by window width P). */
