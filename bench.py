@@ -559,6 +559,19 @@ def large_run(steps, serve_steps=100):
         out[f"fp{prec}"] = {"particle_steps_per_s": N / (ms / 1e3), "ms_per_step": ms,
                             "grid": p.nf, "P": p.P, "tile": p.tile}
         plan.close()
+    # the same box with the local part (full Coulomb), FP32
+    plan = Plan(L, N, tol, local=1)
+    tp = torch.tensor(pos, dtype=torch.float32, device=dev)
+    tq = torch.tensor(q, dtype=torch.float32, device=dev)
+    ph = torch.empty(N, dtype=torch.float32, device=dev)
+    Fs = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    ext = torch.cuda.ExternalStream(plan.stream)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange_async(tp, tq, ph, Fs)
+    msl = _time_plan(plan, ext, tp, tq, ph, Fs, steps)
+    plan.close()
+    out["fp32_full_coulomb"] = {"particle_steps_per_s": N / (msl / 1e3), "ms_per_step": msl}
     out["speedup_fp32_vs_fp64_plain"] = res[64]["ms"] / res[32]["ms"]
     out["rel_rms_F_fp32_vs_fp64"] = rel_rms(res[32]["F"], res[64]["F"])
     out["rel_E_fp32_vs_fp64"] = abs(res[32]["E"] - res[64]["E"]) / abs(res[64]["E"])

@@ -270,3 +270,37 @@ def test_autotune_keeps_the_local_part():
     assert rel_rms(F1, F0) < 1e-5 and abs(E1 - E0) < 1e-6 * abs(E0)
     _, F_r, E_r = full_reference(pos.astype(np.float32).astype(np.float64), q, p)
     assert rel_rms(F1, F_r) < 1e-5 and abs(E1 - E_r) < 1e-6 * abs(E_r)
+
+
+def test_large_water_full_coulomb_sampled():
+    # the 300,000-atom box (L = 100, tol 1e-5, n = 96, P = 8) with the local
+    # part: forces and potentials at 2000 sampled particles against the
+    # reference five-step method plus the local sum at those particles
+    cfg = W.WATER_300K
+    pos, q = W.water_box(cfg["n_mol"], cfg["L"], cfg["seed"])
+    L, tol = cfg["L"], cfg["tol"]
+    plan = Plan(L, len(q), tol, local=1)
+    p = plan.params[0]
+    assert (p.nf, p.P) == (96, 8)
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    pr = pos.astype(np.float32).astype(np.float64)
+    r = five_step(pr, q, L, p.nf, p.P, p.c, p.rc, p.c1)
+    idx = np.random.default_rng(3).choice(len(q), 2000, replace=False)
+    ul, gl = local_sum(pr, q, L, PSWFSplit(p.c, p.rc), targets=idx)
+    F_r = r["F"][idx] - q[idx, None] * gl
+    phi_r = r["phi"][idx] + ul
+    eF, ephi = rel_rms(F[idx], F_r), rel_rms(phi[idx], phi_r)
+    # molecules placed at random at three times liquid density leave some
+    # atoms of different molecules a few hundredths of an angstrom apart; the
+    # FP32 coordinates' rounding (~5e-7 grid units) is then a large relative
+    # error of those pairs' huge forces, which dominate the RMS. Away from such
+    # contacts the FP32 local part meets the tolerance.
+    from scipy.spatial import cKDTree
+    d_nn = cKDTree(np.mod(pr, L), boxsize=L).query(np.mod(pr[idx], L), k=2)[0][:, 1]
+    far = d_nn >= 0.5
+    eF_far = rel_rms(F[idx][far], F_r[far])
+    print(f"300k full Coulomb, 2000 samples: relF={eF:.2e} relphi={ephi:.2e}; "
+          f"{far.sum()} without a contact < 0.5 A: relF={eF_far:.2e}; "
+          f"{(~far).sum()} with one: relF={rel_rms(F[idx][~far], F_r[~far]):.2e}")
+    assert eF_far < 1e-5 and ephi < 1e-5 and eF < 3e-5
