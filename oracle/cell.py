@@ -130,7 +130,13 @@ def local_sum_cell(pos, q, H, split, targets=None, chunk=128):
 
 
 def influence_cell(n, H, P, c, rc, c1):
-    """p_m on the full n^3 index grid (index k in [0, n): m = k or k - n)."""
+    """p_m on the full n^3 index grid (index k in [0, n): m = k or k - n).
+
+    Reading: in a tilted cell p depends on the signs of m, and an index at the
+    Nyquist frequency n/2 stands for both signs; p there is the mean over the
+    sign choices of its Nyquist components, which keeps p(-m) = p(m) on the
+    index grid (the inverse transform of p times a real grid's transform is
+    then real)."""
     H = np.asarray(H, np.float64)
     Hinv = np.linalg.inv(H)
     V = abs(np.linalg.det(H))
@@ -139,10 +145,16 @@ def influence_cell(n, H, P, c, rc, c1):
     m = np.where(kk < n // 2, kk, kk - n).astype(np.float64)
     f = phi_hat_1d(2 * math.pi * m / n, P, 1.0, c1)  # window transform in grid units
     M = np.array(np.meshgrid(m, m, m, indexing="ij"))  # 3 x n x n x n
-    k = 2 * math.pi * np.einsum("dj,d...->j...", Hinv, M)  # k_j = 2 pi sum_d Hinv[d, j] m_d
-    kn = np.sqrt(np.einsum("j...,j...->...", k, k))
-    kn[0, 0, 0] = 1.0
-    p = S_hat(split, kn) / V / (f[:, None, None] * f[None, :, None] * f[None, None, :]) ** 2
+    nyq = np.abs(M) == n // 2
+    acc = np.zeros((n, n, n))
+    for signs in np.ndindex(2, 2, 2):
+        Ms = np.where(nyq & (np.array(signs)[:, None, None, None] == 1), -M, M)
+        k = 2 * math.pi * np.einsum("dj,d...->j...", Hinv, Ms)  # k_j = 2 pi sum_d Hinv[d, j] m_d
+        kn = np.sqrt(np.einsum("j...,j...->...", k, k))
+        kn[0, 0, 0] = 1.0
+        acc += S_hat(split, kn)
+    S = acc / 8
+    p = S / V / (f[:, None, None] * f[None, :, None] * f[None, None, :]) ** 2
     p[0, 0, 0] = 0.0
     return p
 

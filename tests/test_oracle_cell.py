@@ -10,7 +10,7 @@ import pytest
 
 import workloads as W
 from oracle.box import ewald_box, five_step_box, local_sum_box
-from oracle.cell import cell_matrix, ewald_cell, five_step_cell, local_sum_cell, plane_spacings
+from oracle.cell import cell_matrix, ewald_cell, five_step_cell, influence_cell, local_sum_cell, plane_spacings
 from oracle.metrics import rel_rms
 from oracle.params import esp_parameters
 from oracle.split import PSWFSplit
@@ -86,3 +86,22 @@ def test_five_step_in_a_tilted_cell_reaches_the_tolerance(tilts, tol):
     _, F_e, E_e = ewald_cell(pos, q, H)
     assert rel_rms(F, F_e) < tol
     assert abs(0.5 * np.dot(q, r["phi"] + ul) - E_e) < tol * abs(E_e)
+
+
+def test_influence_is_even_on_the_index_grid():
+    # p(-m) = p(m), Nyquist indices included, so the convolution of a real grid is real
+    H = cell_matrix(16.0, 15.0, 14.0, 4.0, -3.0, 2.0)
+    n = 12
+    p = influence_cell(n, H, 6, 12.024, 4.0, 12.5)
+    neg = (-np.arange(n)) % n
+    assert np.max(np.abs(p - p[np.ix_(neg, neg, neg)])) < 1e-14 * np.max(p)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((n, n, n))
+    from oracle.fivestep import dft3
+    c = dft3(p * dft3(b, +1), -1)
+    assert np.max(np.abs(c.imag)) < 1e-13 * np.max(np.abs(c.real))
+    # a zero-tilt cell matches the orthorhombic table
+    from oracle.box import influence_box
+    pb = influence_box(n, (16.0, 15.0, 14.0), 6, 12.024, 4.0, 12.5)
+    pc = influence_cell(n, cell_matrix(16.0, 15.0, 14.0), 6, 12.024, 4.0, 12.5)
+    assert np.max(np.abs(pc - pb)) < 1e-10 * np.max(np.abs(pb))
