@@ -3,8 +3,8 @@
  * prolate spheroidal wave functions (ESP), on one AMD Instinct MI355X (gfx950).
  *
  * Problem (Methods, "A general Ewald split", eq. task): N point charges q_i at
- * r_i in a periodic box (cubic of side L, or orthorhombic with sides L, Ly,
- * Lz), sum q_i = 0, kernel 1/(4 pi r) (nondimensionalised; multiply by the
+ * r_i in a periodic box (cubic of side L, orthorhombic with sides L, Ly, Lz,
+ * or a triclinic cell with tilts xy, xz, yz), sum q_i = 0, kernel 1/(4 pi r) (nondimensionalised; multiply by the
  * Coulomb constant of your unit system).
  * The library evaluates the spectral (smooth, long-range) part of the split
  * 1/(4 pi r) = S(r) + L(r) (eq. kernelsplitting) with the PSWF splitting kernel
@@ -118,6 +118,16 @@ typedef struct {
                              side and rc the coarsest spacing; the influence function
                              becomes a per-system table. Set by esp_plan_create from
                              box[1], box[2]; outputs always hold the three sides. */
+    double xy, xz, yz;    /* tilts of a triclinic cell (0: orthorhombic or cubic): the
+                             lattice vectors are a = (L, 0, 0), b = (xy, Ly, 0) and
+                             c = (xz, yz, Lz), the columns of an upper-triangular H.
+                             The index grid nf^3 then runs over fractional coordinates
+                             s = H^-1 r (grid point l at H l / nf); nf and the default rc
+                             follow the longest lattice vector, and the local part needs
+                             rc at most half the smallest distance between lattice
+                             planes. Forces F = -q H^-T grad_s. Supported with method 0
+                             and force_method 0 (ESP_E_UNSUPPORTED otherwise). Positions
+                             may lie anywhere (each is wrapped into the cell). */
 } esp_params;
 
 typedef struct esp_plan esp_plan;

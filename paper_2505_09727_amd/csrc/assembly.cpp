@@ -118,8 +118,9 @@ size_t tiles_region(size_t tile_bytes, int64_t N, size_t rb) {
 static_assert(kLocalCoefStride == kLocalMaxDegree + 1, "device table stride of the local polynomials");
 
 void local_cells(const esp_params& p, int& lcs, int& R) {
-    // in grid units along the finest axis (the largest rc/h_d)
-    const double rho = grid_rho(p) * p.L / std::min(p.L, std::min(p.Ly, p.Lz));
+    // the largest reach of rc in grid units along any index axis: rc n / d_d
+    // for plane spacing d_d (rc/h_d along the finest axis of a box)
+    const double rho = grid_rho(p) * p.L / cell_of(p).dmin;
     lcs = std::max(1, std::min(8, (int)std::floor(2.0 * p.tile / rho)));
     R = std::max(1, (int)std::ceil(rho * (1.0 + 1e-4) * lcs / p.tile));
 }
@@ -273,6 +274,15 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.inv_Lz = 1.0 / r.Lz;
         d.lay = r.Ly / r.L;  // h_y / h_x
         d.laz = r.Lz / r.L;
+        {
+            const Cell c = cell_of(r);
+            d.ixy = c.ixy;
+            d.ixz = c.ixz;
+            d.iyz = c.iyz;
+            d.mxy = r.xy / r.L;
+            d.mxz = r.xz / r.L;
+            d.myz = r.yz / r.L;
+        }
         d.p3 = sl.scr.p3;
         d.pscale = r.nf / r.L;
         d.s0 = non_cubic(r) ? r.s0 : ct.s0_ref * r.nf / r.L;

@@ -66,7 +66,7 @@ struct SysScratch {
 // Host FP64 values converted to the plan precision (bytes).
 std::vector<unsigned char> to_prec(const std::vector<double>& v, int prec);
 // Whether resolved params describe a non-cubic box.
-inline bool non_cubic(const esp_params& p) { return p.Ly != p.L || p.Lz != p.L; }
+inline bool non_cubic(const esp_params& p) { return p.Ly != p.L || p.Lz != p.L || tilted(p); }
 // Local part: sub-cells per bin side and stencil radius for resolved params.
 void local_cells(const esp_params& p, int& lcs, int& R);
 // Local part: sub-cells per side of one work item's block (a divisor of lcs

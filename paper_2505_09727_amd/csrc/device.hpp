@@ -36,6 +36,11 @@ struct SysDesc {
     double inv_Ly;    // 1/Ly
     double inv_Lz;    // 1/Lz
     double lay, laz;  // local: h_y/h_x, h_z/h_x (1 for a cubic box)
+    // triclinic cell H = [a b c] = [[L, xy, xz], [0, Ly, yz], [0, 0, Lz]]: the
+    // off-diagonal entries of H^-1 (grid coordinates u = n H^-1 r) and of
+    // H / L (a grid-unit displacement in units of h_x = L/n); 0 otherwise
+    double ixy, ixz, iyz;
+    double mxy, mxz, myz;
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
     double wmax3;     // cube of the window's peak value (fixed-point range)

@@ -25,16 +25,30 @@ __device__ __forceinline__ int fdiv(int x, int m) {
     return (int)(((unsigned long long)(unsigned)x * (unsigned)m) >> 20);
 }
 
-// Grid coordinate u in [0, n) of one position component.
+// Grid coordinate u in [0, n) from a fractional coordinate t (any real).
 template <typename R>
-__device__ __forceinline__ R grid_coord(R x, R inv_L, int n) {
-    R t = x * inv_L;
+__device__ __forceinline__ R wrap_coord(R t, int n) {
     t = t - floor(t);
     R u = t * R(n);
     if (u >= R(n)) u -= R(n);
     if (u < R(0)) u = R(0);
     return u;
 }
+
+// Fractional coordinates s = H^-1 r of a cell H = [[L, xy, xz], [0, Ly, yz],
+// [0, 0, Lz]] (upper triangular, so is H^-1); the off-diagonal entries are 0
+// in an orthorhombic or cubic box.
+template <typename R>
+struct CellMap {
+    R ix, iy, iz, ixy, ixz, iyz;
+    __device__ explicit CellMap(const SysDesc& S)
+        : ix(R(S.inv_L)), iy(R(S.inv_Ly)), iz(R(S.inv_Lz)), ixy(R(S.ixy)), ixz(R(S.ixz)), iyz(R(S.iyz)) {}
+    __device__ __forceinline__ void grid(R x, R y, R z, int n, R& ux, R& uy, R& uz) const {
+        ux = wrap_coord(x * ix + (y * ixy + z * ixz), n);
+        uy = wrap_coord(y * iy + z * iyz, n);
+        uz = wrap_coord(z * iz, n);
+    }
+};
 
 // Bin of a particle: cells floor(u) grouped into T^3 blocks (T divides n).
 template <typename R>
@@ -85,14 +99,13 @@ __global__ void __launch_bounds__(kChunkThreads) k_hist(const SysDesc* __restric
     double sq = 0.0, sa = 0.0, s2 = 0.0, qm = 0.0;
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R* q = reinterpret_cast<const R*>(S.q);
-    const R inv_L = R(S.inv_L), inv_Ly = R(S.inv_Ly), inv_Lz = R(S.inv_Lz);
+    const CellMap<R> cm(S);
 #pragma unroll
     for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
         const int il = wi.y + threadIdx.x + k * kChunkThreads;
         if (il < S.N) {
-            const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
-            const R uy = grid_coord(pos[3 * il + 1], inv_Ly, n);
-            const R uz = grid_coord(pos[3 * il + 2], inv_Lz, n);
+            R ux, uy, uz;
+            cm.grid(pos[3 * il + 0], pos[3 * il + 1], pos[3 * il + 2], n, ux, uy, uz);
             S.rank[il] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
             const double qq = (double)q[il];
             sq += qq;
@@ -204,16 +217,15 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
     const SysDesc& S = sys[wi.x];
     if (S.small) return;  // uniform over the block
     const R* pos = reinterpret_cast<const R*>(S.pos);
-    const R inv_L = R(S.inv_L), inv_Ly = R(S.inv_Ly), inv_Lz = R(S.inv_Lz);
+    const CellMap<R> cm(S);
     const int n = S.n;
     const int* hcol = S.hist + (blockIdx.x - S.pitem_off);
 #pragma unroll
     for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
         const int il = wi.y + threadIdx.x + k * kChunkThreads;
         if (il < S.N) {
-            const R ux = grid_coord(pos[3 * il + 0], inv_L, n);
-            const R uy = grid_coord(pos[3 * il + 1], inv_Ly, n);
-            const R uz = grid_coord(pos[3 * il + 2], inv_Lz, n);
+            R ux, uy, uz;
+            cm.grid(pos[3 * il + 0], pos[3 * il + 1], pos[3 * il + 2], n, ux, uy, uz);
             const int bin = bin_of(ux, uy, uz, S);
             const int dst = S.bin_start[bin] + hcol[bin * S.npitem] + S.rank[il];
             typename Vec4<R>::type v;
@@ -689,6 +701,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     __syncthreads();
     const int deg = S.degree;
     const R scx = R(S.n) * R(S.inv_L), scy = R(S.n) * R(S.inv_Ly), scz = R(S.n) * R(S.inv_Lz);
+    // grad_r = n H^-T grad_u: the off-diagonal terms of a triclinic cell (0 otherwise)
+    const R sxy = R(S.n) * R(S.ixy), sxz = R(S.n) * R(S.ixz), syz = R(S.n) * R(S.iyz);
     const R s0 = R(S.s0);
     const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
     R* phi = reinterpret_cast<R*>(S.phi);
@@ -736,8 +750,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
         if (phi) phi[o] = u - v.w * s0 + l.x;
         if (F) {
             F[3LL * o + 0] = -v.w * scx * gxs + l.y;
-            F[3LL * o + 1] = -v.w * scy * gys + l.z;
-            F[3LL * o + 2] = -v.w * scz * gzs + l.w;
+            F[3LL * o + 1] = -v.w * scy * gys - v.w * (sxy * gxs) + l.z;
+            F[3LL * o + 2] = -v.w * scz * gzs - v.w * (sxz * gxs + syz * gys) + l.w;
         }
     }
 }
@@ -820,12 +834,10 @@ __global__ void __launch_bounds__(kChunkThreads) k_drift(const SysDesc* __restri
 constexpr int kSmallBatch = 8;
 
 template <typename R>
-__device__ __forceinline__ void small_bin_class(const SysDesc& S, R x, R y, R z, R inv_L, R inv_Ly, R inv_Lz, R hp,
+__device__ __forceinline__ void small_bin_class(const SysDesc& S, R x, R y, R z, const CellMap<R>& cm, R hp,
                                                 int lo, R& ux, R& uy, R& uz, int& b, int& c) {
     const int n = S.n, T = S.T, t1 = S.tiles1, E = S.E;
-    ux = grid_coord(x, inv_L, n);
-    uy = grid_coord(y, inv_Ly, n);
-    uz = grid_coord(z, inv_Lz, n);
+    cm.grid(x, y, z, n, ux, uy, uz);
     int tx, ty, tz;
     b = bin_of(ux, uy, uz, S, tx, ty, tz);
     const int bx = (int)floor(ux - hp) + 1 - (tx * T + lo);
@@ -850,7 +862,8 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
     unsigned* rmask = reinterpret_cast<unsigned*>(rstart + kSmallRounds);
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R* q = reinterpret_cast<const R*>(S.q);
-    const R inv_L = R(S.inv_L), inv_Ly = R(S.inv_Ly), inv_Lz = R(S.inv_Lz), hp = R(0.5) * R(S.P);
+    const CellMap<R> cm(S);
+    const R hp = R(0.5) * R(S.P);
     const int lo = -((S.P - 1) / 2);
     for (int i = threadIdx.x; i < nb * 32; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
@@ -875,7 +888,7 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
             if (i < N) {
                 R ux, uy, uz;
                 int b, c;
-                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, inv_Ly, inv_Lz, hp, lo, ux, uy, uz, b, c);
+                small_bin_class<R>(S, px[k], py[k], pz[k], cm, hp, lo, ux, uy, uz, b, c);
                 S.rank[i] = atomicAdd(&cnt[b * 32 + c], 1);
                 const double qq = (double)pq[k];
                 sq += qq;
@@ -988,7 +1001,7 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
             if (i < N) {
                 R ux, uy, uz;
                 int b, c;
-                small_bin_class<R>(S, px[k], py[k], pz[k], inv_L, inv_Ly, inv_Lz, hp, lo, ux, uy, uz, b, c);
+                small_bin_class<R>(S, px[k], py[k], pz[k], cm, hp, lo, ux, uy, uz, b, c);
                 int p = binoff[b];
                 if (deal) {
                     const int j = rbase[b] + pr[k];

@@ -13,7 +13,11 @@
 // binning path or the order its LDS atomics left inside a bin. k_local gives
 // every particle of a bin one thread, which walks the (2 lR + 1)^3 sub-cells
 // around its own; a periodic image is a shift by n grid units, and with
-// rc <= L/2 at most one image of a particle lies within rc.
+// rc <= L/2 at most one image of a particle lies within rc. In a triclinic
+// cell the bins and sub-cells are parallelepipeds of the fractional grid
+// u = n H^-1 r; a sub-cell's edge is then measured between its faces
+// (plane spacing), and displacements are mapped to Cartesian units by H/L
+// before the distance test.
 //
 // Kernel. Inside rc, L(r) = 1/(4 pi r) - s(r) with s(r) = G(r/rc)/(4 pi r)
 // smooth. In grid units s and s'(r)/r are polynomials A, B in x = r^2/rho^2
@@ -49,13 +53,12 @@ __device__ __forceinline__ int sub_cell(R u, int tb, int lcs, R lsT) {
     return min(max(c, 0), lcs - 1);
 }
 
-// Grid coordinate of position x relative to the origin o = tb T of its bin
-// row, in FP64 and taken at the image nearest the bin's centre: values lie in
-// [0, T) up to the rounding that placed the particle in this bin, so the
+// Grid coordinate of fractional coordinate t (FP64) relative to the origin
+// o = tb T of its bin row, taken at the image nearest the bin's centre: values
+// lie in [0, T) up to the rounding that placed the particle in this bin, so the
 // stored coordinate keeps ~T/n times the precision of u itself.
 template <typename R>
-__device__ __forceinline__ R bin_local(R x, double inv_L, int n, int o, int T) {
-    double t = (double)x * inv_L;
+__device__ __forceinline__ R bin_local(double t, int n, int o, int T) {
     t -= floor(t);
     double u = t * n - o;
     const double c = u - 0.5 * T;
@@ -105,10 +108,11 @@ __global__ void __launch_bounds__(kLocalThreads) k_cellsort(const SysDesc* __res
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const int n = S.n, T = S.T;
     auto local_coords = [&](int p, R qv) {
+        const double x = pos[3LL * p + 0], y = pos[3LL * p + 1], z = pos[3LL * p + 2];
         V o;
-        o.x = bin_local<R>(pos[3LL * p + 0], S.inv_L, n, tx * T, T);
-        o.y = bin_local<R>(pos[3LL * p + 1], S.inv_Ly, n, ty * T, T);
-        o.z = bin_local<R>(pos[3LL * p + 2], S.inv_Lz, n, tz * T, T);
+        o.x = bin_local<R>(x * S.inv_L + (y * S.ixy + z * S.ixz), n, tx * T, T);
+        o.y = bin_local<R>(y * S.inv_Ly + z * S.iyz, n, ty * T, T);
+        o.z = bin_local<R>(z * S.inv_Lz, n, tz * T, T);
         o.w = qv;
         return o;
     };
@@ -277,9 +281,17 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
     const R rho2 = R(S.lrho2), inv_rho2 = R(1.0 / S.lrho2);
     const R lsT = R(S.lsT);
     const R sc = R(S.n * S.inv_L);  // 1/h_x
-    // pair geometry in units of h_x: y and z grid offsets scale by h_y/h_x,
-    // h_z/h_x (1 in a cubic box)
-    const R ay = R(S.lay), az = R(S.laz);
+    // pair geometry in units of h_x: a grid-unit displacement d maps to
+    // (H/L) d, upper triangular with diagonal (1, h_y/h_x, h_z/h_x) and
+    // off-diagonal entries only in a triclinic cell
+    const R ay = R(S.lay), az = R(S.laz), mxy = R(S.mxy), mxz = R(S.mxz), myz = R(S.myz);
+    // explicit fused operations: a particle's own staged copy maps to exactly
+    // its own coordinates, so the self pair keeps r = 0
+    auto to_cart = [&](R gx, R gy, R gz, R& cx, R& cy, R& cz) {
+        cx = fma(mxz, gz, fma(mxy, gy, gx));
+        cy = fma(myz, gz, gy * ay);
+        cz = gz * az;
+    };
     // separable sub-cell index: cell(gx, gy, gz) = X(gx) + Y(gy) + Z(gz) with
     // Z(g) = (g/s)(nc - s) + g, Y(g) = (g/s)(t1 nc - s^2) + s g,
     // X(g) = (g/s)(t1^2 nc - s^3) + s^2 g
@@ -349,9 +361,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
             V* dst = hp + hs[c];
             for (int j = 0; j < nj; ++j) {
                 V v = cpos[j0 + j];
-                v.x += sx;
-                v.y = (v.y + sy) * ay;
-                v.z = (v.z + sz) * az;
+                to_cart(v.x + sx, v.y + sy, v.z + sz, v.x, v.y, v.z);
                 dst[j] = v;
             }
         }
@@ -375,7 +385,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
         const int lz = sub_cell<R>(vi.z, 0, s, lsT);
         R up = 0, fx = 0, fy = 0, fz = 0;
         if (staged) {
-            const R viy = vi.y * ay, viz = vi.z * az;
+            R vix, viy, viz;
+            to_cart(vi.x, vi.y, vi.z, vix, viy, viz);
             // halo rows hx .. hx + 2 lR around halo row hx + lR of the particle
             const int hx = min(max(lx - ox, 0), a - 1), hy = min(max(ly - oy, 0), a - 1),
                       hz = min(max(lz - oz, 0), a - 1);
@@ -388,18 +399,18 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                     int j = ja;
                     for (; j + 3 < jb; j += 4) {
                         const V v0 = hp[j], v1 = hp[j + 1], v2 = hp[j + 2], v3 = hp[j + 3];
-                        pair_term<R, D>(vi.x - v0.x, viy - v0.y, viz - v0.z, v0.w, rho2, inv_rho2, cA, cB, up, fx,
+                        pair_term<R, D>(vix - v0.x, viy - v0.y, viz - v0.z, v0.w, rho2, inv_rho2, cA, cB, up, fx,
                                         fy, fz);
-                        pair_term<R, D>(vi.x - v1.x, viy - v1.y, viz - v1.z, v1.w, rho2, inv_rho2, cA, cB, up, fx,
+                        pair_term<R, D>(vix - v1.x, viy - v1.y, viz - v1.z, v1.w, rho2, inv_rho2, cA, cB, up, fx,
                                         fy, fz);
-                        pair_term<R, D>(vi.x - v2.x, viy - v2.y, viz - v2.z, v2.w, rho2, inv_rho2, cA, cB, up, fx,
+                        pair_term<R, D>(vix - v2.x, viy - v2.y, viz - v2.z, v2.w, rho2, inv_rho2, cA, cB, up, fx,
                                         fy, fz);
-                        pair_term<R, D>(vi.x - v3.x, viy - v3.y, viz - v3.z, v3.w, rho2, inv_rho2, cA, cB, up, fx,
+                        pair_term<R, D>(vix - v3.x, viy - v3.y, viz - v3.z, v3.w, rho2, inv_rho2, cA, cB, up, fx,
                                         fy, fz);
                     }
                     for (; j < jb; ++j) {
                         const V vj = hp[j];
-                        pair_term<R, D>(vi.x - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
+                        pair_term<R, D>(vix - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
                                         fy, fz);
                     }
                 }
@@ -448,8 +459,9 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                         const int ja = cst[cell], jb = cst[cell + 1];
                         for (int j = ja; j < jb; ++j) {
                             const V vj = cpos[j];
-                            pair_term<R, D>(xs - vj.x, (ys - vj.y) * ay, (zs - vj.z) * az, vj.w, rho2, inv_rho2, cA,
-                                            cB, up, fx, fy, fz);
+                            R dx, dy, dz;
+                            to_cart(xs - vj.x, ys - vj.y, zs - vj.z, dx, dy, dz);
+                            pair_term<R, D>(dx, dy, dz, vj.w, rho2, inv_rho2, cA, cB, up, fx, fy, fz);
                         }
                     }
                 }

@@ -380,8 +380,23 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.Ly == 0) r.Ly = L;
     if (r.Lz == 0) r.Lz = L;
     if (!(std::isfinite(r.Ly) && std::isfinite(r.Lz))) { msg = "box sides must be finite"; return ESP_E_INVALID; }
-    // the longest side sets the grid, the coarsest spacing the cutoff
-    const double Lmax = std::max(L, std::max(r.Ly, r.Lz)), Lmin = std::min(L, std::min(r.Ly, r.Lz));
+    if (!(std::isfinite(r.xy) && std::isfinite(r.xz) && std::isfinite(r.yz))) {
+        msg = "cell tilts must be finite";
+        return ESP_E_INVALID;
+    }
+    if (tilted(r) && r.method != 0) {
+        msg = "a triclinic cell is supported by the ESP method (method 0) only";
+        return ESP_E_UNSUPPORTED;
+    }
+    if (tilted(r) && r.force_method != 0) {
+        msg = "a triclinic cell needs force_method 0 (analytic derivatives)";
+        return ESP_E_UNSUPPORTED;
+    }
+    // the longest lattice vector sets the grid and the cutoff (the resolved
+    // modes |m_d| <= n/2 then hold the sphere |k| <= pi n / Lmax); nearest
+    // images need rc at most half the smallest lattice-plane spacing
+    const Cell cell = cell_of(r);
+    const double Lmax = cell.amax, Lmin = cell.dmin;
     if (r.method == 1) return resolve_classical(L, Lmax, Lmin, tol, r, out, msg);
     if (r.c <= 0) r.c = c_for_tolerance(tol);
     if (r.P <= 0) r.P = order_for_tol(tol);
@@ -411,7 +426,8 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     if (r.force_method != 0 && r.force_method != 1) { msg = "force_method must be 0 or 1"; return ESP_E_INVALID; }
     if (r.local != 0 && r.local != 1) { msg = "local must be 0 or 1"; return ESP_E_INVALID; }
     if (r.local && r.rc > 0.5 * Lmin * (1 + 1e-12)) {
-        msg = "the local part needs rc <= L/2 (nearest images only)";
+        msg = tilted(r) ? "the local part needs rc <= half the smallest lattice-plane spacing"
+                        : "the local part needs rc <= L/2 (nearest images only)";
         return ESP_E_UNSUPPORTED;
     }
     if (r.c1 <= 0) {
@@ -710,14 +726,54 @@ double grid_rho(const esp_params& p) {
     return rho;
 }
 
+Cell cell_of(const esp_params& p) {
+    Cell c;
+    const double Lx = p.L, Ly = p.Ly, Lz = p.Lz;
+    c.i00 = 1.0 / Lx;
+    c.i11 = 1.0 / Ly;
+    c.i22 = 1.0 / Lz;
+    c.ixy = -p.xy / (Lx * Ly);
+    c.iyz = -p.yz / (Ly * Lz);
+    c.ixz = (p.xy * p.yz - p.xz * Ly) / (Lx * Ly * Lz);
+    c.amax = std::max(Lx, std::max(std::hypot(p.xy, Ly), std::hypot(std::hypot(p.xz, p.yz), Lz)));
+    // plane spacing of family d: 1 / |row d of H^-1|
+    const double ry = p.yz / Lz, rx1 = p.xy / Ly, rx2 = (p.xy * p.yz - p.xz * Ly) / (Ly * Lz);
+    c.dmin = std::min(Lz, std::min(Ly / std::sqrt(1.0 + ry * ry), Lx / std::sqrt(1.0 + rx1 * rx1 + rx2 * rx2)));
+    return c;
+}
+
 void box_influence(const esp_params& p, const ClassTables& ct, std::vector<double>& out) {
-    // p_m = S^(|k|)/V Tphi[|m_x|] Tphi[|m_y|] Tphi[|m_z|], k_d = 2 pi m_d/L_d: the
-    // window's transform in grid units is the same on every axis (Tphi of the
-    // class, h = 1), so the spacings cancel against the h^6 of eq. pk
+    // p_m = S^(|k|)/V Tphi[|m_x|] Tphi[|m_y|] Tphi[|m_z|]: the window's transform
+    // in grid units is the same on every axis (Tphi of the class, h = 1), so the
+    // spacings cancel against the h^6 of eq. pk. k = 2 pi H^-T m; in an
+    // orthorhombic box k_d = 2 pi m_d/L_d.
     const int n = p.nf, hs = n / 2 + 1;
     const double box[3] = {p.L, p.Ly, p.Lz}, V = box[0] * box[1] * box[2];
+    const Cell cell = cell_of(p);
+    const bool tilt = tilted(p);
     Prolate chi(p.method == 1 ? 1.0 : p.c);
     const double I1 = p.method == 1 ? 1.0 : chi.integral(1.0);
+    auto chat = [&](double k2) {
+        const double w = p.rc * std::sqrt(k2);
+        return p.method == 1 ? std::exp(-w * w / (4.0 * p.c)) : 0.5 * chi.ft(w) / I1;
+    };
+    // a tilted cell's p depends on the signs of m; an index at the Nyquist
+    // frequency n/2 stands for both signs, and p there is the mean over them,
+    // which keeps p(-m) = p(m) on the index grid (a real inverse transform)
+    auto p_tilted = [&](int mx, int my, int mz) {
+        const int fx = std::abs(mx) == n / 2 ? 2 : 1, fy = std::abs(my) == n / 2 ? 2 : 1,
+                  fz = std::abs(mz) == n / 2 ? 2 : 1;
+        double acc = 0.0;
+        for (int a = 0; a < fx; ++a)
+            for (int b = 0; b < fy; ++b)
+                for (int c = 0; c < fz; ++c) {
+                    const double ax = a ? -mx : mx, by = b ? -my : my, cz = c ? -mz : mz;
+                    const double kx = 2 * kPi * (ax * cell.i00), ky = 2 * kPi * (ax * cell.ixy + by * cell.i11),
+                                 kz = 2 * kPi * (ax * cell.ixz + by * cell.iyz + cz * cell.i22);
+                    acc += chat(kx * kx + ky * ky + kz * kz) / (kx * kx + ky * ky + kz * kz);
+                }
+        return acc / (fx * fy * fz);
+    };
     out.assign((size_t)n * n * hs, 0.0);
     for (int x = 0; x < n; ++x) {
         const int mx = x <= n / 2 ? x : x - n;
@@ -725,11 +781,16 @@ void box_influence(const esp_params& p, const ClassTables& ct, std::vector<doubl
             const int my = y <= n / 2 ? y : y - n;
             for (int z = 0; z < hs; ++z) {
                 if (mx == 0 && my == 0 && z == 0) continue;
-                const double kx = 2 * kPi * mx / box[0], ky = 2 * kPi * my / box[1], kz = 2 * kPi * z / box[2];
-                const double k2 = kx * kx + ky * ky + kz * kz, w = p.rc * std::sqrt(k2);
-                const double chat = p.method == 1 ? std::exp(-w * w / (4.0 * p.c)) : 0.5 * chi.ft(w) / I1;
+                double s;
+                if (tilt) {
+                    s = p_tilted(mx, my, z);
+                } else {
+                    const double kx = 2 * kPi * mx / box[0], ky = 2 * kPi * my / box[1], kz = 2 * kPi * z / box[2];
+                    const double k2 = kx * kx + ky * ky + kz * kz;
+                    s = chat(k2) / k2;
+                }
                 out[((size_t)x * n + y) * hs + z] =
-                    chat / k2 / V * ct.Tphi[std::abs(mx)] * ct.Tphi[std::abs(my)] * ct.Tphi[z];
+                    s / V * ct.Tphi[std::abs(mx)] * ct.Tphi[std::abs(my)] * ct.Tphi[z];
             }
         }
     }

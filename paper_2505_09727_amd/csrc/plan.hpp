@@ -85,4 +85,15 @@ std::shared_ptr<const ClassTables> class_tables(const esp_params& p);
 // the grid's order: n x n x (n/2 + 1) doubles.
 void box_influence(const esp_params& p, const ClassTables& ct, std::vector<double>& out);
 
+// The cell H = [[L, xy, xz], [0, Ly, yz], [0, 0, Lz]] of resolved params: its
+// inverse (upper triangular), the longest lattice vector and the smallest
+// distance between lattice planes (exactly the sides' max and min when the
+// tilts are 0).
+struct Cell {
+    double i00, ixy, ixz, i11, iyz, i22;
+    double amax, dmin;
+};
+Cell cell_of(const esp_params& p);
+inline bool tilted(const esp_params& p) { return p.xy != 0.0 || p.xz != 0.0 || p.yz != 0.0; }
+
 }  // namespace esp

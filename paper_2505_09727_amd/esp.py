@@ -32,7 +32,8 @@ class esp_params(C.Structure):
                 ("c", C.c_double), ("c1", C.c_double), ("rc", C.c_double), ("h_max", C.c_double),
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
                 ("s0", C.c_double), ("force_method", C.c_int), ("local", C.c_int),
-                ("method", C.c_int), ("Ly", C.c_double), ("Lz", C.c_double)]
+                ("method", C.c_int), ("Ly", C.c_double), ("Lz", C.c_double),
+                ("xy", C.c_double), ("xz", C.c_double), ("yz", C.c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -207,13 +208,17 @@ class Plan:
     """A single-system or batched plan (esp_plan_create_ex / esp_batch_create)."""
 
     def __init__(self, L, N, tol, per_system=None, **req):
-        """Single system (scalar L, or a box (Lx, Ly, Lz), and scalar N) or batch
-        (sequences of x sides and sizes; per-system Ly, Lz through per_system).
+        """Single system (scalar L, a box (Lx, Ly, Lz) or a triclinic cell
+        (Lx, Ly, Lz, xy, xz, yz), and scalar N) or batch (sequences of x sides
+        and sizes; per-system Ly, Lz and tilts through per_system).
         per_system: one dict of requested parameters per system of a batch
         (overrides req)."""
         self._h = C.c_void_p()
-        if np.ndim(L) == 0 or (np.ndim(N) == 0 and len(L) == 3):
-            # one system: side L, or an orthorhombic box (Lx, Ly, Lz)
+        if np.ndim(L) == 0 or (np.ndim(N) == 0 and len(L) in (3, 6)):
+            # one system: side L, an orthorhombic box or a triclinic cell
+            if np.ndim(L) and len(L) == 6:
+                req = dict(req, xy=float(L[3]), xz=float(L[4]), yz=float(L[5]))
+                L = L[:3]
             box = _box(float(L)) if np.ndim(L) == 0 else (C.c_double * 3)(*[float(x) for x in L])
             _check(lib().esp_plan_create_ex(box, int(N), float(tol), C.byref(_req(**req)), C.byref(self._h)))
         else:

@@ -153,6 +153,27 @@ def test_orthorhombic_parameters():
         esp.esp_plan_query((24.0, 24.0, 8.0), 1000, 1e-4, local=1)  # rc > 8/2
 
 
+def test_triclinic_parameters():
+    # the longest lattice vector sets the grid and the cutoff; the local part
+    # needs rc at most half the smallest distance between lattice planes
+    _lib_or_skip()
+    p = esp.esp_plan_query((16.0, 15.0, 14.0), 1000, 1e-4, xy=10.0, xz=-2.0, yz=3.0)
+    c = esp.esp_plan_query(math.hypot(10.0, 15.0), 1000, 1e-4)
+    assert (p.xy, p.xz, p.yz) == (10.0, -2.0, 3.0)
+    assert p.nf == c.nf and abs(p.rc - c.rc) < 1e-12 and p.c1 == c.c1 and p.P == c.P
+    assert esp.esp_plan_query((14.0, 14.0, 14.0), 1000, 1e-4, local=1).local == 1
+    with pytest.raises(esp.EspError) as ei:  # plane spacing 14/sqrt(1 + (13/14)^2) = 10.3 < 2 rc
+        esp.esp_plan_query((14.0, 14.0, 14.0), 1000, 1e-4, xy=13.0, local=1)
+    assert ei.value.status == -2 and "plane" in esp.lib().esp_last_error().decode()
+    for kw in ({"force_method": 1}, {"method": 1}):
+        with pytest.raises(esp.EspError) as ei:
+            esp.esp_plan_query((16.0, 15.0, 14.0), 1000, 1e-4, xy=1.0, **kw)
+        assert ei.value.status == -2
+    with pytest.raises(esp.EspError) as ei:
+        esp.esp_plan_query((16.0, 15.0, 14.0), 1000, 1e-4, yz=math.inf)
+    assert ei.value.status == -1
+
+
 def test_table2_through_the_library():
     _lib_or_skip()
     for eps, c_tab, P_tab in [(1e-3, 9.5392, 5), (5e-4, 10.290, 5), (1e-4, 12.024, 6), (5e-5, 12.762, 7),

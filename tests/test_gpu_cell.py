@@ -1,0 +1,128 @@
+"""Triclinic cells (tilts xy, xz, yz; the index grid over fractional
+coordinates): the device path against the reference five-step method in a cell
+(oracle.cell), with the local part against triclinic Ewald, positions outside
+the cell, the rock-salt Madelung constant in a sheared cell, and a batch mixing
+triclinic, orthorhombic and cubic systems.
+
+Workloads: random positions with the water charges (O, H, H repeated) at
+0.03 atoms/Å^3 in a 30 x 28 x 26 Å cell with tilts (6, -4, 5) and a
+24 x 26 x 22 Å cell with tilts (-8, 5, -3), and 4 x 4 x 4 rock-salt cells
+described by the lattice vectors a, a + b, c."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.cell import cell_matrix, ewald_cell, five_step_cell, local_sum_cell
+from oracle.metrics import rel_rms
+from oracle.split import PSWFSplit
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_09727_amd.esp import Plan  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+CELLS = [(30.0, 28.0, 26.0, 6.0, -4.0, 5.0), (24.0, 26.0, 22.0, -8.0, 5.0, -3.0)]
+
+
+def run(plan, pos, q):
+    dt = torch.float64 if plan.precision == 64 else torch.float32
+    tp = torch.tensor(np.ascontiguousarray(pos), dtype=dt, device=DEV)
+    tq = torch.tensor(np.ascontiguousarray(q), dtype=dt, device=DEV)
+    phi = torch.empty(len(q), dtype=dt, device=DEV)
+    F = torch.empty((len(q), 3), dtype=dt, device=DEV)
+    E = plan.longrange(tp, tq, phi, F)
+    torch.cuda.synchronize()
+    return phi.cpu().double().numpy(), F.cpu().double().numpy(), np.asarray(E)
+
+
+def random_cell(cell, seed, density=0.03, outside=False):
+    H = cell_matrix(*cell)
+    rng = np.random.default_rng(seed)
+    N = 3 * int(density * np.linalg.det(H) / 3)
+    s = rng.uniform(0, 1, (N, 3))
+    if outside:  # whole lattice vectors away from the cell
+        s += rng.integers(-2, 3, (N, 3))
+    return s @ H.T, np.tile([W.Q_O, W.Q_H, W.Q_H], N // 3)
+
+
+def reference(pos, q, p, local):
+    H = cell_matrix(p.L, p.Ly, p.Lz, p.xy, p.xz, p.yz)
+    r = five_step_cell(pos, q, H, p.nf, p.P, p.c, p.rc, p.c1)
+    phi, F = r["phi"], r["F"]
+    if local:
+        ul, gl = local_sum_cell(pos, q, H, PSWFSplit(p.c, p.rc))
+        phi, F = phi + ul, F - q[:, None] * gl
+    return phi, F, 0.5 * float(np.dot(q, phi))
+
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("prec,bar_F,bar_E", [(64, 1e-9, 1e-10), (32, 1e-5, 1e-6)])
+@pytest.mark.parametrize("local", [0, 1])
+def test_cell_against_reference(cell, prec, bar_F, bar_E, local):
+    pos, q = random_cell(cell, seed=int(sum(cell)))
+    plan = Plan(cell, len(q), 1e-4, precision=prec, local=local, degree=16 if prec == 64 else None)
+    p = plan.params[0]
+    assert (p.L, p.Ly, p.Lz, p.xy, p.xz, p.yz) == cell and p.nf == 24
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    pr = pos if prec == 64 else pos.astype(np.float32).astype(np.float64)
+    phi_r, F_r, E_r = reference(pr, q, p, local)
+    # E = (1/2) sum q phi cancels between the charges of random positions: its
+    # bar scales with (1/2) sum |q phi|, the size of the terms it sums
+    eE = abs(E[0] - E_r) / (0.5 * float(np.abs(q * phi_r).sum()))
+    eF, ephi = rel_rms(F, F_r), rel_rms(phi, phi_r)
+    print(f"cell {cell} N={len(q)} prec={prec} local={local}: relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
+    assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    if local:
+        _, F_e, E_e = ewald_cell(pr, q, cell_matrix(*cell))
+        print(f"cell {cell} prec={prec}: Delta={rel_rms(F, F_e):.2e}")
+        assert rel_rms(F, F_e) < 1e-4 and abs(E[0] - E_e) < 1e-4 * abs(E_e)
+
+
+def test_positions_outside_the_cell():
+    cell = CELLS[0]
+    pos, q = random_cell(cell, seed=9, outside=True)
+    plan = Plan(cell, len(q), 1e-4, precision=64, local=1, degree=16)
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    phi_r, F_r, E_r = reference(pos, q, plan.params[0], 1)
+    assert rel_rms(F, F_r) < 1e-9 and rel_rms(phi, phi_r) < 1e-9 and abs(E[0] - E_r) < 1e-10 * abs(E_r)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_madelung_constant_in_a_sheared_cell(prec):
+    pos, q, L = W.nacl_crystal(cells=4)
+    cell = (L, L, L, L, 0.0, 0.0)  # lattice vectors a, a + b, c
+    plan = Plan(cell, len(q), 1e-4, precision=prec, degree=16 if prec == 64 else None, local=1)
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    r0 = 5.64 / 2
+    M = -phi * q * 4 * math.pi * r0
+    print(f"sheared rock salt prec={prec}: max |M - M_ref| = {np.max(np.abs(M - 1.747565)):.2e}, "
+          f"max |F| / f_nn = {np.max(np.abs(F)) * 4 * math.pi * r0 ** 2:.2e}")
+    assert np.max(np.abs(M - 1.747565)) < 1e-4 * 1.747565
+    assert np.max(np.abs(F)) < 2e-4 / (4 * math.pi * r0 ** 2)
+
+
+def test_batch_of_triclinic_orthorhombic_and_cubic_systems():
+    cells = [CELLS[0], (20.0, 20.0, 20.0, 0.0, 0.0, 0.0), CELLS[1], (18.0, 21.0, 24.0, 0.0, 0.0, 0.0)]
+    systems = [random_cell(c, seed=60 + i) for i, c in enumerate(cells)]
+    Ns = [len(s[1]) for s in systems]
+    off = np.cumsum([0] + Ns)
+    per = [{"Ly": c[1], "Lz": c[2], "xy": c[3], "xz": c[4], "yz": c[5], "local": 1} for c in cells]
+    batch = Plan([c[0] for c in cells], Ns, 1e-4, per_system=per)
+    phi_b, F_b, E_b = run(batch, np.concatenate([s[0] for s in systems]), np.concatenate([s[1] for s in systems]))
+    batch.close()
+    for i, c in enumerate(cells):
+        single = Plan(c, Ns[i], 1e-4, local=1)
+        phi_s, F_s, E_s = run(single, systems[i][0], systems[i][1])
+        single.close()
+        sl = slice(off[i], off[i + 1])
+        assert np.array_equal(F_s, F_b[sl]) and np.array_equal(phi_s, phi_b[sl]) and E_s[0] == E_b[i], i
