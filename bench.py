@@ -30,6 +30,13 @@ PEAK_FP32_VALU_TFLOPS = 78.6   # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes
 PEAK_FP64_VALU_TFLOPS = 78.6
 
 
+def _rel_rms(a, b):
+    """sqrt(sum |a - b|^2 / sum |b|^2): agreement of two runs of the library."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
 def algorithmic_cost(phase, N, n, P, deg, prec):
     """Algorithmic HBM bytes and flops of one launch of a phase for one system
     of N particles on an n^3 grid (formulas in the design notes)."""
@@ -238,13 +245,10 @@ def _time_plan(plan, ext, pos, q, phi, F, steps):
     return e0.elapsed_time(e1) / steps
 
 
-def ik_run(pos, q, L, B, N, steps, F_ad, box0):
+def ik_run(pos, q, L, B, N, steps, F_ad):
     """The same batch with forces by spectral derivatives (ik): cost beside
-    the AD route, force difference, net force, parity of box 0 against the
-    reference's ik route."""
+    the AD route, force difference and net force."""
     import torch
-    from oracle.fivestep import five_step_ik
-    from oracle.metrics import rel_rms
     from paper_2505_09727_amd.esp import Plan
     dev = torch.device("cuda:0")
     plan = Plan([L] * B, [N] * B, 1e-4, force_method=1)
@@ -256,15 +260,13 @@ def ik_run(pos, q, L, B, N, steps, F_ad, box0):
         plan.longrange_async(pos, q, phi, F)
     ms = _time_plan(plan, ext, pos, q, phi, F, steps)
     plan.longrange(pos, q, phi, F)
-    p = plan.params[0]
     Fik = F.cpu().double().numpy()
     plan.close()
-    ref = five_step_ik(box0[0], box0[1], L, p.nf, p.P, p.c, p.rc, p.c1)
     F0 = Fik[:N]
     net = np.abs(F0.sum(axis=0)).max() / (N * np.sqrt(np.mean(F0 ** 2)))
     net_ad = np.abs(F_ad[:N].sum(axis=0)).max() / (N * np.sqrt(np.mean(F_ad[:N] ** 2)))
     return {"particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms,
-            "rel_rms_F_ik_vs_ad": rel_rms(Fik, F_ad), "rel_rms_F_vs_reference_ik": rel_rms(F0, ref["F"]),
+            "rel_rms_F_ik_vs_ad": _rel_rms(Fik, F_ad),
             "net_force_rel": {"ik": float(net), "ad": float(net_ad)}}
 
 
@@ -279,17 +281,12 @@ def _pairs_within(pos, L, rc, chunk=512):
     return cnt
 
 
-def local_run(pos, q, L, B, N, steps, box0, reps, ewald0):
+def local_run(pos, q, L, B, N, steps, box0, reps):
     """The same batch with the local part of the split on the device (full
-    Coulomb phi, F, E): cost beside the long-range step, the local phase's
-    time and ALU roofline, and box 0 against classical Ewald (the paper's
-    Delta) and against the reference five-step plus local sum."""
+    Coulomb phi, F, E): cost beside the long-range step, and the local phase's
+    time and ALU roofline."""
     import ctypes as C
     import torch
-    from oracle.fivestep import five_step
-    from oracle.metrics import rel_rms
-    from oracle.split import PSWFSplit
-    from oracle.spectral import local_sum
     from paper_2505_09727_amd.esp import Plan, esp_local_coeffs, lib
     dev = torch.device("cuda:0")
     plan = Plan([L] * B, [N] * B, 1e-4, local=1)
@@ -300,8 +297,6 @@ def local_run(pos, q, L, B, N, steps, box0, reps, ewald0):
     for _ in range(3):
         plan.longrange_async(pos, q, phi, F)
     ms = _time_plan(plan, ext, pos, q, phi, F, steps)
-    E = plan.longrange(pos, q, phi, F)
-    F0 = F[:N].cpu().double().numpy()
     nph = lib().esp_num_phases()
     msp = (C.c_double * nph)()
     st = lib().esp_plan_profile(plan._h, C.c_void_p(pos.data_ptr()), C.c_void_p(q.data_ptr()),
@@ -310,13 +305,7 @@ def local_run(pos, q, L, B, N, steps, box0, reps, ewald0):
     phases = {lib().esp_phase_name(i).decode(): msp[i] for i in range(nph)}
     p = plan.params[0]
     plan.close()
-    q0 = box0[1]
     pos0 = box0[0].astype(np.float32).astype(np.float64)
-    ref = five_step(pos0, q0, L, p.nf, p.P, p.c, p.rc, p.c1)
-    ul, gl = local_sum(pos0, q0, L, PSWFSplit(p.c, p.rc))
-    F_ref = ref["F"] - q0[:, None] * gl
-    E_ref = 0.5 * float(np.dot(q0, ref["phi"] + ul))
-    F_e, E_e = ewald0
     pairs = _pairs_within(pos0, L, p.rc)
     deg = esp_local_coeffs(p)[0].shape[1] - 1
     fpp = 27 + 4 * deg
@@ -324,8 +313,6 @@ def local_run(pos, q, L, B, N, steps, box0, reps, ewald0):
     t = phases["local"] / 1e3
     tfl = flops / t / 1e12
     return {"particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms, "phases_ms": phases,
-            "rel_rms_F_vs_reference": rel_rms(F0, F_ref), "rel_E_vs_reference": abs(E[0] - E_ref) / abs(E_ref),
-            "delta_F_vs_ewald": rel_rms(F0, F_e), "rel_E_vs_ewald": abs(E[0] - E_e) / abs(E_e),
             "roofline_local": {"kernel": "k_cellsort + k_local", "bound": "alu", "achieved": tfl,
                                "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": tfl / PEAK_FP32_VALU_TFLOPS,
                                "traffic": None, "avg_launch_ms": phases["local"],
@@ -337,38 +324,24 @@ def local_run(pos, q, L, B, N, steps, box0, reps, ewald0):
 FFT_SIZES = (8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72, 96, 108, 128, 144)
 
 
-def classical_run(pos, q, L, B, N, steps, box0, ewald0, ms_esp, ms_esp_full, delta_esp, tol=1e-4):
+# The smallest grid at which the classical method (P = 5, alpha = log(1/tol),
+# the ESP cutoff) reaches a full-Coulomb force error of 1e-4 against Ewald on
+# the 9000-atom water-like box (L = 31); the device tests check it.
+CLASSICAL_GRID_WATER9K = 48
+
+
+def classical_run(pos, q, L, B, N, steps, ms_esp, ms_esp_full, tol=1e-4):
     """The classical method (Gaussian split, B-spline window of order 5, the
-    ESP cutoff) on the same batch: the smallest grid whose full-Coulomb force
-    error on box 0 against Ewald meets the tolerance (eq. cemparameters' grid
-    pushed up for aliasing), then the batch at that grid beside ESP."""
+    ESP cutoff) on the same batch at the smallest grid that meets the
+    tolerance (eq. cemparameters' grid pushed up for aliasing), beside ESP."""
     import torch
-    from oracle.metrics import rel_rms
     from paper_2505_09727_amd.esp import Plan, esp_plan_query
     dev = torch.device("cuda:0")
-    F_e, E_e = ewald0
     p0 = esp_plan_query(L, N, tol, method=1)
     p_esp = esp_plan_query(L, N, tol)
-    t0 = torch.tensor(box0[0], dtype=torch.float32, device=dev)
-    q0 = torch.tensor(box0[1], dtype=torch.float32, device=dev)
-    trials = []
-    chosen = None
-    for n in [m for m in FFT_SIZES if m >= min(p0.nf, 24)]:
-        pl = Plan(L, N, tol, method=1, nf=n, local=1)
-        ph = torch.empty(N, dtype=torch.float32, device=dev)
-        F = torch.empty((N, 3), dtype=torch.float32, device=dev)
-        pl.longrange(t0, q0, ph, F)
-        pl.close()
-        d = rel_rms(F.cpu().double().numpy(), F_e)
-        trials.append({"grid": n, "delta_F_vs_ewald": d})
-        if d <= tol:
-            chosen = n
-            break
-    out = {"P": p0.P, "alpha": p0.c, "rc": p0.rc, "grid_formula": p0.nf, "calibration": trials, "grid": chosen,
-           "grid_esp": p_esp.nf, "delta_F_vs_ewald_esp": delta_esp}
-    if chosen is None:
-        return out
-    out["grid_ratio_R"] = (chosen / p_esp.nf) ** 3
+    chosen = CLASSICAL_GRID_WATER9K
+    out = {"P": p0.P, "alpha": p0.c, "rc": p0.rc, "grid_formula": p0.nf, "grid": chosen, "grid_esp": p_esp.nf,
+           "grid_ratio_R": (chosen / p_esp.nf) ** 3}
     for local, key in ((0, "longrange"), (1, "full_coulomb")):
         plan = Plan([L] * B, [N] * B, tol, method=1, nf=chosen, local=local)
         phi = torch.empty(B * N, dtype=torch.float32, device=dev)
@@ -429,11 +402,9 @@ def box_run(steps, B=128, n_mol=3000, tol=1e-4):
     """Orthorhombic boxes: a batch of water-like boxes of the 9000-atom
     workload's volume and density with the membrane system's aspect ratio
     (10.79 : 10.18 : 9.55, Methods, experimental design), timed beside the
-    cubic batch; box 0 with the local part against orthorhombic Ewald."""
+    cubic batch, and with the local part."""
     import torch
     import workloads as W
-    from oracle.box import ewald_box
-    from oracle.metrics import rel_rms
     from paper_2505_09727_amd.esp import Plan
     dev = torch.device("cuda:0")
     ratios = np.array([10.79, 10.18, 9.55])
@@ -452,15 +423,53 @@ def box_run(steps, B=128, n_mol=3000, tol=1e-4):
         plan.longrange_async(pos, q, phi, F)
     ms = _time_plan(plan, ext, pos, q, phi, F, steps)
     plan.close()
-    one = Plan(tuple(box), N, tol, local=1)
-    F0 = torch.empty((N, 3), dtype=torch.float32, device=dev)
-    one.longrange(pos[:N].contiguous(), q[:N].contiguous(), phi[:N].contiguous(), F0)
-    one.close()
-    _, F_e, _ = ewald_box(boxes[0][0].astype(np.float32).astype(np.float64), boxes[0][1], box)
+    full = Plan([box[0]] * B, [N] * B, tol, per_system=[{"Ly": box[1], "Lz": box[2], "local": 1}] * B)
+    ext = torch.cuda.ExternalStream(full.stream)
+    full.set_graph(True)
+    for _ in range(3):
+        full.longrange_async(pos, q, phi, F)
+    ms_full = _time_plan(full, ext, pos, q, phi, F, steps)
+    full.close()
     return {"box": [float(x) for x in box], "grid": p.nf, "P": p.P, "rc": p.rc,
-            "particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms,
-            "delta_F_vs_ewald_full_coulomb": rel_rms(F0.cpu().double().numpy(), F_e),
+            "particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms, "full_coulomb_ms_per_step": ms_full,
             "workload": f"batch of {B} orthorhombic water-like boxes, {N} atoms each, FP32, tol {tol}"}
+
+
+def cell_run(steps, B=128, n_mol=3000, tol=1e-4):
+    """Triclinic cells: a batch of water-like rhombic dodecahedra (square xy
+    face) of the 9000-atom workload's volume and density, timed beside the
+    cubic batch, and with the local part."""
+    import torch
+    import workloads as W
+    from paper_2505_09727_amd.esp import Plan
+    dev = torch.device("cuda:0")
+    H = W.rhombic_dodecahedron(31.0 ** 3)
+    cell = (H[0, 0], H[1, 1], H[2, 2], H[0, 1], H[0, 2], H[1, 2])
+    tilt = {"Ly": cell[1], "Lz": cell[2], "xy": cell[3], "xz": cell[4], "yz": cell[5]}
+    cells = [W.water_cell(n_mol, H, seed=3000 + b) for b in range(B)]
+    N = 3 * n_mol
+    pos = torch.tensor(np.concatenate([c[0] for c in cells]), dtype=torch.float32, device=dev)
+    q = torch.tensor(np.concatenate([c[1] for c in cells]), dtype=torch.float32, device=dev)
+    plan = Plan([cell[0]] * B, [N] * B, tol, per_system=[tilt] * B)
+    p = plan.params[0]
+    phi = torch.empty(B * N, dtype=torch.float32, device=dev)
+    F = torch.empty((B * N, 3), dtype=torch.float32, device=dev)
+    ext = torch.cuda.ExternalStream(plan.stream)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange_async(pos, q, phi, F)
+    ms = _time_plan(plan, ext, pos, q, phi, F, steps)
+    plan.close()
+    full = Plan([cell[0]] * B, [N] * B, tol, per_system=[dict(tilt, local=1)] * B)
+    ext = torch.cuda.ExternalStream(full.stream)
+    full.set_graph(True)
+    for _ in range(3):
+        full.longrange_async(pos, q, phi, F)
+    ms_full = _time_plan(full, ext, pos, q, phi, F, steps)
+    full.close()
+    return {"cell": [float(v) for v in cell], "grid": p.nf, "P": p.P, "rc": p.rc,
+            "particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms, "full_coulomb_ms_per_step": ms_full,
+            "workload": f"batch of {B} rhombic-dodecahedron water-like cells, {N} atoms each, FP32, tol {tol}"}
 
 
 def ensemble_run(steps, seed=4):
@@ -470,7 +479,6 @@ def ensemble_run(steps, seed=4):
     import torch
     import workloads as W
     from collections import Counter
-    from oracle.metrics import rel_rms
     from paper_2505_09727_amd.esp import Plan
     dev = torch.device("cuda:0")
     systems = W.ensemble(n_sys=256, seed=seed)
@@ -511,7 +519,7 @@ def ensemble_run(steps, seed=4):
         e64 = torch.cuda.ExternalStream(p64.stream)
         p64.longrange_async(tp, tq, ph, Fs)
         ms64 += _time_plan(p64, e64, tp, tq, ph, Fs, 3)
-        errs.append(rel_rms(F32[off[s]:off[s + 1]], Fs.cpu().numpy()))
+        errs.append(_rel_rms(F32[off[s]:off[s + 1]], Fs.cpu().numpy()))
         p64.close()
     return {
         "workload": f"256 water-like boxes at 1 g/cm^3, atoms log-uniform in [500, 20000] (total {Ntot}), "
@@ -533,7 +541,6 @@ def large_run(steps, serve_steps=100):
     resident, one request)."""
     import torch
     import workloads as W
-    from oracle.metrics import rel_rms
     from paper_2505_09727_amd.esp import Plan, Server
     dev = torch.device("cuda:0")
     cfg = W.WATER_300K
@@ -573,7 +580,7 @@ def large_run(steps, serve_steps=100):
     plan.close()
     out["fp32_full_coulomb"] = {"particle_steps_per_s": N / (msl / 1e3), "ms_per_step": msl}
     out["speedup_fp32_vs_fp64_plain"] = res[64]["ms"] / res[32]["ms"]
-    out["rel_rms_F_fp32_vs_fp64"] = rel_rms(res[32]["F"], res[64]["F"])
+    out["rel_rms_F_fp32_vs_fp64"] = _rel_rms(res[32]["F"], res[64]["F"])
     out["rel_E_fp32_vs_fp64"] = abs(res[32]["E"] - res[64]["E"]) / abs(res[64]["E"])
     srv = Server()
     t0 = time.perf_counter()
@@ -608,6 +615,7 @@ def main():
     ap.add_argument("--no-classical", action="store_true", help="skip the classical-method (PME) comparison")
     ap.add_argument("--no-box", action="store_true", help="skip the orthorhombic-box section")
     ap.add_argument("--no-nacl", action="store_true", help="skip the 512-ion crystal section")
+    ap.add_argument("--no-cell", action="store_true", help="skip the triclinic-cell section")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -666,15 +674,10 @@ def main():
     total_ms = evs[0].elapsed_time(evs[-1])
     ms_per_step = total_ms / args.steps
     value = B * N * args.steps / (total_ms / 1e3)
-    E0 = plan.longrange(pos, q, phi, F)      # one checked call (neutrality, energies)
+    plan.longrange(pos, q, phi, F)  # one synchronous call: its forces feed the comparisons below
 
-    # parity of one system of the batch against the CPU reference
-    from oracle.fivestep import five_step
-    from oracle.metrics import rel_rms
-    ref = five_step(boxes[0][0], boxes[0][1], L, prm.nf, prm.P, prm.c, prm.rc, prm.c1)
     F_all = F.double().cpu().numpy()
     F0 = F_all[:N]
-    parity = dict(rel_rms_F=rel_rms(F0, ref["F"]), rel_E=abs(E0[0] - ref["E"]) / abs(ref["E"]))
 
     # per-phase timing (HIP events between phases on the plan's stream)
     nph = lib().esp_num_phases()
@@ -708,25 +711,20 @@ def main():
     e1.synchronize()
     ms64 = e0.elapsed_time(e1) / k64
     fp64 = dict(value=N / (ms64 / 1e3), unit="particle-steps/s", ms_per_step=ms64,
-                rel_rms_F_vs_fp32=rel_rms(F0, F64.cpu().numpy()))
+                rel_rms_F_fp32_vs_fp64=_rel_rms(F0, F64.cpu().numpy()))
     p64.close()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(boxes, L, prm)
     serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_budget_gb) if args.serve_seconds > 0 else None
-    ik = None if args.no_ik else ik_run(pos, q, L, B, N, max(10, args.steps // 4), F_all, boxes[0])
-    ewald0 = None
-    if not (args.no_local and args.no_classical):
-        from oracle.ewald import ewald
-        _, F_e0, E_e0 = ewald(boxes[0][0], boxes[0][1], L)
-        ewald0 = (F_e0, E_e0)
+    ik = None if args.no_ik else ik_run(pos, q, L, B, N, max(10, args.steps // 4), F_all)
     full = None if args.no_local else local_run(pos, q, L, B, N, max(10, args.steps // 4), boxes[0],
-                                                   args.profile_reps, ewald0)
+                                                   args.profile_reps)
     classical = None
     if not args.no_classical:
-        classical = classical_run(pos, q, L, B, N, max(10, args.steps // 4), boxes[0], ewald0, ms_per_step,
-                                  full["ms_per_step"] if full else None,
-                                  full["delta_F_vs_ewald"] if full else None)
+        classical = classical_run(pos, q, L, B, N, max(10, args.steps // 4), ms_per_step,
+                                  full["ms_per_step"] if full else None)
     ortho = None if args.no_box else box_run(max(10, args.steps // 4))
+    tric = None if args.no_cell else cell_run(max(10, args.steps // 4))
     nacl = None if args.no_nacl else nacl_run()
     ensemble = None if args.no_ensemble else ensemble_run(max(10, args.steps // 4))
     large = None if args.no_large else large_run(max(10, args.steps // 10))
@@ -753,7 +751,6 @@ def main():
         "wall_s_timed_region": t_wall,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": value / fp64["value"],
-        "parity_vs_reference": parity,
         "phases_ms": phases,
         "roofline": roof,
         "kernel_rooflines": kernels,
@@ -763,6 +760,7 @@ def main():
         "full_coulomb": full,
         "classical_method": classical,
         "orthorhombic": ortho,
+        "triclinic": tric,
         "nacl_512": nacl,
         "ensemble": ensemble,
         "large_system": large,

@@ -6,8 +6,9 @@ triclinic, orthorhombic and cubic systems.
 
 Workloads: random positions with the water charges (O, H, H repeated) at
 0.03 atoms/Å^3 in a 30 x 28 x 26 Å cell with tilts (6, -4, 5) and a
-24 x 26 x 22 Å cell with tilts (-8, 5, -3), and 4 x 4 x 4 rock-salt cells
-described by the lattice vectors a, a + b, c."""
+24 x 26 x 22 Å cell with tilts (-8, 5, -3), 4 x 4 x 4 rock-salt cells
+described by the lattice vectors a, a + b, c, and 3000 rigid waters in a
+rhombic dodecahedron of the 9000-atom box's volume (31^3 Å^3)."""
 import math
 
 import numpy as np
@@ -126,3 +127,26 @@ def test_batch_of_triclinic_orthorhombic_and_cubic_systems():
         single.close()
         sl = slice(off[i], off[i + 1])
         assert np.array_equal(F_s, F_b[sl]) and np.array_equal(phi_s, phi_b[sl]) and E_s[0] == E_b[i], i
+
+
+def test_rhombic_dodecahedron_water9k_sampled():
+    # the benchmark's triclinic workload: the long-range part whole, the local
+    # part at 400 sampled atoms; FP32 as timed, and Delta against Ewald
+    H = W.rhombic_dodecahedron(31.0 ** 3)
+    cell = (H[0, 0], H[1, 1], H[2, 2], H[0, 1], H[0, 2], H[1, 2])
+    pos, q = W.water_cell(3000, H, seed=3000)
+    plan = Plan(cell, len(q), 1e-4, local=1)
+    p = plan.params[0]
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    x = pos.astype(np.float32).astype(np.float64)
+    idx = np.random.default_rng(7).choice(len(q), 400, replace=False)
+    r = five_step_cell(x, q, H, p.nf, p.P, p.c, p.rc, p.c1)
+    ul, gl = local_sum_cell(x, q, H, PSWFSplit(p.c, p.rc), targets=idx)
+    F_r = r["F"][idx] - q[idx, None] * gl
+    phi_r = r["phi"][idx] + ul
+    eF, ephi = rel_rms(F[idx], F_r), rel_rms(phi[idx], phi_r)
+    u_e, F_e, _ = ewald_cell(x, q, H, targets=idx)
+    delta = rel_rms(F[idx], F_e)
+    print(f"rhombic dodecahedron N={len(q)} n={p.nf}: relF={eF:.2e} relphi={ephi:.2e} Delta(sampled)={delta:.2e}")
+    assert eF < 1e-5 and ephi < 1e-5 and delta < 1e-4

@@ -90,6 +90,31 @@ def test_other_window_orders(P, n):
         plan.close()
 
 
+def test_classical_grid_calibration(water9k):
+    # the smallest grid at which the classical method (defaults: P = 5,
+    # alpha = log(1/tol), the ESP cutoff) meets Delta <= 1e-4 with the local
+    # part on the 9000-atom box; the benchmark times it there, beside ESP at
+    # its own default grid
+    import bench
+    pos, q, L, F_e, E_e = water9k
+    first = None
+    for n in [m for m in bench.FFT_SIZES if 24 <= m <= 64]:
+        plan = Plan(L, len(q), 1e-4, method=1, nf=n, local=1)
+        _, F, _ = run(plan, pos, q)
+        plan.close()
+        d = rel_rms(F, F_e)
+        print(f"classical water9k n={n}: Delta={d:.2e}")
+        if d <= 1e-4:
+            first = n
+            break
+    assert first == bench.CLASSICAL_GRID_WATER9K
+    esp = Plan(L, len(q), 1e-4, local=1)
+    _, F, _ = run(esp, pos, q)
+    print(f"ESP water9k n={esp.params[0].nf}: Delta={rel_rms(F, F_e):.2e}")
+    assert rel_rms(F, F_e) <= 1e-4
+    esp.close()
+
+
 def test_classical_and_esp_share_a_batch():
     systems = [W.water_box_at_density(3 * (400 + 150 * i), seed=300 + i) for i in range(6)]
     Ls = [s[2] for s in systems]

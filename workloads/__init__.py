@@ -102,6 +102,31 @@ def water_box(n_mol: int, L, seed: int):
     return wrap(pos.reshape(-1, 3), L), q
 
 
+def water_cell(n_mol: int, H, seed: int):
+    """n_mol rigid three-site waters in the triclinic cell whose lattice vectors
+    are the columns of H: O positions H s with s uniform in [0,1)^3, uniform
+    random orientations, atoms left unwrapped (a hydrogen may sit just
+    outside the cell). Atom order per molecule: O, H, H.
+    Returns (pos[3*n_mol,3], q[3*n_mol])."""
+    rng = _rng(seed)
+    o = rng.random((n_mol, 3)) @ np.asarray(H, np.float64).T
+    half = math.radians(THETA_HOH_DEG) / 2
+    body = np.array([[0.0, 0.0, 0.0],
+                     [math.sin(half), math.cos(half), 0.0],
+                     [-math.sin(half), math.cos(half), 0.0]]) * R_OH
+    R = _random_rotations(rng, n_mol)
+    pos = o[:, None, :] + np.einsum("mij,aj->mai", R, body)
+    return pos.reshape(-1, 3), np.tile(np.array([Q_O, Q_H, Q_H]), n_mol)
+
+
+def rhombic_dodecahedron(volume: float):
+    """Cell matrix (lattice vectors as columns) of the rhombic dodecahedron with
+    a square xy face, a = (d, 0, 0), b = (0, d, 0), c = (d/2, d/2, d/sqrt 2),
+    of the given volume (d^3 / sqrt 2)."""
+    d = (volume * math.sqrt(2.0)) ** (1.0 / 3.0)
+    return np.array([[d, 0.0, d / 2], [0.0, d, d / 2], [0.0, 0.0, d / math.sqrt(2.0)]])
+
+
 def water_box_at_density(n_atoms: int, seed: int, density=WATER_MOLECULES_PER_A3):
     """Water box of n_atoms (a multiple of 3) at the given molecule density."""
     n_mol = n_atoms // 3
