@@ -368,8 +368,16 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
         __syncthreads();
     }
     const int nown = roff[a * a];
+    const int span = 2 * LR + 1, nrun = span * span;
+    // lanes per own particle: a block with few own particles (coarse sub-cells,
+    // as in strongly tilted cells) splits each particle's stencil rows over NL
+    // adjacent lanes and adds their partial sums in a fixed butterfly order
+    int NL = 1;
+    if (staged)
+        while (NL < 16 && 2 * NL <= nrun && 2 * NL * nown <= (int)blockDim.x) NL *= 2;
+    const int gl = threadIdx.x & (NL - 1);
     double e = 0.0;
-    for (int k = threadIdx.x; k < nown; k += blockDim.x) {
+    for (int k = threadIdx.x / NL; k < nown; k += blockDim.x / NL) {
         int lo = 0, hi = a * a;  // run r with roff[r] <= k < roff[r + 1]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -390,29 +398,28 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
             // halo rows hx .. hx + 2 lR around halo row hx + lR of the particle
             const int hx = min(max(lx - ox, 0), a - 1), hy = min(max(ly - oy, 0), a - 1),
                       hz = min(max(lz - oz, 0), a - 1);
-            for (int u = 0; u <= 2 * LR; ++u) {
-                for (int v = 0; v <= 2 * LR; ++v) {
-                    const int row = ((hx + u) * W + (hy + v)) * W + hz;
-                    const int ja = hs[row], jb = hs[row + 2 * LR + 1];
-                    // four candidates loaded before any is used: the LDS
-                    // latency overlaps instead of stalling every pair
-                    int j = ja;
-                    for (; j + 3 < jb; j += 4) {
-                        const V v0 = hp[j], v1 = hp[j + 1], v2 = hp[j + 2], v3 = hp[j + 3];
-                        pair_term<R, D>(vix - v0.x, viy - v0.y, viz - v0.z, v0.w, rho2, inv_rho2, cA, cB, up, fx,
-                                        fy, fz);
-                        pair_term<R, D>(vix - v1.x, viy - v1.y, viz - v1.z, v1.w, rho2, inv_rho2, cA, cB, up, fx,
-                                        fy, fz);
-                        pair_term<R, D>(vix - v2.x, viy - v2.y, viz - v2.z, v2.w, rho2, inv_rho2, cA, cB, up, fx,
-                                        fy, fz);
-                        pair_term<R, D>(vix - v3.x, viy - v3.y, viz - v3.z, v3.w, rho2, inv_rho2, cA, cB, up, fx,
-                                        fy, fz);
-                    }
-                    for (; j < jb; ++j) {
-                        const V vj = hp[j];
-                        pair_term<R, D>(vix - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
-                                        fy, fz);
-                    }
+            for (int rr = gl; rr < nrun; rr += NL) {
+                const int u = rr / span, v = rr - u * span;
+                const int row = ((hx + u) * W + (hy + v)) * W + hz;
+                const int ja = hs[row], jb = hs[row + 2 * LR + 1];
+                // four candidates loaded before any is used: the LDS
+                // latency overlaps instead of stalling every pair
+                int j = ja;
+                for (; j + 3 < jb; j += 4) {
+                    const V v0 = hp[j], v1 = hp[j + 1], v2 = hp[j + 2], v3 = hp[j + 3];
+                    pair_term<R, D>(vix - v0.x, viy - v0.y, viz - v0.z, v0.w, rho2, inv_rho2, cA, cB, up, fx,
+                                    fy, fz);
+                    pair_term<R, D>(vix - v1.x, viy - v1.y, viz - v1.z, v1.w, rho2, inv_rho2, cA, cB, up, fx,
+                                    fy, fz);
+                    pair_term<R, D>(vix - v2.x, viy - v2.y, viz - v2.z, v2.w, rho2, inv_rho2, cA, cB, up, fx,
+                                    fy, fz);
+                    pair_term<R, D>(vix - v3.x, viy - v3.y, viz - v3.z, v3.w, rho2, inv_rho2, cA, cB, up, fx,
+                                    fy, fz);
+                }
+                for (; j < jb; ++j) {
+                    const V vj = hp[j];
+                    pair_term<R, D>(vix - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
+                                    fy, fz);
                 }
             }
         } else {
@@ -467,15 +474,23 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                 }
             }
         }
-        const R pot = up * sc;
-        const R fq = vi.w * sc * sc;
-        V o;
-        o.x = pot;
-        o.y = fq * fx;
-        o.z = fq * fy;
-        o.w = fq * fz;
-        loc[S.cidx[gi]] = o;
-        e += (double)vi.w * (double)pot;
+        for (int off = NL >> 1; off > 0; off >>= 1) {  // the lanes of a group are all active
+            up += __shfl_xor(up, off, 64);
+            fx += __shfl_xor(fx, off, 64);
+            fy += __shfl_xor(fy, off, 64);
+            fz += __shfl_xor(fz, off, 64);
+        }
+        if (gl == 0) {
+            const R pot = up * sc;
+            const R fq = vi.w * sc * sc;
+            V o;
+            o.x = pot;
+            o.y = fq * fx;
+            o.z = fq * fy;
+            o.w = fq * fz;
+            loc[S.cidx[gi]] = o;
+            e += (double)vi.w * (double)pot;
+        }
     }
     e = block_sum(e, red);
     if (threadIdx.x == 0) lpart[blockIdx.x] = e;

@@ -284,12 +284,15 @@ def test_large_water_full_coulomb_sampled():
     assert (p.nf, p.P) == (96, 8)
     phi, F, E = run(plan, pos, q)
     plan.close()
+    bad = np.flatnonzero(~(np.isfinite(phi) & np.isfinite(F).all(1)))
+    assert len(bad) == 0 and np.isfinite(E[0]), f"device output not finite at {len(bad)} particles: {bad[:8]}, E={E}"
     pr = pos.astype(np.float32).astype(np.float64)
     r = five_step(pr, q, L, p.nf, p.P, p.c, p.rc, p.c1)
     idx = np.random.default_rng(3).choice(len(q), 2000, replace=False)
     ul, gl = local_sum(pr, q, L, PSWFSplit(p.c, p.rc), targets=idx)
     F_r = r["F"][idx] - q[idx, None] * gl
     phi_r = r["phi"][idx] + ul
+    assert np.isfinite(F_r).all() and np.isfinite(phi_r).all(), "reference not finite"
     eF, ephi = rel_rms(F[idx], F_r), rel_rms(phi[idx], phi_r)
     # molecules placed at random at three times liquid density leave some
     # atoms of different molecules a few hundredths of an angstrom apart; the
