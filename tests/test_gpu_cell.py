@@ -150,3 +150,44 @@ def test_rhombic_dodecahedron_water9k_sampled():
     delta = rel_rms(F[idx], F_e)
     print(f"rhombic dodecahedron N={len(q)} n={p.nf}: relF={eF:.2e} relphi={ephi:.2e} Delta(sampled)={delta:.2e}")
     assert eF < 1e-5 and ephi < 1e-5 and delta < 1e-4
+
+
+def test_graph_replay_and_autotune_in_a_tilted_cell():
+    # re-assembly (autotuned bin edges) keeps the per-system influence table;
+    # graph replays equal the eager call
+    cell = CELLS[1]
+    pos, q = random_cell(cell, seed=21)
+    plan = Plan(cell, len(q), 1e-4, local=1)
+    eager = run(plan, pos, q)
+    tp = torch.tensor(pos, dtype=torch.float32, device=DEV)
+    tq = torch.tensor(q, dtype=torch.float32, device=DEV)
+    phi = torch.empty(len(q), dtype=torch.float32, device=DEV)
+    F = torch.empty((len(q), 3), dtype=torch.float32, device=DEV)
+    plan.autotune(tp, tq, phi, F, reps=2)
+    tuned = run(plan, pos, q)
+    plan.set_graph(True)
+    for _ in range(3):
+        plan.longrange(tp, tq, phi, F)
+        torch.cuda.synchronize()
+        assert np.array_equal(F.cpu().double().numpy(), tuned[1])
+        run(plan, pos, q)  # eager work between replays
+    plan.close()
+    assert rel_rms(tuned[1], eager[1]) < 1e-6 and rel_rms(tuned[0], eager[0]) < 1e-6
+
+
+@pytest.mark.parametrize("cell,n_atoms", [((12.0, 13.0, 14.0, 9.0, -7.0, 8.0), 3), ((20.0, 18.0, 16.0, 14.0, 0.0, -11.0), 300)])
+def test_small_and_non_reduced_cells(cell, n_atoms):
+    # tilts beyond half a side (a non-reduced cell) and a three-atom system
+    H = cell_matrix(*cell)
+    rng = np.random.default_rng(17)
+    pos = rng.uniform(0, 1, (n_atoms, 3)) @ H.T
+    q = np.tile([W.Q_O, W.Q_H, W.Q_H], n_atoms // 3)
+    # degree 16: the window polynomials exact to FP64 (the default degree fits
+    # them to the tolerance, about 1e-5)
+    plan = Plan(cell, len(q), 1e-4, precision=64, local=0, degree=16)
+    phi, F, E = run(plan, pos, q)
+    p = plan.params[0]
+    plan.close()
+    phi_r, F_r, E_r = reference(pos, q, p, 0)
+    print(f"cell {cell} N={n_atoms} n={p.nf}: relF={rel_rms(F, F_r):.2e}")
+    assert rel_rms(F, F_r) < 1e-9 and rel_rms(phi, phi_r) < 1e-9
