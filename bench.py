@@ -631,8 +631,8 @@ def main():
                           "launches": 10}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py measures one GPU; sharding across GPUs is designed but not "
+                                   "implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
