@@ -23,7 +23,7 @@ import math
 import numpy as np
 from scipy.special import erfc
 
-from .fivestep import dft3, interpolate, phi_hat_1d, spread
+from .fivestep import dft3, ik_factors, interpolate, phi_hat_1d, spread
 from .split import L_and_dL, PSWFSplit, S_hat
 
 
@@ -176,3 +176,26 @@ def five_step_cell(pos, q, H, n, P, c, rc, c1):
     phi = ut - q * s0
     F = -q[:, None] * grad
     return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=0.5 * float(np.dot(q, phi)), s0=s0)
+
+
+def five_step_cell_ik(pos, q, H, n, P, c, rc, c1):
+    """Five-step method in a triclinic cell with forces by the "ik" route
+    (Methods, force paragraph): the derivative of the potential along each
+    fractional coordinate is the inverse transform of p b^ times -2 pi i m_d
+    (0 at the Nyquist index), interpolated with the window itself; forces are
+    F_i = -q_i H^-T grad_s. Potentials and energy are those of five_step_cell."""
+    base = five_step_cell(pos, q, H, n, P, c, rc, c1)
+    H = np.asarray(H, np.float64)
+    Hinv = np.linalg.inv(H)
+    frac = np.mod(np.asarray(pos, np.float64) @ Hinv.T, 1.0)
+    chat = base["p"] * base["bhat"]
+    d = ik_factors(n, 1.0)  # derivative along a fractional coordinate
+    gs = np.zeros((len(q), 3))
+    for ax in range(3):
+        shape = [1, 1, 1]
+        shape[ax] = n
+        g = np.real(dft3(chat * d.reshape(shape), -1))
+        gs[:, ax], _ = interpolate(frac, 1.0, n, P, c1, g)
+    out = dict(base)
+    out["F"] = -np.asarray(q, np.float64)[:, None] * (gs @ Hinv)
+    return out

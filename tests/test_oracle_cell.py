@@ -10,7 +10,8 @@ import pytest
 
 import workloads as W
 from oracle.box import ewald_box, five_step_box, local_sum_box
-from oracle.cell import cell_matrix, ewald_cell, five_step_cell, influence_cell, local_sum_cell, plane_spacings
+from oracle.cell import (cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, influence_cell,
+                         local_sum_cell, plane_spacings)
 from oracle.metrics import rel_rms
 from oracle.params import esp_parameters
 from oracle.split import PSWFSplit
@@ -105,3 +106,29 @@ def test_influence_is_even_on_the_index_grid():
     pb = influence_box(n, (16.0, 15.0, 14.0), 6, 12.024, 4.0, 12.5)
     pc = influence_cell(n, cell_matrix(16.0, 15.0, 14.0), 6, 12.024, 4.0, 12.5)
     assert np.max(np.abs(pc - pb)) < 1e-10 * np.max(np.abs(pb))
+
+
+
+def test_ik_forces_in_a_cell():
+    # a cubic cell reproduces the cubic ik route, which is built on Cartesian
+    # derivatives instead of fractional ones
+    from oracle.fivestep import five_step_ik
+    L, n, P, c, rc, c1 = 14.0, 16, 6, 12.024, 4.5, 12.5
+    pos, q = W.water_box(120, L, seed=4)
+    a = five_step_ik(pos, q, L, n, P, c, rc, c1)
+    b = five_step_cell_ik(pos, q, cell_matrix(L, L, L), n, P, c, rc, c1)
+    assert rel_rms(b["F"], a["F"]) < 1e-12
+    # a tilted cell: momentum conserved exactly, Delta against Ewald within
+    # the tolerance, and agreement with the analytic-derivative forces
+    H = cell_matrix(20.0, 19.0, 18.0, 3.0, -2.0, 4.0)
+    N = 3 * int(0.03 * abs(np.linalg.det(H)) / 3)
+    pos, q = _random_charges(H, N, 7)
+    pr = esp_parameters(float(np.linalg.norm(H, axis=0).max()), 1e-4)
+    n, P, c, rc, c1 = pr["n"], pr["P"], pr["c"], pr["rc"], pr["c1"]
+    r = five_step_cell_ik(pos, q, H, n, P, c, rc, c1)
+    ad = five_step_cell(pos, q, H, n, P, c, rc, c1)
+    assert np.abs(r["F"].sum(0)).max() < 1e-12 * np.abs(r["F"]).max() * N
+    ul, gl = local_sum_cell(pos, q, H, PSWFSplit(c, rc))
+    _, F_e, _ = ewald_cell(pos, q, H)
+    assert rel_rms(r["F"] - q[:, None] * gl, F_e) < 1e-4
+    assert rel_rms(r["F"], ad["F"]) < 1e-3
