@@ -125,9 +125,10 @@ typedef struct {
                              s = H^-1 r (grid point l at H l / nf); nf and the default rc
                              follow the longest lattice vector, and the local part needs
                              rc at most half the smallest distance between lattice
-                             planes. Forces F = -q H^-T grad_s. Supported with method 0
-                             and force_method 0 (ESP_E_UNSUPPORTED otherwise). Positions
-                             may lie anywhere (each is wrapped into the cell). */
+                             planes. Forces F = -q H^-T grad_s, by either force_method
+                             (ik: derivatives along the fractional coordinates). Method 0
+                             only (ESP_E_UNSUPPORTED for method 1). Positions may lie
+                             anywhere (each is wrapped into the cell). */
 } esp_params;
 
 typedef struct esp_plan esp_plan;

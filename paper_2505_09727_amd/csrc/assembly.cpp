@@ -282,6 +282,10 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             d.mxy = r.xy / r.L;
             d.mxz = r.xz / r.L;
             d.myz = r.yz / r.L;
+            const bool tilt = tilted(r);
+            d.ikx = tilt ? 1.0 : d.inv_L;
+            d.iky = tilt ? 1.0 : d.inv_Ly;
+            d.ikz = tilt ? 1.0 : d.inv_Lz;
         }
         d.p3 = sl.scr.p3;
         d.pscale = r.nf / r.L;

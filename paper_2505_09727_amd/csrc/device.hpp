@@ -41,6 +41,10 @@ struct SysDesc {
     // H / L (a grid-unit displacement in units of h_x = L/n); 0 otherwise
     double ixy, ixz, iyz;
     double mxy, mxz, myz;
+    // ik: scale of the spectral derivative along each index axis, 1/L_d in a
+    // box (Cartesian derivatives), 1 in a tilted cell (derivatives along the
+    // fractional coordinates, mapped to Cartesian ones by H^-T in the gather)
+    double ikx, iky, ikz;
     double s0;        // self constant S(0) of this box
     double pscale;    // influence scale: tables are made for a box of side n, p ~ 1/L
     double wmax3;     // cube of the window's peak value (fixed-point range)

@@ -309,9 +309,9 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __
     if (S.ik) {  // uniform over the block
         R* g = reinterpret_cast<R*>(S.grad);
         const long long G = (long long)N * N * RL;
-        inv_yz_plane<R, N, BD>(buf, tw, plane, g + G + off, 2, R(S.inv_Ly));
+        inv_yz_plane<R, N, BD>(buf, tw, plane, g + G + off, 2, R(S.iky));
         __syncthreads();
-        inv_yz_plane<R, N, BD>(buf, tw, plane, g + 2 * G + off, 3, R(S.inv_Lz));
+        inv_yz_plane<R, N, BD>(buf, tw, plane, g + 2 * G + off, 3, R(S.ikz));
         __syncthreads();
         inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, R(0));
         __syncthreads();
@@ -373,7 +373,7 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
             const cplx<R> cb = {b.x * p, b.y * p};
             buf[idx] = cb;
             if (ik) {
-                const R d = ik_factor<R, N>(x, R(S.inv_L));
+                const R d = ik_factor<R, N>(x, R(S.ikx));
                 bufx[idx] = {-cb.y * d, cb.x * d};
             }
         }

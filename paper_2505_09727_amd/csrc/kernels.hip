@@ -625,7 +625,10 @@ __device__ __forceinline__ void load_tile(R* __restrict__ lds, const R* __restri
 // Gather with ik forces (Methods, force paragraph): four passes over the
 // bin's particles, each interpolating one grid with the window itself:
 // the potential (phi_i = u~_i - q_i S(0)) and the three gradient grids
-// (F_i = -q_i times the interpolated gradient, physical units).
+// (F_i = -q_i times the interpolated gradient). In a box the grids hold
+// Cartesian derivatives; in a tilted cell they hold derivatives g_d along the
+// fractional coordinates and F = -q H^-T g, accumulated over the passes (H^-1
+// upper triangular: pass d adds to components d and beyond).
 template <typename R, int P>
 __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __restrict__ ct, int ox, int oy, int oz,
                           int beg, int end) {
@@ -635,6 +638,9 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __rest
     R* phi = reinterpret_cast<R*>(S.phi);
     R* F = reinterpret_cast<R*>(S.F);
     const R s0 = R(S.s0);
+    const bool tilt = S.ixy != 0.0 || S.ixz != 0.0 || S.iyz != 0.0;  // uniform
+    // column pass - 1 of H^-T: the factors of g_{pass-1} in F_x, F_y, F_z
+    const R hinv[3][3] = {{R(S.inv_L), R(S.ixy), R(S.ixz)}, {R(0), R(S.inv_Ly), R(S.iyz)}, {R(0), R(0), R(S.inv_Lz)}};
     for (int pass = 0; pass < 4; ++pass) {
         if (pass == 0 && !phi) continue;
         if (pass > 0 && !F) break;
@@ -666,10 +672,18 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __rest
             const int o = S.perm[k];
             R l = 0;  // local part (k_local), component `pass`
             if (S.local) l = reinterpret_cast<const R*>(S.loc)[4LL * k + pass];
-            if (pass == 0)
+            if (pass == 0) {
                 phi[o] = u - v.w * s0 + l;
-            else
+            } else if (!tilt) {
                 F[3LL * o + (pass - 1)] = -v.w * u + l;
+            } else {
+                // the same thread owns particle k in every pass
+                const int d = pass - 1;
+                for (int j = d; j < 3; ++j) {
+                    const R t = -v.w * (hinv[d][j] * u) + (j == d ? l : R(0));
+                    F[3LL * o + j] = d == 0 ? t : F[3LL * o + j] + t;
+                }
+            }
         }
     }
 }

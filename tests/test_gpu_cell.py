@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle.cell import cell_matrix, ewald_cell, five_step_cell, local_sum_cell
+from oracle.cell import cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, local_sum_cell
 from oracle.metrics import rel_rms
 from oracle.split import PSWFSplit
 
@@ -191,3 +191,44 @@ def test_small_and_non_reduced_cells(cell, n_atoms):
     phi_r, F_r, E_r = reference(pos, q, p, 0)
     print(f"cell {cell} N={n_atoms} n={p.nf}: relF={rel_rms(F, F_r):.2e}")
     assert rel_rms(F, F_r) < 1e-9 and rel_rms(phi, phi_r) < 1e-9
+
+
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("prec,bar_F", [(64, 1e-9), (32, 1e-5)])
+def test_ik_forces_in_a_tilted_cell(cell, prec, bar_F):
+    # spectral derivatives along the fractional coordinates, mapped by H^-T,
+    # against the reference ik route; with the local part against Ewald
+    pos, q = random_cell(cell, seed=31)
+    plan = Plan(cell, len(q), 1e-4, precision=prec, local=1, force_method=1, degree=16 if prec == 64 else None)
+    p = plan.params[0]
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    H = cell_matrix(*cell)
+    pr = pos if prec == 64 else pos.astype(np.float32).astype(np.float64)
+    r = five_step_cell_ik(pr, q, H, p.nf, p.P, p.c, p.rc, p.c1)
+    ul, gl = local_sum_cell(pr, q, H, PSWFSplit(p.c, p.rc))
+    F_r, phi_r = r["F"] - q[:, None] * gl, r["phi"] + ul
+    eF, ephi = rel_rms(F, F_r), rel_rms(phi, phi_r)
+    _, F_e, _ = ewald_cell(pr, q, H)
+    print(f"ik cell {cell} prec={prec}: relF={eF:.2e} relphi={ephi:.2e} Delta={rel_rms(F, F_e):.2e}")
+    assert eF < bar_F and ephi < bar_F and rel_rms(F, F_e) < 1e-4
+    # the long-range ik forces conserve momentum; the local part does by symmetry
+    assert np.abs(F.sum(0)).max() < (1e-10 if prec == 64 else 1e-4) * np.abs(F).max() * len(q)
+
+
+def test_ik_batch_of_tilted_and_box_systems_equals_each_alone():
+    cells = [CELLS[0], (18.0, 21.0, 24.0, 0.0, 0.0, 0.0), CELLS[1]]
+    systems = [random_cell(c, seed=70 + i) for i, c in enumerate(cells)]
+    Ns = [len(s[1]) for s in systems]
+    off = np.cumsum([0] + Ns)
+    per = [{"Ly": c[1], "Lz": c[2], "xy": c[3], "xz": c[4], "yz": c[5], "force_method": 1} for c in cells]
+    batch = Plan([c[0] for c in cells], Ns, 1e-4, per_system=per)
+    phi_b, F_b, E_b = run(batch, np.concatenate([s[0] for s in systems]), np.concatenate([s[1] for s in systems]))
+    batch.close()
+    for i, c in enumerate(cells):
+        single = Plan(c, Ns[i], 1e-4, force_method=1)
+        phi_s, F_s, E_s = run(single, systems[i][0], systems[i][1])
+        single.close()
+        sl = slice(off[i], off[i + 1])
+        assert np.array_equal(F_s, F_b[sl]) and np.array_equal(phi_s, phi_b[sl]) and E_s[0] == E_b[i], i
