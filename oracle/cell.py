@@ -24,7 +24,8 @@ import numpy as np
 from scipy.special import erfc
 
 from .fivestep import dft3, ik_factors, interpolate, phi_hat_1d, spread
-from .split import L_and_dL, PSWFSplit, S_hat
+from . import classical
+from .split import GaussianSplit, L_and_dL, PSWFSplit, S_hat
 
 
 def cell_matrix(Lx, Ly, Lz, xy=0.0, xz=0.0, yz=0.0):
@@ -129,8 +130,10 @@ def local_sum_cell(pos, q, H, split, targets=None, chunk=128):
     return u, g
 
 
-def influence_cell(n, H, P, c, rc, c1):
-    """p_m on the full n^3 index grid (index k in [0, n): m = k or k - n).
+def _influence_on_index_grid(n, H, split, f):
+    """p_m = S^(|k|)/V / prod_d f_d^2 on the full n^3 index grid (index k in
+    [0, n): m = k or k - n), k = 2 pi H^-T m, f the window's transform in grid
+    units per axis (an array over the index).
 
     Reading: in a tilted cell p depends on the signs of m, and an index at the
     Nyquist frequency n/2 stands for both signs; p there is the mean over the
@@ -140,10 +143,8 @@ def influence_cell(n, H, P, c, rc, c1):
     H = np.asarray(H, np.float64)
     Hinv = np.linalg.inv(H)
     V = abs(np.linalg.det(H))
-    split = PSWFSplit(c, rc)
     kk = np.arange(n)
     m = np.where(kk < n // 2, kk, kk - n).astype(np.float64)
-    f = phi_hat_1d(2 * math.pi * m / n, P, 1.0, c1)  # window transform in grid units
     M = np.array(np.meshgrid(m, m, m, indexing="ij"))  # 3 x n x n x n
     nyq = np.abs(M) == n // 2
     acc = np.zeros((n, n, n))
@@ -157,6 +158,15 @@ def influence_cell(n, H, P, c, rc, c1):
     p = S / V / (f[:, None, None] * f[None, :, None] * f[None, None, :]) ** 2
     p[0, 0, 0] = 0.0
     return p
+
+
+def influence_cell(n, H, P, c, rc, c1):
+    """ESP influence function on the index grid of a cell (eq. pk with V/n^3
+    per grid point): PSWF splitting kernel, PSWF window."""
+    kk = np.arange(n)
+    m = np.where(kk < n // 2, kk, kk - n).astype(np.float64)
+    f = phi_hat_1d(2 * math.pi * m / n, P, 1.0, c1)  # window transform in grid units
+    return _influence_on_index_grid(n, H, PSWFSplit(c, rc), f)
 
 
 def five_step_cell(pos, q, H, n, P, c, rc, c1):
@@ -199,3 +209,26 @@ def five_step_cell_ik(pos, q, H, n, P, c, rc, c1):
     out = dict(base)
     out["F"] = -np.asarray(q, np.float64)[:, None] * (gs @ Hinv)
     return out
+
+
+def five_step_classical_cell(pos, q, H, n, P, alpha, rc):
+    """The classical method (Gaussian split, cardinal B-spline window of order
+    P; Methods, classical fast Ewald methods) in a triclinic cell, on the same
+    fractional grid as five_step_cell."""
+    pos = np.asarray(pos, np.float64)
+    q = np.asarray(q, np.float64)
+    H = np.asarray(H, np.float64)
+    Hinv = np.linalg.inv(H)
+    frac = np.mod(pos @ Hinv.T, 1.0)
+    b = classical.spread(frac, q, 1.0, n, P)
+    bhat = dft3(b, +1)
+    kk = np.arange(n)
+    m = np.where(kk < n // 2, kk, kk - n).astype(np.float64)
+    f = classical.phi_hat_1d(2 * math.pi * m / n, P, 1.0)  # h sinc^P in grid units
+    p = _influence_on_index_grid(n, H, GaussianSplit(alpha, rc), f)
+    cgrid = np.real(dft3(p * bhat, -1))
+    ut, g_frac = classical.interpolate(frac, 1.0, n, P, cgrid)
+    s0 = GaussianSplit(alpha, rc).S0()
+    phi = ut - q * s0
+    F = -q[:, None] * (g_frac @ Hinv)
+    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=0.5 * float(np.dot(q, phi)), s0=s0)

@@ -10,8 +10,8 @@ import pytest
 
 import workloads as W
 from oracle.box import ewald_box, five_step_box, local_sum_box
-from oracle.cell import (cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, influence_cell,
-                         local_sum_cell, plane_spacings)
+from oracle.cell import (cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, five_step_classical_cell,
+                         influence_cell, local_sum_cell, plane_spacings)
 from oracle.metrics import rel_rms
 from oracle.params import esp_parameters
 from oracle.split import PSWFSplit
@@ -132,3 +132,29 @@ def test_ik_forces_in_a_cell():
     _, F_e, _ = ewald_cell(pos, q, H)
     assert rel_rms(r["F"] - q[:, None] * gl, F_e) < 1e-4
     assert rel_rms(r["F"], ad["F"]) < 1e-3
+
+
+
+def test_classical_method_in_a_cell():
+    # a cubic cell reproduces the cubic classical reference
+    from oracle.classical import five_step_classical
+    from oracle.split import GaussianSplit
+    L = 14.0
+    pos, q = W.water_box(120, L, seed=4)
+    alpha, rc, n, P = math.log(1e4), 4.5, 24, 6
+    a = five_step_classical(pos, q, L, n, P, alpha, rc)
+    b = five_step_classical_cell(pos, q, cell_matrix(L, L, L), n, P, alpha, rc)
+    assert rel_rms(b["F"], a["F"]) < 1e-12 and abs(b["E"] - a["E"]) < 1e-12 * abs(a["E"])
+    # a tilted cell: Delta against triclinic Ewald falls with the grid and
+    # settles at the split's own error (alpha = log 1e4: about 1.2e-5)
+    H = cell_matrix(20.0, 19.0, 18.0, 3.0, -2.0, 4.0)
+    N = 3 * int(0.03 * abs(np.linalg.det(H)) / 3)
+    pos, q = _random_charges(H, N, 7)
+    _, F_e, _ = ewald_cell(pos, q, H)
+    rc = 5.0
+    ul, gl = local_sum_cell(pos, q, H, GaussianSplit(alpha, rc, support=rc))
+    deltas = []
+    for n, P in ((24, 5), (32, 5), (48, 8)):
+        r = five_step_classical_cell(pos, q, H, n, P, alpha, rc)
+        deltas.append(rel_rms(r["F"] - q[:, None] * gl, F_e))
+    assert deltas[0] > deltas[1] > deltas[2] and deltas[2] < 3e-5
