@@ -126,9 +126,9 @@ typedef struct {
                              follow the longest lattice vector, and the local part needs
                              rc at most half the smallest distance between lattice
                              planes. Forces F = -q H^-T grad_s, by either force_method
-                             (ik: derivatives along the fractional coordinates). Method 0
-                             only (ESP_E_UNSUPPORTED for method 1). Positions may lie
-                             anywhere (each is wrapped into the cell). */
+                             (ik: derivatives along the fractional coordinates) and with
+                             either method. Positions may lie anywhere (each is wrapped
+                             into the cell). */
 } esp_params;
 
 typedef struct esp_plan esp_plan;

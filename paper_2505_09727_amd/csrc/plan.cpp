@@ -384,10 +384,6 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
         msg = "cell tilts must be finite";
         return ESP_E_INVALID;
     }
-    if (tilted(r) && r.method != 0) {
-        msg = "a triclinic cell is supported by the ESP method (method 0) only";
-        return ESP_E_UNSUPPORTED;
-    }
     // the longest lattice vector sets the grid and the cutoff (the resolved
     // modes |m_d| <= n/2 then hold the sphere |k| <= pi n / Lmax); nearest
     // images need rc at most half the smallest lattice-plane spacing

@@ -68,7 +68,7 @@ int main() {
     }
     run_case(20.0, 18.0, 16.0, 14.0, 0.0, -11.0, 0, 0, 1e-4, true);
     run_case(14.0, 14.0, 14.0, 13.0, 0.0, 0.0, 0, 1, 1e-4, false);  // rc beyond half a plane spacing
-    run_case(16.0, 15.0, 14.0, 1.0, 0.0, 0.0, 1, 0, 1e-4, false);   // classical method in a tilted cell
+    run_case(16.0, 15.0, 14.0, 1.0, 0.0, 0.0, 1, 1, 1e-4, true);    // classical method in a tilted cell
     run_case(10.0, -1.0, 10.0, 0, 0, 0, 0, 0, 1e-4, false);         // negative side
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "ok", failures);
     return failures ? 1 : 0;

@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle.cell import cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, local_sum_cell
+from oracle.cell import (cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, five_step_classical_cell,
+                         local_sum_cell)
 from oracle.metrics import rel_rms
 from oracle.split import PSWFSplit
 
@@ -232,3 +233,33 @@ def test_ik_batch_of_tilted_and_box_systems_equals_each_alone():
         single.close()
         sl = slice(off[i], off[i + 1])
         assert np.array_equal(F_s, F_b[sl]) and np.array_equal(phi_s, phi_b[sl]) and E_s[0] == E_b[i], i
+
+
+
+@pytest.mark.parametrize("cell", CELLS)
+@pytest.mark.parametrize("prec,bar_F", [(64, 1e-10), (32, 1e-5)])
+@pytest.mark.parametrize("local", [0, 1])
+def test_classical_method_in_a_tilted_cell(cell, prec, bar_F, local):
+    # Gaussian split and B-spline window on the fractional grid, at the
+    # library's classical defaults (P = 5, alpha = log(1/tol), the ESP cutoff)
+    from oracle.split import GaussianSplit
+    pos, q = random_cell(cell, seed=41)
+    plan = Plan(cell, len(q), 1e-4, precision=prec, local=local, method=1)
+    p = plan.params[0]
+    assert p.method == 1
+    phi, F, E = run(plan, pos, q)
+    plan.close()
+    H = cell_matrix(*cell)
+    pr = pos if prec == 64 else pos.astype(np.float32).astype(np.float64)
+    r = five_step_classical_cell(pr, q, H, p.nf, p.P, p.c, p.rc)
+    phi_r, F_r = r["phi"], r["F"]
+    if local:
+        ul, gl = local_sum_cell(pr, q, H, GaussianSplit(p.c, p.rc, support=p.rc))
+        phi_r, F_r = phi_r + ul, F_r - q[:, None] * gl
+    eF, ephi = rel_rms(F, F_r), rel_rms(phi, phi_r)
+    msg = f"classical cell {cell} n={p.nf} P={p.P} prec={prec} local={local}: relF={eF:.2e} relphi={ephi:.2e}"
+    if local:
+        _, F_e, _ = ewald_cell(pr, q, H)
+        msg += f" Delta={rel_rms(F, F_e):.2e}"
+    print(msg)
+    assert eF < bar_F and ephi < bar_F
