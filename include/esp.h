@@ -135,8 +135,9 @@ typedef struct esp_plan esp_plan;
 
 /* ---- host-only queries (no device use; safe on machines without a GPU) ---- */
 
-/* Resolve parameters for a box of sides box[0..2] (cubic or orthorhombic), N
- * particles and tolerance tol in [1e-8, 1e-2]. req may be NULL. */
+/* Resolve parameters for a box of sides box[0..2] (cubic or orthorhombic, or
+ * a triclinic cell with req->xy, xz, yz), N particles and tolerance tol in
+ * [1e-8, 1e-2]. req may be NULL. */
 esp_status esp_plan_query(const double box[3], int64_t N, double tol,
                           const esp_params* req, esp_params* out);
 
@@ -148,9 +149,12 @@ esp_status esp_plan_query(const double box[3], int64_t N, double tol,
  * psi_0^{c1}(2 (u - l0 - j)/P). coef must hold P*(degree+1) doubles. */
 esp_status esp_window_coeffs(const esp_params* resolved, double* coef);
 
-/* Influence function in factored form (eq. pk): for Fourier index m in
- * [-nf/2, nf/2)^3,  p_m = TS[mx^2+my^2+mz^2] * Tphi[|mx|] Tphi[|my|] Tphi[|mz|].
- * TS holds 3*(nf/2)^2 + 1 doubles (TS[0] = 0), Tphi holds nf/2 + 1 doubles. */
+/* Influence function in factored form (eq. pk) of a cubic box: for Fourier
+ * index m in [-nf/2, nf/2)^3,
+ *   p_m = TS[mx^2+my^2+mz^2] * Tphi[|mx|] Tphi[|my|] Tphi[|mz|].
+ * TS holds 3*(nf/2)^2 + 1 doubles (TS[0] = 0), Tphi holds nf/2 + 1 doubles.
+ * Non-cubic boxes and cells use a per-system table built on the host at plan
+ * creation; Tphi is still their per-axis factor. */
 esp_status esp_influence_tables(const esp_params* resolved, double* TS, double* Tphi);
 
 /* Local kernel of the split (eq. kernelsplitting), for pairing with a
@@ -178,12 +182,14 @@ esp_status esp_warm_tables(const double* tols, int ntol, int nf_max, int threads
 
 /* ---- single-system plans ---- */
 
+/* box[0..2]: the sides L, Ly, Lz (all equal for a cubic box); a triclinic
+ * cell adds its tilts through req->xy, xz, yz. */
 esp_status esp_plan_create(const double box[3], int64_t N, double tol, esp_plan** out);
 esp_status esp_plan_create_ex(const double box[3], int64_t N, double tol,
                               const esp_params* req, esp_plan** out);
 
 /* Batched plan: nsys independent systems of sides L[s] (with reqs[s].Ly, Lz for
- * orthorhombic ones), N[s] particles and
+ * orthorhombic ones and reqs[s].xy, xz, yz for triclinic ones), N[s] particles and
  * tolerances tol[s]; req (may be NULL) applies to every system, or reqs[s]
  * (may be NULL) per system. One call evaluates all systems with one launch per
  * pipeline phase (systems grouped by window width P). */
