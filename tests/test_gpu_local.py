@@ -292,7 +292,9 @@ def test_large_water_full_coulomb_sampled():
     ul, gl = local_sum(pr, q, L, PSWFSplit(p.c, p.rc), targets=idx)
     F_r = r["F"][idx] - q[idx, None] * gl
     phi_r = r["phi"][idx] + ul
-    assert np.isfinite(F_r).all() and np.isfinite(phi_r).all(), "reference not finite"
+    parts = {"five_step F": r["F"], "five_step phi": r["phi"], "local u": ul, "local grad": gl}
+    assert np.isfinite(F_r).all() and np.isfinite(phi_r).all(), \
+        "reference not finite: " + ", ".join(f"{k} {int((~np.isfinite(v)).sum())}" for k, v in parts.items())
     eF, ephi = rel_rms(F[idx], F_r), rel_rms(phi[idx], phi_r)
     # molecules placed at random at three times liquid density leave some
     # atoms of different molecules a few hundredths of an angstrom apart; the
