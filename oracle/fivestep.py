@@ -73,11 +73,12 @@ def dft_matrix(n, sign):
 
 
 def dft3(a, sign):
-    """sum_l exp(sign 2 pi i k.l/n) a_l along all three axes."""
+    """sum_l exp(sign 2 pi i k.l/n) a_l along all three axes (numpy's own
+    summation loops, without BLAS)."""
     F = dft_matrix(a.shape[0], sign)
-    out = np.tensordot(F, a, axes=([1], [0]))
-    out = np.tensordot(F, out, axes=([1], [1])).transpose(1, 0, 2)
-    out = np.tensordot(F, out, axes=([1], [2])).transpose(1, 2, 0)
+    out = np.einsum("kl,lmn->kmn", F, a, optimize=False)
+    out = np.einsum("kl,mln->mkn", F, out, optimize=False)
+    out = np.einsum("kl,mnl->mnk", F, out, optimize=False)
     return out
 
 

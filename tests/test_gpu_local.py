@@ -292,7 +292,8 @@ def test_large_water_full_coulomb_sampled():
     ul, gl = local_sum(pr, q, L, PSWFSplit(p.c, p.rc), targets=idx)
     F_r = r["F"][idx] - q[idx, None] * gl
     phi_r = r["phi"][idx] + ul
-    parts = {"five_step F": r["F"], "five_step phi": r["phi"], "local u": ul, "local grad": gl}
+    parts = {"spread b": r["b"], "b^": r["bhat"], "p": r["p"], "c^": r["chat"], "c": r["c"],
+             "five_step F": r["F"], "five_step phi": r["phi"], "local u": ul, "local grad": gl}
     assert np.isfinite(F_r).all() and np.isfinite(phi_r).all(), \
         "reference not finite: " + ", ".join(f"{k} {int((~np.isfinite(v)).sum())}" for k, v in parts.items())
     eF, ephi = rel_rms(F[idx], F_r), rel_rms(phi[idx], phi_r)
