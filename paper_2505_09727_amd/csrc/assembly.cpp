@@ -380,6 +380,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         const int fused = systems[s].prm.fft_passes == 1 && !hsys_[s].ik && !hsys_[s].p3 &&
                           fft_fused_lds(n, prec) <= kMaxLds;
         by_n[{n, fused}].push_back(s);
+        hsys_[s].fin_fft = !fused;  // the plane-pass FFT's last kernel finalizes the energy
     }
     const int C = fft_x_columns(prec);
     std::vector<int> fused_sys;
@@ -439,6 +440,8 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.prec = prec;
     L_.nsys = nsys;
     L_.any_local = any_local;
+    L_.any_fin_kernel = 0;
+    for (const SysDesc& d : hsys_) L_.any_fin_kernel = L_.any_fin_kernel || !d.fin_fft;
     // LDS staging of a bin's halo for the local pass: the expected particle
     // count of the largest halo with 30% headroom (a bin whose halo holds more
     // takes the global-memory path), within 64 KB

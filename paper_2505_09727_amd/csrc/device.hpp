@@ -32,6 +32,7 @@ struct SysDesc {
     int lsa;          // local: sub-cells per side of a local work item's block (divides lcs)
     int litem_off;    // local: first local work item of the system in the launch's list ...
     int nlitem;       // ... and their count (bins x (lcs / lsa)^3)
+    int fin_fft;      // 1: the last FFT pass (k_inv_yz) finalizes the energy; 0: k_finalize
     double inv_L;     // 1/L (x side)
     double inv_Ly;    // 1/Ly
     double inv_Lz;    // 1/Lz

@@ -64,6 +64,39 @@ template <typename R> struct Bfly<R, 4> {
 
 // ---------------------------------------------------------------------------
 // Deterministic block sum of a double (fixed tree; blockDim a power of two).
+// Energy of one system, E = E_k - S(0)/2 sum q^2 (plus (1/2) sum q u^l with
+// the local part), and the charge sums, by the 64 lanes of one wave (all
+// active) in a fixed order, so the result does not depend on the kernel or
+// block that runs it. Written to S.out[0..3] and E_dev[sys] (if non-null).
+__device__ inline void finalize_system(const SysDesc& S, const double* __restrict__ epart,
+                                       const double* __restrict__ bpart, const double* __restrict__ lpart,
+                                       double* __restrict__ E_dev, int sys) {
+    const int lane = threadIdx.x & 63;
+    double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
+    for (int i = lane; i < S.ncol; i += 64) ek += epart[S.col_off + i];
+    if (S.local)
+        for (int i = lane; i < S.nlitem; i += 64) ek += 0.5 * lpart[S.litem_off + i];
+    for (int i = lane; i < S.npitem; i += 64) {
+        sq += bpart[4 * (S.pitem_off + i) + 0];
+        sa += bpart[4 * (S.pitem_off + i) + 1];
+        s2 += bpart[4 * (S.pitem_off + i) + 2];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ek += __shfl_down(ek, off, 64);
+        sq += __shfl_down(sq, off, 64);
+        sa += __shfl_down(sa, off, 64);
+        s2 += __shfl_down(s2, off, 64);
+    }
+    if (lane == 0) {
+        const double E = ek - 0.5 * S.s0 * s2;
+        S.out[0] = E;
+        S.out[1] = sq;
+        S.out[2] = sa;
+        S.out[3] = s2;
+        if (E_dev) E_dev[sys] = E;
+    }
+}
+
 __device__ inline double block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

@@ -295,7 +295,11 @@ __device__ __forceinline__ void inv_yz_plane(cplx<R>* __restrict__ buf, const cp
 // first gradient grid (in place).
 template <typename R, int N>
 __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __restrict__ sys,
-                                                              const int2* __restrict__ items) {
+                                                              const int2* __restrict__ items,
+                                                              const double* __restrict__ epart,
+                                                              const double* __restrict__ bpart,
+                                                              const double* __restrict__ lpart,
+                                                              double* __restrict__ E_dev) {
     constexpr int RL = N + 2, BD = plane_threads<N>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wi = items[blockIdx.x];
@@ -319,6 +323,9 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_inv_yz(const SysDesc* __
     } else {
         inv_yz_plane<R, N, BD>(buf, tw, plane, plane, 0, R(0));
     }
+    // the system's energy, by the first wave of its plane-0 block: the
+    // partials it sums were complete before this pass started
+    if (S.fin_fft && wi.y == 0 && threadIdx.x < 64) finalize_system(S, epart, bpart, lpart, E_dev, wi.x);
 }
 
 // Pass along x for C consecutive columns c0 .. c0+cnt-1 of the flattened
@@ -630,7 +637,7 @@ static hipError_t allow_lds(K kernel, int bytes) {
 }
 
 template <typename R, int N>
-static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode) {
+static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode, double* E_dev) {
     hipError_t e;
     if constexpr (fused_fits<N, R>()) {
         if (G.fused) {
@@ -656,35 +663,36 @@ static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode)
                                                                          L.epart + G.col_off, mode);
     } else {
         if ((e = allow_lds(k_inv_yz<R, N>, lds_plane)) != hipSuccess) return e;
-        k_inv_yz<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(L.sys, L.planes + G.plane_off);
+        k_inv_yz<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(
+            L.sys, L.planes + G.plane_off, L.epart, L.bpart, L.lpart, E_dev);
     }
     return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t fft_r(const Launch& L, const FftGroup& G, int which, int mode) {
+static hipError_t fft_r(const Launch& L, const FftGroup& G, int which, int mode, double* E_dev) {
     switch (G.n) {
-        case 8: return fft_n<R, 8>(L, G, which, mode);
-        case 12: return fft_n<R, 12>(L, G, which, mode);
-        case 16: return fft_n<R, 16>(L, G, which, mode);
-        case 18: return fft_n<R, 18>(L, G, which, mode);
-        case 24: return fft_n<R, 24>(L, G, which, mode);
-        case 32: return fft_n<R, 32>(L, G, which, mode);
-        case 36: return fft_n<R, 36>(L, G, which, mode);
-        case 48: return fft_n<R, 48>(L, G, which, mode);
-        case 54: return fft_n<R, 54>(L, G, which, mode);
-        case 64: return fft_n<R, 64>(L, G, which, mode);
-        case 72: return fft_n<R, 72>(L, G, which, mode);
-        case 96: return fft_n<R, 96>(L, G, which, mode);
-        case 108: return fft_n<R, 108>(L, G, which, mode);
-        case 128: return fft_n<R, 128>(L, G, which, mode);
-        case 144: return fft_n<R, 144>(L, G, which, mode);
+        case 8: return fft_n<R, 8>(L, G, which, mode, E_dev);
+        case 12: return fft_n<R, 12>(L, G, which, mode, E_dev);
+        case 16: return fft_n<R, 16>(L, G, which, mode, E_dev);
+        case 18: return fft_n<R, 18>(L, G, which, mode, E_dev);
+        case 24: return fft_n<R, 24>(L, G, which, mode, E_dev);
+        case 32: return fft_n<R, 32>(L, G, which, mode, E_dev);
+        case 36: return fft_n<R, 36>(L, G, which, mode, E_dev);
+        case 48: return fft_n<R, 48>(L, G, which, mode, E_dev);
+        case 54: return fft_n<R, 54>(L, G, which, mode, E_dev);
+        case 64: return fft_n<R, 64>(L, G, which, mode, E_dev);
+        case 72: return fft_n<R, 72>(L, G, which, mode, E_dev);
+        case 96: return fft_n<R, 96>(L, G, which, mode, E_dev);
+        case 108: return fft_n<R, 108>(L, G, which, mode, E_dev);
+        case 128: return fft_n<R, 128>(L, G, which, mode, E_dev);
+        case 144: return fft_n<R, 144>(L, G, which, mode, E_dev);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode) {
-    return L.prec == 64 ? fft_r<double>(L, G, which, mode) : fft_r<float>(L, G, which, mode);
+hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode, double* E_dev) {
+    return L.prec == 64 ? fft_r<double>(L, G, which, mode, E_dev) : fft_r<float>(L, G, which, mode, E_dev);
 }
 
 }  // namespace esp

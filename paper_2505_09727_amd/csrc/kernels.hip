@@ -770,34 +770,15 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     }
 }
 
-// Energy per system: E = E_k - S(0)/2 sum q^2 (plus (1/2) sum q u^l with the
-// local part), and the charge sums.
-__global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
-                                                  const double* __restrict__ bpart, const double* __restrict__ lpart,
-                                                  double* __restrict__ E_dev) {
-    __shared__ double red[16];
+// Energy per system (finalize_system) for the systems whose FFT ran as one
+// fused kernel; the others are finalized by their last FFT pass (k_inv_yz).
+// One wave per system.
+__global__ void __launch_bounds__(64) k_finalize(const SysDesc* __restrict__ sys, const double* __restrict__ epart,
+                                                 const double* __restrict__ bpart, const double* __restrict__ lpart,
+                                                 double* __restrict__ E_dev) {
     const SysDesc& S = sys[blockIdx.x];
-    double ek = 0.0, sq = 0.0, sa = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < S.ncol; i += blockDim.x) ek += epart[S.col_off + i];
-    if (S.local)
-        for (int i = threadIdx.x; i < S.nlitem; i += blockDim.x) ek += 0.5 * lpart[S.litem_off + i];
-    for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) {
-        sq += bpart[4 * (S.pitem_off + i) + 0];
-        sa += bpart[4 * (S.pitem_off + i) + 1];
-        s2 += bpart[4 * (S.pitem_off + i) + 2];
-    }
-    ek = block_sum(ek, red);
-    sq = block_sum(sq, red);
-    sa = block_sum(sa, red);
-    s2 = block_sum(s2, red);
-    if (threadIdx.x == 0) {
-        const double E = ek - 0.5 * S.s0 * s2;
-        S.out[0] = E;
-        S.out[1] = sq;
-        S.out[2] = sa;
-        S.out[3] = s2;
-        if (E_dev) E_dev[blockIdx.x] = E;
-    }
+    if (S.fin_fft) return;  // uniform over the block
+    finalize_system(S, epart, bpart, lpart, E_dev, blockIdx.x);
 }
 
 // Serving: move the resident positions of every system with step > 0 by the
@@ -1139,7 +1120,8 @@ hipError_t launch_drift(const Launch& L) {
 }
 
 hipError_t launch_finalize(const Launch& L, double* E_dev) {
-    k_finalize<<<L.nsys, 256, 0, L.stream>>>(L.sys, L.epart, L.bpart, L.lpart, E_dev);
+    if (!L.any_fin_kernel) return hipSuccess;  // every system was finalized by k_inv_yz
+    k_finalize<<<L.nsys, 64, 0, L.stream>>>(L.sys, L.epart, L.bpart, L.lpart, E_dev);
     return hipGetLastError();
 }
 

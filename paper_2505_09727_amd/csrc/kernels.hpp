@@ -44,6 +44,7 @@ struct Launch {
     int n_litems;
     double* lpart;        // per local item: local-part energy partial, sum q u^l
     int any_local;        // some system evaluates the local part
+    int any_fin_kernel;   // some system is finalized by k_finalize (fused FFT), not by k_inv_yz
     int local_cap;        // particles of a bin's halo the local pass stages in LDS
     int local_cells;      // largest halo sub-cell count, (lcs + 2 lR)^3
     int local_deg;        // largest local-part polynomial degree
@@ -95,7 +96,9 @@ hipError_t launch_fold(const Launch& L);
 // spread tiles and mode >> 2 is the x-pass mode; for which = 1 the mode is
 // 0 full, 1 forward only, 2 forward + scaling. A fused group runs its whole
 // transform at which = 0 (with mode >> 2) and nothing at 1 and 2.
-hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode);
+// which 2 (the last pass) also finalizes the energy of systems with fin_fft,
+// writing E_dev[sys] when E_dev is non-null.
+hipError_t launch_fft(const Launch& L, const FftGroup& G, int which, int mode, double* E_dev = nullptr);
 hipError_t launch_gather(const Launch& L, const Group& G);
 hipError_t launch_finalize(const Launch& L, double* E_dev);
 // Local part of the split (systems with local = 1): sub-cell order, then the

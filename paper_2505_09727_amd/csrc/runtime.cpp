@@ -228,7 +228,7 @@ esp_status run_phase(esp_plan* p, int ph, double* E_dev, int fft_mode) {
             for (const FftGroup& G : p->ls.fft_groups()) HIP_TRY(launch_fft(L, G, 1, fft_mode));
             break;
         case kFftYZ:
-            for (const FftGroup& G : p->ls.fft_groups()) HIP_TRY(launch_fft(L, G, 2, 0));
+            for (const FftGroup& G : p->ls.fft_groups()) HIP_TRY(launch_fft(L, G, 2, 0, E_dev));
             break;
         case kGather:
             for (const Group& G : p->ls.groups()) HIP_TRY(launch_gather(L, G));
