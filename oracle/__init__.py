@@ -7,9 +7,10 @@ computes its own PSWF, parameters, influence function and five-step
 pipeline from the paper's definitions.
 
 Modules
-  pswf      psi_0^c by Nystrom discretisation of the finite Fourier operator
-            (Methods, PSWF section); an independent Legendre-basis solver used
-            only to pin the first.
+  pswf      psi_0^c from the prolate differential operator in the even
+            Legendre basis (Methods, PSWF section); the paper's own definition
+            (Nystrom discretisation of the finite Fourier operator) serves only
+            as an independent cross-check that pins it.
   split     the general radial kernel split (eq. kernelsplitting) for the PSWF
             kernel (eq. pswf) and, as a textbook special case, the Gaussian.
   ewald     classical Ewald summation (eq. ewalderf): physics ground truth.
@@ -21,6 +22,11 @@ Modules
   params    the parameter rules (Table 2, eqs. pswfparameters and
             errorformula).
   metrics   relative RMS force error (eq. Deltadef).
+  box, cell orthorhombic boxes and triclinic cells; classical: the Gaussian
+            split with a B-spline window (eq. cem).
+
+Every sum is evaluated by numpy's own loops (no BLAS call); the only LAPACK
+use is the small PSWF eigenproblem.
 
 Pins (see tests/test_oracle_*.py): Table 2 shape parameters, the Fig. 5 cut-off
 numbers, the NaCl Madelung constant, brute-force image sums, the

@@ -37,7 +37,7 @@ def _modes(pos, q, box, ms, W, targets, chunk=256):
         p = pos[s:s + chunk]
         ex = _phase(p[:, 0], mx, box[0]) * q[s:s + chunk, None]
         eyz = (_phase(p[:, 1], my, box[1])[:, :, None] * _phase(p[:, 2], mz, box[2])[:, None, :]).reshape(len(p), -1)
-        rho += ex.T @ eyz
+        rho += np.einsum("ja,jb->ab", ex, eyz, optimize=False)
     A = W.reshape(len(mx), -1) * rho
     kx, ky, kz = (2 * math.pi * np.asarray(m, np.float64) / L for m, L in zip(ms, box))
     kyf = np.repeat(ky, len(mz))
@@ -50,8 +50,8 @@ def _modes(pos, q, box, ms, W, targets, chunk=256):
         exc = np.conj(_phase(p[:, 0], mx, box[0]))
         eyz = np.conj((_phase(p[:, 1], my, box[1])[:, :, None] * _phase(p[:, 2], mz, box[2])[:, None, :])
                       .reshape(len(p), -1))
-        B = exc @ A
-        Bx = (exc * (-1j * kx)[None, :]) @ A
+        B = np.einsum("ia,ab->ib", exc, A, optimize=False)
+        Bx = np.einsum("ia,ab->ib", exc * (-1j * kx)[None, :], A, optimize=False)
         u[s:s + chunk] = np.real(np.sum(B * eyz, axis=1))
         g[s:s + chunk, 0] = np.real(np.sum(Bx * eyz, axis=1))
         g[s:s + chunk, 1] = np.real(np.sum(B * eyz * (-1j * kyf)[None, :], axis=1))
@@ -80,7 +80,7 @@ def ewald_box(pos, q, box, beta=None, targets=None):
         r2 = np.where(self_mask, 1.0, r2)
         r = np.sqrt(r2)
         e = np.where(self_mask, 0.0, erfc(beta * r) / (4 * math.pi * r))
-        ur[s:s + 256] = e @ q
+        ur[s:s + 256] = np.einsum("ab,b->a", e, q, optimize=False)
         dr = -(erfc(beta * r) / r2 + c2 * np.exp(-beta * beta * r2) / r) / (4 * math.pi)
         dr = np.where(self_mask, 0.0, dr) / r
         gr[s:s + 256] = np.einsum("ab,abk->ak", dr * q[None, :], d)
@@ -94,7 +94,7 @@ def ewald_box(pos, q, box, beta=None, targets=None):
     uk, gk = _modes(pos, q, box, ms, w, idx)
     u = ur + uk - q[idx] * beta / (2 * math.pi ** 1.5)
     F = -q[idx, None] * (gr + gk)
-    E = 0.5 * float(np.dot(q[idx], u)) if targets is None else None
+    E = 0.5 * float(np.einsum("i,i->", q[idx], u, optimize=False)) if targets is None else None
     return u, F, E
 
 
@@ -151,4 +151,5 @@ def five_step_box(pos, q, box, n, P, c, rc, c1):
     s0 = PSWFSplit(c, rc).S0()
     phi = ut - q * s0
     F = -q[:, None] * grad
-    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=0.5 * float(np.dot(q, phi)), s0=s0)
+    E = 0.5 * float(np.einsum("i,i->", q, phi, optimize=False))
+    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=E, s0=s0)

@@ -42,11 +42,11 @@ _SHIFTS = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (
 
 def _nearest_images(d, H, Hinv):
     """Nearest-image displacements for an (..., 3) array of displacements."""
-    s = d @ Hinv.T
+    s = np.einsum("...k,jk->...j", d, Hinv, optimize=False)
     s -= np.round(s)
     best = None
     for t in _SHIFTS:
-        c = (s + t) @ H.T
+        c = np.einsum("...k,jk->...j", s + t, H, optimize=False)
         r2 = np.einsum("...k,...k->...", c, c)
         if best is None:
             best, bd = r2, c
@@ -78,7 +78,8 @@ def ewald_cell(pos, q, H, beta=None, targets=None):
         self_mask = ii[:, None] == np.arange(len(pos))[None, :]
         r2 = np.where(self_mask, 1.0, r2)
         r = np.sqrt(r2)
-        ur[s:s + 128] = np.where(self_mask, 0.0, erfc(beta * r) / (4 * math.pi * r)) @ q
+        ur[s:s + 128] = np.einsum("ab,b->a", np.where(self_mask, 0.0, erfc(beta * r) / (4 * math.pi * r)), q,
+                                  optimize=False)
         dr = -(erfc(beta * r) / r2 + c2 * np.exp(-beta * beta * r2) / r) / (4 * math.pi)
         dr = np.where(self_mask, 0.0, dr) / r
         gr[s:s + 128] = np.einsum("ab,abk->ak", dr * q[None, :], d)
@@ -87,7 +88,7 @@ def ewald_cell(pos, q, H, beta=None, targets=None):
     M = [int(math.ceil(kmax * np.linalg.norm(H[:, d]) / (2 * math.pi))) for d in range(3)]
     ms = np.array(np.meshgrid(*[np.arange(-m, m + 1) for m in M], indexing="ij")).reshape(3, -1).T
     ms = ms[np.any(ms != 0, axis=1)]
-    k = 2 * math.pi * ms @ Hinv  # k = 2 pi H^-T m, as rows
+    k = 2 * math.pi * np.einsum("mj,jk->mk", ms, Hinv, optimize=False)  # k = 2 pi H^-T m, as rows
     k2 = np.einsum("mk,mk->m", k, k)
     keep = k2 <= kmax * kmax
     k, k2 = k[keep], k2[keep]
@@ -96,14 +97,14 @@ def ewald_cell(pos, q, H, beta=None, targets=None):
     gk = np.zeros((len(idx), 3))
     for s in range(0, len(k), 2048):
         ks = k[s:s + 2048]
-        ph = pos @ ks.T                       # N x modes
+        ph = np.einsum("ik,mk->im", pos, ks, optimize=False)   # N x modes
         rho = (q[:, None] * np.exp(1j * ph)).sum(0)
         e = np.exp(-1j * ph[idx]) * (w[s:s + 2048] * rho)[None, :]
         uk += np.real(e.sum(1))
-        gk += np.real((e * -1j) @ ks)
+        gk += np.real(np.einsum("im,mk->ik", e * -1j, ks, optimize=False))
     u = ur + uk - q[idx] * beta / (2 * math.pi ** 1.5)
     F = -q[idx, None] * (gr + gk)
-    E = 0.5 * float(np.dot(q[idx], u)) if targets is None else None
+    E = 0.5 * float(np.einsum("i,i->", q[idx], u, optimize=False)) if targets is None else None
     return u, F, E
 
 
@@ -175,17 +176,18 @@ def five_step_cell(pos, q, H, n, P, c, rc, c1):
     q = np.asarray(q, np.float64)
     H = np.asarray(H, np.float64)
     Hinv = np.linalg.inv(H)
-    frac = np.mod(pos @ Hinv.T, 1.0)
+    frac = np.mod(np.einsum("ik,jk->ij", pos, Hinv, optimize=False), 1.0)
     b = spread(frac, q, 1.0, n, P, c1)
     bhat = dft3(b, +1)
     p = influence_cell(n, H, P, c, rc, c1)
     cgrid = np.real(dft3(p * bhat, -1))
     ut, g_frac = interpolate(frac, 1.0, n, P, c1, cgrid)  # gradient in fractional coordinates
-    grad = g_frac @ Hinv                                   # d/dr = H^-T d/ds
+    grad = np.einsum("ij,jk->ik", g_frac, Hinv, optimize=False)   # d/dr = H^-T d/ds
     s0 = PSWFSplit(c, rc).S0()
     phi = ut - q * s0
     F = -q[:, None] * grad
-    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=0.5 * float(np.dot(q, phi)), s0=s0)
+    E = 0.5 * float(np.einsum("i,i->", q, phi, optimize=False))
+    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=E, s0=s0)
 
 
 def five_step_cell_ik(pos, q, H, n, P, c, rc, c1):
@@ -197,7 +199,7 @@ def five_step_cell_ik(pos, q, H, n, P, c, rc, c1):
     base = five_step_cell(pos, q, H, n, P, c, rc, c1)
     H = np.asarray(H, np.float64)
     Hinv = np.linalg.inv(H)
-    frac = np.mod(np.asarray(pos, np.float64) @ Hinv.T, 1.0)
+    frac = np.mod(np.einsum("ik,jk->ij", np.asarray(pos, np.float64), Hinv, optimize=False), 1.0)
     chat = base["p"] * base["bhat"]
     d = ik_factors(n, 1.0)  # derivative along a fractional coordinate
     gs = np.zeros((len(q), 3))
@@ -207,7 +209,7 @@ def five_step_cell_ik(pos, q, H, n, P, c, rc, c1):
         g = np.real(dft3(chat * d.reshape(shape), -1))
         gs[:, ax], _ = interpolate(frac, 1.0, n, P, c1, g)
     out = dict(base)
-    out["F"] = -np.asarray(q, np.float64)[:, None] * (gs @ Hinv)
+    out["F"] = -np.asarray(q, np.float64)[:, None] * np.einsum("ij,jk->ik", gs, Hinv, optimize=False)
     return out
 
 
@@ -219,7 +221,7 @@ def five_step_classical_cell(pos, q, H, n, P, alpha, rc):
     q = np.asarray(q, np.float64)
     H = np.asarray(H, np.float64)
     Hinv = np.linalg.inv(H)
-    frac = np.mod(pos @ Hinv.T, 1.0)
+    frac = np.mod(np.einsum("ik,jk->ij", pos, Hinv, optimize=False), 1.0)
     b = classical.spread(frac, q, 1.0, n, P)
     bhat = dft3(b, +1)
     kk = np.arange(n)
@@ -230,5 +232,6 @@ def five_step_classical_cell(pos, q, H, n, P, alpha, rc):
     ut, g_frac = classical.interpolate(frac, 1.0, n, P, cgrid)
     s0 = GaussianSplit(alpha, rc).S0()
     phi = ut - q * s0
-    F = -q[:, None] * (g_frac @ Hinv)
-    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=0.5 * float(np.dot(q, phi)), s0=s0)
+    F = -q[:, None] * np.einsum("ij,jk->ik", g_frac, Hinv, optimize=False)
+    E = 0.5 * float(np.einsum("i,i->", q, phi, optimize=False))
+    return dict(b=b, bhat=bhat, p=p, c=cgrid, phi=phi, F=F, E=E, s0=s0)

@@ -129,6 +129,6 @@ def five_step_classical(pos, q, L, n, P, alpha, rc):
     s0 = GaussianSplit(alpha, rc).S0()
     phi = ut - q * s0
     F = -q[:, None] * grad
-    E = 0.5 * float(np.dot(q, phi))
+    E = 0.5 * float(np.einsum("i,i->", q, phi, optimize=False))
     return dict(b=b, bhat=bhat, p=p, chat=chat, c=cgrid, phi=phi, F=F, E=E, s0=s0,
                 Ek=0.5 * float(np.sum(p * np.abs(bhat) ** 2)))

@@ -43,7 +43,7 @@ def ewald_real(pos, q, L, beta, targets=None, chunk=256):
         r = np.sqrt(r2)
         e = erfc(beta * r) / (4 * math.pi * r)
         e = np.where(self_mask, 0.0, e)
-        u[s:s + chunk] = e @ q
+        u[s:s + chunk] = np.einsum("ab,b->a", e, q, optimize=False)
         # d/dr [erfc(beta r)/(4 pi r)] = -(erfc/r^2 + c2 exp(-beta^2 r^2)/r)/(4 pi)
         dr = -(erfc(beta * r) / r2 + c2 * np.exp(-beta * beta * r2) / r) / (4 * math.pi)
         dr = np.where(self_mask, 0.0, dr) / r
@@ -69,5 +69,5 @@ def ewald(pos, q, L, beta=None, mmax=None, targets=None):
     uk, gk = evaluate_modes(pos[idx], L, m, w * rho / L ** 3)
     u = ur + uk - q[idx] * beta / (2 * math.pi ** 1.5)
     F = -q[idx, None] * (gr + gk)
-    E = 0.5 * float(np.dot(q[idx], u)) if targets is None else None
+    E = 0.5 * float(np.einsum("i,i->", q[idx], u, optimize=False)) if targets is None else None
     return u, F, E

@@ -119,20 +119,30 @@ def interpolate(pos, L, n, P, c1, cgrid, chunk=20000):
     return ut, g * (n / L)
 
 
+def _finite(name, a):
+    """Every stage of a finite input is finite; name the first one that is not."""
+    if not np.all(np.isfinite(a)):
+        raise FloatingPointError(f"five-step reference: stage {name} holds "
+                                 f"{int(np.count_nonzero(~np.isfinite(a)))} non-finite values")
+    return a
+
+
 def five_step(pos, q, L, n, P, c, rc, c1):
     """All stages of the five-step method; returns a dict."""
-    pos = np.asarray(pos, np.float64)
-    q = np.asarray(q, np.float64)
-    b = spread(pos, q, L, n, P, c1)
-    bhat = dft3(b, +1)
-    p = influence(n, L, P, c, rc, c1)
+    pos = _finite("positions", np.asarray(pos, np.float64))
+    q = _finite("charges", np.asarray(q, np.float64))
+    b = _finite("b (spread)", spread(pos, q, L, n, P, c1))
+    bhat = _finite("b^ (forward DFT)", dft3(b, +1))
+    p = _finite("p (influence)", influence(n, L, P, c, rc, c1))
     chat = p * bhat
-    cgrid = np.real(dft3(chat, -1))
+    cgrid = _finite("c (inverse DFT)", np.real(dft3(chat, -1)))
     ut, grad = interpolate(pos, L, n, P, c1, cgrid)
+    _finite("u~ (interpolation)", ut)
+    _finite("grad u~ (interpolation)", grad)
     s0 = PSWFSplit(c, rc).S0()
     phi = ut - q * s0
     F = -q[:, None] * grad
-    E = 0.5 * float(np.dot(q, phi))
+    E = 0.5 * float(np.einsum("i,i->", q, phi, optimize=False))
     Ek = 0.5 * float(np.sum(p * np.abs(bhat) ** 2))
     return dict(b=b, bhat=bhat, p=p, chat=chat, c=cgrid, u_tilde=ut, grad=grad,
                 phi=phi, F=F, E=E, Ek=Ek, s0=s0)

@@ -83,7 +83,7 @@ def _aliasing_from_weights(m, a, n, L, c1, P):
     psi1 = pswf(c1)
     ft = lambda xi: psi1.ft(xi * P * h / 2.0)
     ratio = np.abs(ft(2 * math.pi * (m + n) / L) / ft(2 * math.pi * m / L))
-    return 6.0 * float(np.dot(a, ratio))
+    return 6.0 * float(np.einsum("i,i->", a, ratio, optimize=False))
 
 
 def aliasing_error(n, L, c, rc, c1, P):

@@ -75,7 +75,7 @@ class PSWF:
     def ft(self, omega):
         """int_{-1}^{1} psi(t) cos(omega t) dt (256-node Gauss-Legendre)."""
         omega = np.asarray(omega, dtype=np.float64)
-        return np.cos(np.multiply.outer(omega, _QT)) @ (_QW * self(_QT))
+        return np.einsum("...t,t->...", np.cos(np.multiply.outer(omega, _QT)), _QW * self(_QT), optimize=False)
 
 
 class NystromPSWF:
@@ -89,14 +89,15 @@ class NystromPSWF:
         A = sw[:, None] * np.cos(self.c * np.outer(t, t)) * sw[None, :]
         vals, vecs = np.linalg.eigh(A)
         psi = vecs[:, -1] / sw
-        if np.dot(w, psi) < 0:
+        if np.einsum("i,i->", w, psi, optimize=False) < 0:
             psi = -psi
         self.lam = float(vals[-1])
         self.t, self._wpsi = t, w * psi
 
     def __call__(self, x):
         x = np.asarray(x, dtype=np.float64)
-        return (np.cos(self.c * np.multiply.outer(x, self.t)) @ self._wpsi) / self.lam
+        return np.einsum("...t,t->...", np.cos(self.c * np.multiply.outer(x, self.t)), self._wpsi,
+                         optimize=False) / self.lam
 
 
 @functools.lru_cache(maxsize=128)

@@ -7,7 +7,8 @@
   * local_sum:        the local part (eq. localpart) over pairs within the
                       kernel's support (minimum image)
 
-All sums are plain O(N x modes) and O(N^2) loops expressed as matrix products;
+All sums are plain O(N x modes) and O(N^2) loops, written as einsum contractions
+evaluated by numpy's own loops (optimize=False, so no BLAS call);
 exponentials factor per axis, exp(i k.r) = exp(i k_x x) exp(i k_y y) exp(i k_z z).
 
 Reading for the Nyquist modes (listed in the design notes): I is the
@@ -36,7 +37,7 @@ def structure_factor(pos, q, L, m, chunk=1024):
         p = pos[s:s + chunk]
         ex = _phase(p[:, 0], m, L) * q[s:s + chunk, None]
         eyz = (_phase(p[:, 1], m, L)[:, :, None] * _phase(p[:, 2], m, L)[:, None, :]).reshape(len(p), M * M)
-        S += ex.T @ eyz
+        S += np.einsum("ja,jb->ab", ex, eyz, optimize=False)
     return S.reshape(M, M, M)
 
 
@@ -54,8 +55,8 @@ def evaluate_modes(pos, L, m, W, chunk=512):
         p = pos[s:s + chunk]
         exc = np.conj(_phase(p[:, 0], m, L))
         eyz = np.conj((_phase(p[:, 1], m, L)[:, :, None] * _phase(p[:, 2], m, L)[:, None, :]).reshape(len(p), M * M))
-        A = exc @ Wf
-        Ax = (exc * (-1j * k)[None, :]) @ Wf
+        A = np.einsum("ia,ab->ib", exc, Wf, optimize=False)
+        Ax = np.einsum("ia,ab->ib", exc * (-1j * k)[None, :], Wf, optimize=False)
         u[s:s + chunk] = np.real(np.sum(A * eyz, axis=1))
         g[s:s + chunk, 0] = np.real(np.sum(Ax * eyz, axis=1))
         g[s:s + chunk, 1] = np.real(np.sum(A * eyz * (-1j * kyz_y)[None, :], axis=1))

@@ -11,11 +11,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
     config.addinivalue_line("markers", "slow: CPU test taking more than ~20 s")
-    # The FP64 reference's BLAS and LAPACK calls (matrix DFTs, the PSWF
-    # eigenproblem) run on one thread: threaded OpenBLAS is the only
-    # nondeterministic part of the reference, and on the GPU host the
-    # 300,000-atom reference has come back all-NaN while the device output
-    # was finite.
+    # The FP64 reference's only LAPACK call (the PSWF eigenproblem) runs on
+    # one thread, so its results are reproducible run to run. Its sums call
+    # no BLAS (tests/test_oracle_robustness.py).
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:
