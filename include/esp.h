@@ -33,9 +33,11 @@
  *     F is N x 3 row-major. Positions may lie anywhere: they are wrapped into
  *     [0, L). For a batch, the arrays of the systems are concatenated in system
  *     order.
- *   - The plan owns all scratch memory (grids, sorted particles, tables) and
- *     its HIP stream; PyTorch or any other allocator only supplies the
- *     caller's buffers.
+ *   - The plan owns all scratch memory (grids, sorted particles, tables).
+ *     The caller may supply the HIP stream the plan enqueues on
+ *     (esp_params.stream, esp_plan_set_stream); otherwise the plan creates
+ *     its own. PyTorch or any other allocator only supplies the caller's
+ *     buffers and, optionally, the stream.
  *   - Thread safety: calls on different plans may run concurrently; calls on
  *     one plan must be serialised by the caller.
  */
@@ -129,6 +131,18 @@ typedef struct {
                              (ik: derivatives along the fractional coordinates) and with
                              either method. Positions may lie anywhere (each is wrapped
                              into the cell). */
+    void*  stream;        /* hipStream_t the plan enqueues on. Input of esp_plan_create_ex /
+                             esp_batch_create (the batch takes reqs[0].stream): the
+                             caller's stream, which the plan then uses and never
+                             destroys; NULL: the plan creates and owns a stream of its
+                             own. Output: the stream in use. See esp_plan_set_stream. */
+    int    deterministic; /* 1: results are bitwise reproducible run to run and do not
+                             depend on which other systems share a batch or a served step.
+                             FP32 plans always are (the spread sums in 64-bit fixed point,
+                             every other sum has a fixed order). FP64 plans are not: their
+                             spread adds with FP64 LDS atomics, whose order varies, so
+                             runs agree to rounding only. Input 0 (either) or 1 (required:
+                             ESP_E_UNSUPPORTED for precision 64); output as described. */
 } esp_params;
 
 typedef struct esp_plan esp_plan;
@@ -198,8 +212,17 @@ esp_status esp_batch_create(int nsys, const double* L, const int64_t* N, const d
 
 esp_status esp_plan_get_params(const esp_plan* plan, int sys, esp_params* out);
 int        esp_plan_num_systems(const esp_plan* plan);
-/* Stream (hipStream_t) the plan enqueues on; created by the plan. */
+/* Stream (hipStream_t) the plan enqueues on: the caller's (esp_params.stream)
+ * or the plan's own. */
 void*      esp_plan_stream(const esp_plan* plan);
+/* Enqueue all later work of the plan on `stream` (hipStream_t of the plan's
+ * device; NULL selects the device's null stream, on which graph capture is
+ * not possible). The call waits for the work already enqueued on the current
+ * stream, so the plan's scratch is never used by two streams at once; a
+ * stream the plan created stays alive until esp_plan_destroy. The caller
+ * keeps `stream` alive while the plan uses it. A captured graph is kept (it
+ * is launched on whichever stream is current). */
+esp_status esp_plan_set_stream(esp_plan* plan, void* stream);
 
 /* Evaluate potentials, forces and energy (Methods, five-step method; AD
  * forces). phi and/or F may be NULL to skip writing them. E is a HOST array
@@ -214,6 +237,30 @@ esp_status esp_longrange_async(esp_plan* plan, const void* pos, const void* q,
                                void* phi, void* F, double* E_dev);
 esp_status esp_plan_sync(esp_plan* plan);
 
+/* Batched evaluation (Methods, five-step method, applied to many independent
+ * systems at once): esp_longrange on a plan made by esp_batch_create. pos, q,
+ * phi, F hold the systems' arrays concatenated in system order (device, plan
+ * precision); E (HOST, nsys doubles, or NULL) receives each system's energy,
+ * and when non-NULL the call waits and checks every system's neutrality
+ * (ESP_E_NOT_NEUTRAL names the first offending system). Every system's
+ * results are bitwise those it gets alone. Same errors as esp_longrange. */
+esp_status esp_batch_longrange(esp_plan* batch, const void* pos, const void* q,
+                               void* phi, void* F, double* E);
+
+/* Short-range kernel of the plan's split for pairing with a short-range code
+ * (Methods: eq. kernelsplitting, L(r) = 1/(4 pi r) - S(r) for r < rc and 0
+ * beyond; eq. localpart sums q_j L(r_ij) over pairs within rc). Host only;
+ * system 0 of a batch (esp_plan_get_params and esp_local_coeffs give any
+ * other system's). coef (room for 2 * ESP_LOCAL_COEF_MAX doubles) receives
+ * the two piecewise polynomials of esp_local_coeffs, A then B right after
+ * it, each (*npieces) x (*degree + 1), in grid units of the plan (lengths divided by
+ * its h = L/nf): for 0 < r < rc/h, with x = r^2 h^2/rc^2,
+ * k = min(floor(K x), K-1), y = K x - k - 1/2,
+ *   h L(h r)        = 1/(4 pi r)   - sum_m A[k][m] y^m,
+ *   h^2 L'(h r) / r = -1/(4 pi r^3) - sum_m B[k][m] y^m.
+ * The polynomials match L and L' to 1e-12 of their peak. */
+esp_status esp_plan_shortrange_coeffs(const esp_plan* plan, double* coef, int* npieces, int* degree);
+
 /* Autotuner of the bin edge T (spec batching: tile and bin sizes picked
  * by measurement). Systems are grouped by (grid size, window width); for each
  * group, largest total particle count first, every admissible T (divisors of
@@ -225,8 +272,10 @@ esp_status esp_plan_sync(esp_plan* plan);
  * every T. The plan is then rebuilt with the choice: its scratch is reallocated and
  * a captured graph is dropped (recaptured on the next graph call). tiles_out
  * (nsys ints, may be NULL) receives the chosen T per system. Blocks until
- * done. Results do not depend on T beyond rounding (FP64) or at all (the FP32
- * fixed-point spread). */
+ * done. Results depend on T only through rounding: the fold of the bins'
+ * overlapping tiles into the grid adds in an order set by T (about 1e-6
+ * relative in FP32 forces, 1e-15 in FP64); the spread itself sums in fixed
+ * point and does not depend on T at all. */
 esp_status esp_plan_autotune(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
                              int* tiles_out);
 
@@ -252,12 +301,23 @@ void esp_plan_destroy(esp_plan* plan);
 esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q,
                            const void* grid_in, int stage, void* grid_out);
 
+/* The interpolation stage alone (eq. interp, AD forces) on a single-system
+ * long-range plan (local = 0, force_method = 0): bins the particles as
+ * esp_longrange does, takes grid_c (device, nf x nf x (nf+2) reals of the
+ * plan precision, last axis padded) as the potential grid c, and writes
+ *   phi_i = sum_l phi~(r_i - h l) c_l - q_i S(0),
+ *   F_i   = -q_i grad_r sum_l phi~(r_i - h l) c_l
+ * to phi and F (device, caller order; either may be NULL). Waits for the
+ * stream. ESP_E_UNSUPPORTED for batches, local or ik plans. */
+esp_status esp_debug_gather(esp_plan* plan, const void* pos, const void* q, const void* grid_c,
+                            void* phi, void* F);
+
 /* Time each pipeline phase: runs the full pipeline `reps` times on the plan's
  * stream with a HIP event between consecutive phases and writes the mean
  * milliseconds of each phase to ms[0..ESP_NUM_PHASES-1] (names from
  * esp_phase_name). Each timed pass follows an untimed one, so the phases
  * are not charged for host launch latency. Waits for the stream. */
-#define ESP_NUM_PHASES 9
+#define ESP_NUM_PHASES 10
 esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void* phi, void* F,
                             int reps, double* ms);
 int         esp_num_phases(void);

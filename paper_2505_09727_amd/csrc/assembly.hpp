@@ -104,6 +104,8 @@ class LaunchSet {
     // Upload the descriptors after set_io / set_step.
     esp_status upload_descriptors(std::string& msg);
     const Launch& launch() const { return L_; }
+    // Stream of later launches and uploads.
+    void set_stream(hipStream_t stream) { L_.stream = stream; }
     const std::vector<Group>& groups() const { return groups_; }
     const std::vector<FftGroup>& fft_groups() const { return fgroups_; }
     int nsys() const { return (int)hsys_.size(); }

@@ -36,6 +36,9 @@ struct SysDesc {
     double inv_L;     // 1/L (x side)
     double inv_Ly;    // 1/Ly
     double inv_Lz;    // 1/Lz
+    double side[3];   // L, Ly, Lz
+    double nside[3];  // n/L, n/Ly, n/Lz (grid coordinate per length unit in a box)
+    int tilt;         // 1: triclinic cell (grid coordinates n mod(H^-1 r, 1))
     double lay, laz;  // local: h_y/h_x, h_z/h_x (1 for a cubic box)
     // triclinic cell H = [a b c] = [[L, xy, xz], [0, Ly, yz], [0, 0, Lz]]: the
     // off-diagonal entries of H^-1 (grid coordinates u = n H^-1 r) and of
@@ -65,7 +68,8 @@ struct SysDesc {
     void* phi;        // N or null
     void* F;          // N x 3 or null
     // scratch owned by the plan or server
-    void* sorted;     // N x (u_x, u_y, u_z, q) in bin order
+    void* sorted;     // N x (v_x, v_y, v_z, q) in bin order, v = u - T (bin coordinates):
+                      // grid coordinates relative to the bin's first cell
     int* perm;        // N: caller index of each sorted particle
     int* rank;        // N: rank within (chunk, bin)
     int* hist;        // nbins x npitem counts, then offsets

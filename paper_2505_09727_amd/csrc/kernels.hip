@@ -25,46 +25,74 @@ __device__ __forceinline__ int fdiv(int x, int m) {
     return (int)(((unsigned long long)(unsigned)x * (unsigned)m) >> 20);
 }
 
-// Grid coordinate u in [0, n) from a fractional coordinate t (any real).
-template <typename R>
-__device__ __forceinline__ R wrap_coord(R t, int n) {
-    t = t - floor(t);
-    R u = t * R(n);
-    if (u >= R(n)) u -= R(n);
-    if (u < R(0)) u = R(0);
-    return u;
+// x mod L for L > 0, as the definition takes it (fmod, then + L for a
+// negative remainder); x itself inside [0, L).
+__device__ __forceinline__ double mod_side(double x, double L) {
+    if (x >= 0.0 && x < L) return x;
+    double t = fmod(x, L);
+    if (t < 0.0) t = __dadd_rn(t, L);
+    return t;
 }
 
-// Fractional coordinates s = H^-1 r of a cell H = [[L, xy, xz], [0, Ly, yz],
-// [0, 0, Lz]] (upper triangular, so is H^-1); the off-diagonal entries are 0
-// in an orthorhombic or cubic box.
+// Grid coordinates of a particle and its bin, in FP64 with the definition's
+// operations: u_d = mod(x_d, L_d) (n / L_d) in a box, u = n mod(H^-1 r, 1) in
+// a triclinic cell (H^-1 upper triangular, each row summed left to right),
+// u in [0, n) (u = n, a rounding of the last representable position, is the
+// periodic image 0). The cells floor(u), and with them the bin and the first
+// point of every window (l0 = floor(u - P/2) + 1), are therefore decided in
+// FP64. The coordinates are kept relative to the bin's first cell, v = u -
+// T t_d in [0, T), rounded toward zero in FP32: the window boundaries (whole
+// and half grid points) are representable, so floor(v - P/2) is the FP64
+// decision exactly, and v keeps T/n times the absolute precision of u.
 template <typename R>
-struct CellMap {
-    R ix, iy, iz, ixy, ixz, iyz;
-    __device__ explicit CellMap(const SysDesc& S)
-        : ix(R(S.inv_L)), iy(R(S.inv_Ly)), iz(R(S.inv_Lz)), ixy(R(S.ixy)), ixz(R(S.ixz)), iyz(R(S.iyz)) {}
-    __device__ __forceinline__ void grid(R x, R y, R z, int n, R& ux, R& uy, R& uz) const {
-        ux = wrap_coord(x * ix + (y * ixy + z * ixz), n);
-        uy = wrap_coord(y * iy + z * iyz, n);
-        uz = wrap_coord(z * iz, n);
-    }
+struct BinCoords {
+    R vx, vy, vz;
+    int tx, ty, tz, bin;
 };
 
-// Bin of a particle: cells floor(u) grouped into T^3 blocks (T divides n).
 template <typename R>
-__device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S, int& tx, int& ty, int& tz) {
-    const int nm1 = S.n - 1;
-    const int cx = min((int)ux, nm1), cy = min((int)uy, nm1), cz = min((int)uz, nm1);
-    tx = fdiv(cx, S.mT);
-    ty = fdiv(cy, S.mT);
-    tz = fdiv(cz, S.mT);
-    return (tx * S.tiles1 + ty) * S.tiles1 + tz;
+__device__ __forceinline__ R to_bin_real(double v);
+template <>
+__device__ __forceinline__ float to_bin_real<float>(double v) {
+    return __double2float_rz(v);
+}
+template <>
+__device__ __forceinline__ double to_bin_real<double>(double v) {
+    return v;
 }
 
 template <typename R>
-__device__ __forceinline__ int bin_of(R ux, R uy, R uz, const SysDesc& S) {
-    int tx, ty, tz;
-    return bin_of(ux, uy, uz, S, tx, ty, tz);
+__device__ __forceinline__ BinCoords<R> bin_coords_of(const SysDesc& S, double x, double y, double z) {
+    const double n = (double)S.n;
+    double u[3];
+    if (S.tilt) {
+        const double sx = __dadd_rn(__dadd_rn(__dmul_rn(x, S.inv_L), __dmul_rn(y, S.ixy)), __dmul_rn(z, S.ixz));
+        const double sy = __dadd_rn(__dmul_rn(y, S.inv_Ly), __dmul_rn(z, S.iyz));
+        const double sz = __dmul_rn(z, S.inv_Lz);
+        u[0] = __dmul_rn(mod_side(sx, 1.0), n);
+        u[1] = __dmul_rn(mod_side(sy, 1.0), n);
+        u[2] = __dmul_rn(mod_side(sz, 1.0), n);
+    } else {
+        u[0] = __dmul_rn(mod_side(x, S.side[0]), S.nside[0]);
+        u[1] = __dmul_rn(mod_side(y, S.side[1]), S.nside[1]);
+        u[2] = __dmul_rn(mod_side(z, S.side[2]), S.nside[2]);
+    }
+    BinCoords<R> b;
+    int t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (u[d] >= n) u[d] = __dadd_rn(u[d], -n);
+        const int c = min((int)u[d], S.n - 1);
+        t[d] = fdiv(c, S.mT);
+    }
+    b.tx = t[0];
+    b.ty = t[1];
+    b.tz = t[2];
+    b.vx = to_bin_real<R>(__dadd_rn(u[0], -(double)(t[0] * S.T)));
+    b.vy = to_bin_real<R>(__dadd_rn(u[1], -(double)(t[1] * S.T)));
+    b.vz = to_bin_real<R>(__dadd_rn(u[2], -(double)(t[2] * S.T)));
+    b.bin = (t[0] * S.tiles1 + t[1]) * S.tiles1 + t[2];
+    return b;
 }
 
 // Coordinates (tx, ty, tz) of bin t.
@@ -93,20 +121,18 @@ __global__ void __launch_bounds__(kChunkThreads) k_hist(const SysDesc* __restric
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
     if (S.small) return;  // uniform over the block
-    const int n = S.n, t1 = S.tiles1, nb = t1 * t1 * t1;
+    const int t1 = S.tiles1, nb = t1 * t1 * t1;
     for (int b = threadIdx.x; b < nb; b += kChunkThreads) cnt[b] = 0;
     __syncthreads();
     double sq = 0.0, sa = 0.0, s2 = 0.0, qm = 0.0;
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R* q = reinterpret_cast<const R*>(S.q);
-    const CellMap<R> cm(S);
 #pragma unroll
     for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
         const int il = wi.y + threadIdx.x + k * kChunkThreads;
         if (il < S.N) {
-            R ux, uy, uz;
-            cm.grid(pos[3 * il + 0], pos[3 * il + 1], pos[3 * il + 2], n, ux, uy, uz);
-            S.rank[il] = atomicAdd(&cnt[bin_of(ux, uy, uz, S)], 1);
+            const BinCoords<R> bc = bin_coords_of<R>(S, pos[3 * il + 0], pos[3 * il + 1], pos[3 * il + 2]);
+            S.rank[il] = atomicAdd(&cnt[bc.bin], 1);
             const double qq = (double)q[il];
             sq += qq;
             sa += fabs(qq);
@@ -208,8 +234,9 @@ __device__ __forceinline__ int* stage_perm(const SysDesc& S) {
     return reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(S.tiles) + off);
 }
 
-// Scatter particles into bin order as (u_x, u_y, u_z, q) with their caller
-// indices, into the staging area; the dealing pass writes the final order.
+// Scatter particles into bin order as (v_x, v_y, v_z, q) (bin coordinates)
+// with their caller indices, into the staging area; the dealing pass writes
+// the final order.
 template <typename R>
 __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __restrict__ sys,
                                                            const int2* __restrict__ items) {
@@ -217,21 +244,18 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
     const SysDesc& S = sys[wi.x];
     if (S.small) return;  // uniform over the block
     const R* pos = reinterpret_cast<const R*>(S.pos);
-    const CellMap<R> cm(S);
-    const int n = S.n;
     const int* hcol = S.hist + (blockIdx.x - S.pitem_off);
 #pragma unroll
     for (int k = 0; k < kParticleChunk / kChunkThreads; ++k) {
         const int il = wi.y + threadIdx.x + k * kChunkThreads;
         if (il < S.N) {
-            R ux, uy, uz;
-            cm.grid(pos[3 * il + 0], pos[3 * il + 1], pos[3 * il + 2], n, ux, uy, uz);
-            const int bin = bin_of(ux, uy, uz, S);
+            const BinCoords<R> bc = bin_coords_of<R>(S, pos[3 * il + 0], pos[3 * il + 1], pos[3 * il + 2]);
+            const int bin = bc.bin;
             const int dst = S.bin_start[bin] + hcol[bin * S.npitem] + S.rank[il];
             typename Vec4<R>::type v;
-            v.x = ux;
-            v.y = uy;
-            v.z = uz;
+            v.x = bc.vx;
+            v.y = bc.vy;
+            v.z = bc.vz;
             v.w = reinterpret_cast<const R*>(S.q)[il];
             stage_vals<R>(S)[dst] = v;
             stage_perm<R>(S)[dst] = il;
@@ -262,11 +286,13 @@ constexpr int kGatherThreads = ESP_GATHER_THREADS;
 constexpr int kDealRounds = 1024;
 constexpr int kDealRegs = 8;  // staged particles per thread held in registers
 
+// Bank class of a particle at bin coordinates v: the tile index of its
+// window's first entry, l0 - (bin origin + lo) per axis, mod 32.
 template <typename R>
-__device__ __forceinline__ int deal_class(const typename Vec4<R>::type& v, R hp, int ox, int oy, int oz, int E) {
-    const int bx = (int)floor(v.x - hp) + 1 - ox;
-    const int by = (int)floor(v.y - hp) + 1 - oy;
-    const int bz = (int)floor(v.z - hp) + 1 - oz;
+__device__ __forceinline__ int deal_class(R vx, R vy, R vz, R hp, int lo, int E) {
+    const int bx = (int)floor(vx - hp) + 1 - lo;
+    const int by = (int)floor(vy - hp) + 1 - lo;
+    const int bz = (int)floor(vz - hp) + 1 - lo;
     return ((bx * E + by) * E + bz) & 31;
 }
 
@@ -281,7 +307,7 @@ __global__ void __launch_bounds__(256) k_deal(const SysDesc* __restrict__ sys, c
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
     if (S.small) return;  // uniform over the block
-    const int t = wi.y, T = S.T, t1 = S.tiles1, E = S.E;
+    const int t = wi.y, E = S.E;
     const int beg = S.bin_start[t], count = S.bin_start[t + 1] - beg;
     if (count == 0) return;  // uniform over the block
     const V* src = stage_vals<R>(S) + beg;
@@ -289,10 +315,7 @@ __global__ void __launch_bounds__(256) k_deal(const SysDesc* __restrict__ sys, c
     V* dst = reinterpret_cast<V*>(S.sorted) + beg;
     int* dstp = S.perm + beg;
     int* key = S.rank + beg;  // free after the scatter; keys beyond the registers
-    int tx, ty, tz;
-    bin_coords(t, S, tx, ty, tz);
     const int lo = -((S.P - 1) / 2);
-    const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const R hp = R(0.5) * R(S.P);
     if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -311,12 +334,13 @@ __global__ void __launch_bounds__(256) k_deal(const SysDesc* __restrict__ sys, c
     for (int k = 0; k < kDealRegs; ++k) {
         const int i = threadIdx.x + k * BD;
         if (i < count) {
-            const int c = deal_class<R>(vr[k], hp, ox, oy, oz, E);
+            const int c = deal_class<R>(vr[k].x, vr[k].y, vr[k].z, hp, lo, E);
             kr[k] = (c << 16) | atomicAdd(&cnt[c], 1);
         }
     }
     for (int i = threadIdx.x + kDealRegs * BD; i < count; i += BD) {
-        const int c = deal_class<R>(src[i], hp, ox, oy, oz, E);
+        const V s = src[i];
+        const int c = deal_class<R>(s.x, s.y, s.z, hp, lo, E);
         key[i] = (c << 16) | atomicAdd(&cnt[c], 1);
     }
     __syncthreads();
@@ -516,12 +540,9 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
     A* lds = reinterpret_cast<A*>(smem_raw);
     const int2 wi = items[blockIdx.x];
     const SysDesc& S = sys[wi.x];
-    const int t = wi.y, T = S.T, t1 = S.tiles1;
-    int tx, ty, tz;
-    bin_coords(t, S, tx, ty, tz);
+    const int t = wi.y;
     const int lo = -((P - 1) / 2);
     const int E = S.E, E3 = E * E * E;
-    const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const int beg = S.bin_start[t], end = S.bin_start[t + 1];
     R* out = reinterpret_cast<R*>(S.tiles) + (long long)t * E3;
     if (beg == end) {  // uniform over the block
@@ -544,7 +565,7 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
         R w[3][P];
         int l0[3];
         windows3<R, P>(v.x, v.y, v.z, ct, deg, w, l0);
-        const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
+        const int bx = l0[0] - lo, by = l0[1] - lo, bz = l0[2] - lo;  // bin coordinates
         const R qs = v.w * scale;
         // fixed point: every term of a particle has the sign of its charge
         // (weights >= 0), so the high word of the 64-bit addend is that sign
@@ -654,7 +675,8 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __rest
             R w[3][P];
             int l0[3];
             windows3<R, P, false>(v.x, v.y, v.z, ct, deg, w, l0);
-            const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
+            const int lo = -((P - 1) / 2);
+            const int bx = l0[0] - lo, by = l0[1] - lo, bz = l0[2] - lo;  // bin coordinates
             R u = 0;
 #pragma unroll 1
             for (int a = 0; a < P; ++a) {
@@ -726,7 +748,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
         R w[3][P], dw[3][P];
         int l0[3];
         windows3_d<R, P>(v.x, v.y, v.z, ct, ctd, deg, w, dw, l0);
-        const int bx = l0[0] - ox, by = l0[1] - oy, bz = l0[2] - oz;
+        const int bx = l0[0] - lo, by = l0[1] - lo, bz = l0[2] - lo;  // bin coordinates
         const R(&wx)[P] = w[0];
         const R(&wy)[P] = w[1];
         const R(&wz)[P] = w[2];
@@ -829,16 +851,10 @@ __global__ void __launch_bounds__(kChunkThreads) k_drift(const SysDesc* __restri
 constexpr int kSmallBatch = 8;
 
 template <typename R>
-__device__ __forceinline__ void small_bin_class(const SysDesc& S, R x, R y, R z, const CellMap<R>& cm, R hp,
-                                                int lo, R& ux, R& uy, R& uz, int& b, int& c) {
-    const int n = S.n, T = S.T, t1 = S.tiles1, E = S.E;
-    cm.grid(x, y, z, n, ux, uy, uz);
-    int tx, ty, tz;
-    b = bin_of(ux, uy, uz, S, tx, ty, tz);
-    const int bx = (int)floor(ux - hp) + 1 - (tx * T + lo);
-    const int by = (int)floor(uy - hp) + 1 - (ty * T + lo);
-    const int bz = (int)floor(uz - hp) + 1 - (tz * T + lo);
-    c = ((bx * E + by) * E + bz) & 31;
+__device__ __forceinline__ BinCoords<R> small_bin_class(const SysDesc& S, R x, R y, R z, R hp, int lo, int& c) {
+    const BinCoords<R> bc = bin_coords_of<R>(S, x, y, z);
+    c = deal_class<R>(bc.vx, bc.vy, bc.vz, hp, lo, S.E);
+    return bc;
 }
 
 template <typename R>
@@ -857,7 +873,6 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
     unsigned* rmask = reinterpret_cast<unsigned*>(rstart + kSmallRounds);
     const R* pos = reinterpret_cast<const R*>(S.pos);
     const R* q = reinterpret_cast<const R*>(S.q);
-    const CellMap<R> cm(S);
     const R hp = R(0.5) * R(S.P);
     const int lo = -((S.P - 1) / 2);
     for (int i = threadIdx.x; i < nb * 32; i += blockDim.x) cnt[i] = 0;
@@ -881,9 +896,8 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
         for (int k = 0; k < kSmallBatch; ++k) {
             const int i = base + k * 1024 + threadIdx.x;
             if (i < N) {
-                R ux, uy, uz;
-                int b, c;
-                small_bin_class<R>(S, px[k], py[k], pz[k], cm, hp, lo, ux, uy, uz, b, c);
+                int c;
+                const int b = small_bin_class<R>(S, px[k], py[k], pz[k], hp, lo, c).bin;
                 S.rank[i] = atomicAdd(&cnt[b * 32 + c], 1);
                 const double qq = (double)pq[k];
                 sq += qq;
@@ -994,9 +1008,9 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
         for (int k = 0; k < kSmallBatch; ++k) {
             const int i = base + k * 1024 + threadIdx.x;
             if (i < N) {
-                R ux, uy, uz;
-                int b, c;
-                small_bin_class<R>(S, px[k], py[k], pz[k], cm, hp, lo, ux, uy, uz, b, c);
+                int c;
+                const BinCoords<R> bc = small_bin_class<R>(S, px[k], py[k], pz[k], hp, lo, c);
+                const int b = bc.bin;
                 int p = binoff[b];
                 if (deal) {
                     const int j = rbase[b] + pr[k];
@@ -1005,9 +1019,9 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
                     p += cnt[b * 32 + c] + pr[k];
                 }
                 V v;
-                v.x = ux;
-                v.y = uy;
-                v.z = uz;
+                v.x = bc.vx;
+                v.y = bc.vy;
+                v.z = bc.vz;
                 v.w = pq[k];
                 sorted[p] = v;
                 S.perm[p] = i;

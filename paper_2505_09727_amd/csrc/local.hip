@@ -28,6 +28,14 @@
 // with r and u in grid units. The results go to a per-particle buffer in bin
 // order, which the gather adds to phi and F; the energy partial of every bin,
 // sum_i q_i u^l_i, goes to the launch's per-bin slots for k_finalize.
+//
+// Close pairs. The staged coordinates carry the rounding of values up to ~2T
+// grid units (a few 1e-6), a large relative error of a displacement of a few
+// hundredths of a grid unit, whose pair force is large. A pair closer than
+// kClosePair grid units (h_x) therefore takes its displacement again, in
+// FP64, from the caller's positions (minimum image), as the definition
+// does; the sweep pays for that only on the rare wave steps where a lane
+// meets such a pair.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -81,6 +89,40 @@ __device__ __forceinline__ double rsqrt_r<double>(double x) {
 }  // namespace
 
 constexpr int kMaxSubCells = 512;  // lcs <= 8
+constexpr double kClosePair = 0.5;  // grid units (h_x): pairs closer than this take an FP64 displacement
+
+// Minimum-image displacement r_i - r_j in units of h_x (Cartesian), in FP64
+// from the caller's positions.
+__device__ __forceinline__ void exact_disp(const SysDesc& S, const double (&ri)[3], const double (&rj)[3],
+                                           double& cx, double& cy, double& cz) {
+    const double dx = ri[0] - rj[0], dy = ri[1] - rj[1], dz = ri[2] - rj[2];
+    const double n = (double)S.n;
+    if (S.tilt) {
+        double sx = dx * S.inv_L + dy * S.ixy + dz * S.ixz;
+        double sy = dy * S.inv_Ly + dz * S.iyz;
+        double sz = dz * S.inv_Lz;
+        sx = (sx - rint(sx)) * n;
+        sy = (sy - rint(sy)) * n;
+        sz = (sz - rint(sz)) * n;
+        cx = sx + S.mxy * sy + S.mxz * sz;
+        cy = S.lay * sy + S.myz * sz;
+        cz = S.laz * sz;
+    } else {
+        const double sc = S.nside[0];  // 1/h_x
+        cx = (dx - S.side[0] * rint(dx * S.inv_L)) * sc;
+        cy = (dy - S.side[1] * rint(dy * S.inv_Ly)) * sc;
+        cz = (dz - S.side[2] * rint(dz * S.inv_Lz)) * sc;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void caller_pos(const SysDesc& S, int gi, double (&r)[3]) {
+    const R* pos = reinterpret_cast<const R*>(S.pos);
+    const long long p = S.perm[S.cidx[gi]];
+    r[0] = (double)pos[3 * p + 0];
+    r[1] = (double)pos[3 * p + 1];
+    r[2] = (double)pos[3 * p + 2];
+}
 
 template <typename R>
 __global__ void __launch_bounds__(kLocalThreads) k_cellsort(const SysDesc* __restrict__ sys,
@@ -279,6 +321,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
     int tx, ty, tz;
     bin_coords_l(t, S, tx, ty, tz);
     const R rho2 = R(S.lrho2), inv_rho2 = R(1.0 / S.lrho2);
+    const R close2 = R(kClosePair * kClosePair);
     const R lsT = R(S.lsT);
     const R sc = R(S.n * S.inv_L);  // 1/h_x
     // pair geometry in units of h_x: a grid-unit displacement d maps to
@@ -392,9 +435,40 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
         const int ly = sub_cell<R>(vi.y, 0, s, lsT);
         const int lz = sub_cell<R>(vi.z, 0, s, lsT);
         R up = 0, fx = 0, fy = 0, fz = 0;
+        double ri[3];  // i's caller position, for close pairs
+        caller_pos<R>(S, gi, ri);
+        // a pair closer than kClosePair: its displacement from the caller's
+        // positions (j: index into cpos)
+        auto refine = [&](int gj, R& dx, R& dy, R& dz) {
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < close2 && r2 > R(0)) {
+                double rj[3], cx, cy, cz;
+                caller_pos<R>(S, gj, rj);
+                exact_disp(S, ri, rj, cx, cy, cz);
+                dx = R(cx);
+                dy = R(cy);
+                dz = R(cz);
+            }
+        };
         if (staged) {
             R vix, viy, viz;
             to_cart(vi.x, vi.y, vi.z, vix, viy, viz);
+            // index into cpos of the staged particle in slot j of the z-run
+            // of halo cells row .. row + 2 lR
+            auto global_of = [&](int row, int j) {
+                int c = row;
+                while (c < row + 2 * LR && hs[c + 1] <= j) ++c;
+                int cell;
+                R sx, sy, sz;
+                halo_cell(c, cell, sx, sy, sz);
+                return cst[cell] + (j - hs[c]);
+            };
+            auto staged_pair = [&](int row, int j, const V& vj) {
+                R dx = vix - vj.x, dy = viy - vj.y, dz = viz - vj.z;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < close2 && r2 > R(0)) refine(global_of(row, j), dx, dy, dz);
+                pair_term<R, D>(dx, dy, dz, vj.w, rho2, inv_rho2, cA, cB, up, fx, fy, fz);
+            };
             // halo rows hx .. hx + 2 lR around halo row hx + lR of the particle
             const int hx = min(max(lx - ox, 0), a - 1), hy = min(max(ly - oy, 0), a - 1),
                       hz = min(max(lz - oz, 0), a - 1);
@@ -407,20 +481,12 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                 int j = ja;
                 for (; j + 3 < jb; j += 4) {
                     const V v0 = hp[j], v1 = hp[j + 1], v2 = hp[j + 2], v3 = hp[j + 3];
-                    pair_term<R, D>(vix - v0.x, viy - v0.y, viz - v0.z, v0.w, rho2, inv_rho2, cA, cB, up, fx,
-                                    fy, fz);
-                    pair_term<R, D>(vix - v1.x, viy - v1.y, viz - v1.z, v1.w, rho2, inv_rho2, cA, cB, up, fx,
-                                    fy, fz);
-                    pair_term<R, D>(vix - v2.x, viy - v2.y, viz - v2.z, v2.w, rho2, inv_rho2, cA, cB, up, fx,
-                                    fy, fz);
-                    pair_term<R, D>(vix - v3.x, viy - v3.y, viz - v3.z, v3.w, rho2, inv_rho2, cA, cB, up, fx,
-                                    fy, fz);
+                    staged_pair(row, j, v0);
+                    staged_pair(row, j + 1, v1);
+                    staged_pair(row, j + 2, v2);
+                    staged_pair(row, j + 3, v3);
                 }
-                for (; j < jb; ++j) {
-                    const V vj = hp[j];
-                    pair_term<R, D>(vix - vj.x, viy - vj.y, viz - vj.z, vj.w, rho2, inv_rho2, cA, cB, up, fx,
-                                    fy, fz);
-                }
+                for (; j < jb; ++j) staged_pair(row, j, hp[j]);
             }
         } else {
             const int cx = tx * s + lx, cy = ty * s + ly, cz = tz * s + lz;
@@ -468,6 +534,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(const SysDesc* __restri
                             const V vj = cpos[j];
                             R dx, dy, dz;
                             to_cart(xs - vj.x, ys - vj.y, zs - vj.z, dx, dy, dz);
+                            if (j != gi) refine(j, dx, dy, dz);
                             pair_term<R, D>(dx, dy, dz, vj.w, rho2, inv_rho2, cA, cB, up, fx, fy, fz);
                         }
                     }

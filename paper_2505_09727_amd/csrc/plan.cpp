@@ -376,6 +376,14 @@ esp_status resolve_params(double L, int64_t N, double tol, const esp_params* req
     r.L = L;
     r.tol = tol;
     if (r.method != 0 && r.method != 1) { msg = "method must be 0 (ESP) or 1 (classical)"; return ESP_E_INVALID; }
+    if (r.deterministic != 0 && r.deterministic != 1) { msg = "deterministic must be 0 or 1"; return ESP_E_INVALID; }
+    if (r.deterministic == 1 && r.precision == 64) {
+        msg = "FP64 plans are not bitwise reproducible (the spread adds with FP64 LDS atomics)";
+        return ESP_E_UNSUPPORTED;
+    }
+    // FP32 plans sum the spread in fixed point and everything else in a fixed
+    // order; FP64 plans add the spread with floating-point LDS atomics
+    r.deterministic = r.precision == 64 ? 0 : 1;
     if (r.Ly < 0 || r.Lz < 0) { msg = "box sides must be positive"; return ESP_E_INVALID; }
     if (r.Ly == 0) r.Ly = L;
     if (r.Lz == 0) r.Lz = L;

@@ -53,8 +53,8 @@ struct esp_plan {
     std::vector<std::vector<double>> p3host;  // orthorhombic systems' influence tables
     unsigned char* scratch = nullptr;
     double* d_out = nullptr;   // kOutDoubles per system, contiguous
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr;  // where work is enqueued: the caller's or `own`
+    hipStream_t own = nullptr;     // created by the plan when the caller gave none
     double* h_out = nullptr;   // pinned copy of d_out
     // caller buffers the descriptors currently point to
     const void* io_pos = nullptr;
@@ -75,7 +75,7 @@ struct esp_plan {
         if (scratch) (void)hipFree(scratch);
         if (d_out) (void)hipFree(d_out);
         if (h_out) (void)hipHostFree(h_out);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        if (own) (void)hipStreamDestroy(own);
     }
 };
 
@@ -169,8 +169,13 @@ esp_status build_plan(int nsys, const double* Ls, const int64_t* Ns, const doubl
     HIP_TRY(hipMalloc(&p->d_out, sizeof(double) * kOutDoubles * nsys));
     HIP_TRY(hipMemset(p->d_out, 0, sizeof(double) * kOutDoubles * nsys));
     HIP_TRY(hipHostMalloc((void**)&p->h_out, sizeof(double) * kOutDoubles * nsys, hipHostMallocDefault));
-    HIP_TRY(hipStreamCreate(&p->stream));
-    p->own_stream = true;
+    if (reqs && reqs[0].stream) {
+        p->stream = static_cast<hipStream_t>(reqs[0].stream);  // the caller's
+    } else {
+        HIP_TRY(hipStreamCreate(&p->own));
+        p->stream = p->own;
+    }
+    for (int s = 0; s < nsys; ++s) p->prm[s].stream = p->stream;
     p->slots.resize(nsys);
     p->p3host.resize(nsys);
     esp_status st = assemble(p);
@@ -204,6 +209,7 @@ esp_status bind_io(esp_plan* p, const void* pos, const void* q, void* phi, void*
 
 // Pipeline phases (one kernel launch each, or one per window-width group).
 enum Phase { kHist, kScan, kScatter, kLocal, kSpread, kFftZY, kFftX, kFftYZ, kGather, kFinalize, kNumPhases };
+static_assert(kNumPhases == ESP_NUM_PHASES, "esp.h's phase count must match the pipeline");
 const char* const kPhaseNames[kNumPhases] = {"hist", "scan", "scatter", "local", "spread", "fft_zy",
                                              "fft_x_scale", "fft_yz", "gather", "finalize"};
 
@@ -415,6 +421,30 @@ int esp_plan_num_systems(const esp_plan* plan) { return plan ? plan->nsys : 0; }
 
 void* esp_plan_stream(const esp_plan* plan) { return plan ? (void*)plan->stream : nullptr; }
 
+esp_status esp_plan_set_stream(esp_plan* plan, void* stream) {
+    if (!plan) return fail(ESP_E_INVALID, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (s == plan->stream) return ESP_OK;
+    // the scratch must not be in use on two streams at once
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+    plan->stream = s;
+    plan->ls.set_stream(s);
+    for (auto& r : plan->prm) r.stream = stream;
+    for (auto& sl : plan->slots) sl.prm.stream = stream;
+    return ESP_OK;
+}
+
+esp_status esp_plan_shortrange_coeffs(const esp_plan* plan, double* coef, int* npieces, int* degree) {
+    if (!plan || !coef || !npieces || !degree) return fail(ESP_E_INVALID, "NULL argument");
+    double A[ESP_LOCAL_COEF_MAX], B[ESP_LOCAL_COEF_MAX];
+    const esp_status s = esp_local_coeffs(&plan->prm[0], A, B, npieces, degree);
+    if (s != ESP_OK) return s;
+    const int m = *npieces * (*degree + 1);  // A, then B right after it
+    std::memcpy(coef, A, sizeof(double) * m);
+    std::memcpy(coef + m, B, sizeof(double) * m);
+    return ESP_OK;
+}
+
 esp_status esp_plan_sync(esp_plan* plan) {
     if (!plan) return fail(ESP_E_INVALID, "plan is NULL");
     HIP_TRY(hipMemcpyAsync(plan->h_out, plan->d_out, sizeof(double) * kOutDoubles * plan->nsys, hipMemcpyDeviceToHost,
@@ -465,6 +495,10 @@ esp_status esp_longrange(esp_plan* plan, const void* pos, const void* q, void* p
     s = esp_plan_sync(plan);
     for (int i = 0; i < plan->nsys; ++i) E[i] = plan->h_out[kOutDoubles * i];
     return s;
+}
+
+esp_status esp_batch_longrange(esp_plan* batch, const void* pos, const void* q, void* phi, void* F, double* E) {
+    return esp_longrange(batch, pos, q, phi, F, E);
 }
 
 esp_status esp_plan_autotune(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
@@ -554,6 +588,24 @@ esp_status esp_debug_stage(esp_plan* plan, const void* pos, const void* q, const
     const esp_params& r = plan->prm[0];
     HIP_TRY(hipMemcpyAsync(grid_out, plan->slots[0].scr.grid, (size_t)r.nf * r.nf * (r.nf + 2) * (plan->prec == 64 ? 8 : 4),
                            hipMemcpyDeviceToDevice, plan->stream));
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+    return ESP_OK;
+}
+
+esp_status esp_debug_gather(esp_plan* plan, const void* pos, const void* q, const void* grid_c, void* phi,
+                            void* F) {
+    if (!plan || !pos || !q || !grid_c) return fail(ESP_E_INVALID, "NULL argument");
+    const esp_params& r = plan->prm[0];
+    if (plan->nsys != 1 || r.local || r.force_method != 0)
+        return fail(ESP_E_UNSUPPORTED, "the gather stage alone needs a single-system long-range plan with AD forces");
+    esp_status s = bind_io(plan, pos, q, phi, F);
+    if (s != ESP_OK) return s;
+    for (int ph = kHist; ph <= kScatter; ++ph)
+        if ((s = run_phase(plan, ph, nullptr, 0)) != ESP_OK) return s;
+    HIP_TRY(hipMemcpyAsync(plan->slots[0].scr.grid, grid_c,
+                           (size_t)r.nf * r.nf * (r.nf + 2) * (plan->prec == 64 ? 8 : 4), hipMemcpyDeviceToDevice,
+                           plan->stream));
+    if ((s = run_phase(plan, kGather, nullptr, 0)) != ESP_OK) return s;
     HIP_TRY(hipStreamSynchronize(plan->stream));
     return ESP_OK;
 }

@@ -2,8 +2,11 @@
 
 Argument marshalling only: every step of the pipeline runs in the HIP
 library. Device buffers are torch tensors on the plan's GPU; their data
-pointers are handed to the library, and the plan's HIP stream is ordered
-after torch's current stream before each call (and torch's stream after it).
+pointers are handed to the library. A plan given a torch stream
+(Plan(..., stream=s)) enqueues on it, and calls made while that stream is
+torch's current stream need no ordering; otherwise the plan's stream is
+ordered after torch's current stream before each call (and torch's stream
+after it).
 """
 from __future__ import annotations
 
@@ -33,7 +36,8 @@ class esp_params(C.Structure):
                 ("kappa", C.c_double), ("L", C.c_double), ("h", C.c_double), ("tol", C.c_double),
                 ("s0", C.c_double), ("force_method", C.c_int), ("local", C.c_int),
                 ("method", C.c_int), ("Ly", C.c_double), ("Lz", C.c_double),
-                ("xy", C.c_double), ("xz", C.c_double), ("yz", C.c_double)]
+                ("xy", C.c_double), ("xz", C.c_double), ("yz", C.c_double),
+                ("stream", C.c_void_p), ("deterministic", C.c_int)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,6 +91,9 @@ _SIGS = {
     "esp_plan_get_params": (C.c_int, [_vp, C.c_int, _P(esp_params)]),
     "esp_plan_num_systems": (C.c_int, [_vp]),
     "esp_plan_stream": (_vp, [_vp]),
+    "esp_plan_set_stream": (C.c_int, [_vp, _vp]),
+    "esp_plan_shortrange_coeffs": (C.c_int, [_vp, _P(C.c_double), _P(C.c_int), _P(C.c_int)]),
+    "esp_batch_longrange": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(C.c_double)]),
     "esp_longrange": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(C.c_double)]),
     "esp_longrange_async": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esp_plan_sync": (C.c_int, [_vp]),
@@ -94,6 +101,7 @@ _SIGS = {
     "esp_plan_autotune": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_int)]),
     "esp_plan_destroy": (None, [_vp]),
     "esp_debug_stage": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
+    "esp_debug_gather": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esp_plan_profile": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_double)]),
     "esp_phase_name": (C.c_char_p, [C.c_int]),
     "esp_server_create": (C.c_int, [_P(esp_server_opts), _P(_vp)]),
@@ -129,11 +137,16 @@ def _check(status):
         raise EspError(status, lib().esp_last_error().decode())
 
 
+def _stream_handle(stream):
+    """hipStream_t of a torch stream (or a raw handle)."""
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
 def _req(**kw) -> esp_params:
     p = esp_params()
     for k, v in kw.items():
         if v is not None:
-            setattr(p, k, v)
+            setattr(p, k, _stream_handle(v) if k == "stream" else v)
     return p
 
 
@@ -204,6 +217,7 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+
 class Plan:
     """A single-system or batched plan (esp_plan_create_ex / esp_batch_create)."""
 
@@ -243,28 +257,62 @@ class Plan:
     def stream(self):
         return lib().esp_plan_stream(self._h)
 
+    def set_stream(self, stream):
+        """esp_plan_set_stream: enqueue later work on a torch stream (or handle)."""
+        _check(lib().esp_plan_set_stream(self._h, C.c_void_p(_stream_handle(stream))))
+        self.params = [self.get_params(s) for s in range(self.nsys)]
+
     def _order_after_torch(self):
+        """Order the plan's stream after torch's current one; None when they
+        are the same stream (nothing to order)."""
         import torch
+        cur = torch.cuda.current_stream()
+        if (self.stream or 0) == cur.cuda_stream:
+            return None
         ext = torch.cuda.ExternalStream(self.stream)
-        ext.wait_stream(torch.cuda.current_stream())
+        ext.wait_stream(cur)
         return ext
+
+    @staticmethod
+    def _order_torch_after(ext):
+        if ext is not None:
+            import torch
+            torch.cuda.current_stream().wait_stream(ext)
 
     def longrange(self, pos, q, phi=None, F=None, energy=True):
         """Enqueue esp_longrange; returns the energies (numpy, one per system) or None."""
-        import torch
         ext = self._order_after_torch()
         E = (C.c_double * self.nsys)() if energy else None
         st = lib().esp_longrange(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), E)
-        torch.cuda.current_stream().wait_stream(ext)
+        self._order_torch_after(ext)
+        _check(st)
+        return np.array(E[:]) if energy else None
+
+    def batch_longrange(self, pos, q, phi=None, F=None, energy=True):
+        """esp_batch_longrange: all systems of a batch plan (concatenated
+        arrays); returns the per-system energies (numpy) or None."""
+        ext = self._order_after_torch()
+        E = (C.c_double * self.nsys)() if energy else None
+        st = lib().esp_batch_longrange(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), E)
+        self._order_torch_after(ext)
         _check(st)
         return np.array(E[:]) if energy else None
 
     def longrange_async(self, pos, q, phi=None, F=None, E_dev=None):
-        import torch
         ext = self._order_after_torch()
         st = lib().esp_longrange_async(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), _ptr(E_dev))
-        torch.cuda.current_stream().wait_stream(ext)
+        self._order_torch_after(ext)
         _check(st)
+
+    def shortrange_coeffs(self):
+        """esp_plan_shortrange_coeffs: the (A, B) piecewise polynomials of the
+        local kernel L(r), L'(r) of system 0, in grid units (esp.h)."""
+        coef = np.zeros(2 * ESP_LOCAL_COEF_MAX)
+        K, d = C.c_int(0), C.c_int(0)
+        _check(lib().esp_plan_shortrange_coeffs(self._h, coef.ctypes.data_as(_P(C.c_double)), C.byref(K),
+                                                C.byref(d)))
+        m = K.value * (d.value + 1)
+        return coef[:m].reshape(K.value, d.value + 1), coef[m:2 * m].reshape(K.value, d.value + 1)
 
     def sync(self):
         _check(lib().esp_plan_sync(self._h))
@@ -276,20 +324,25 @@ class Plan:
         """esp_plan_autotune: time the admissible bin edges per (grid, P) group
         on these buffers and rebuild the plan with the fastest; returns the
         chosen bin edge of every system."""
-        import torch
         ext = self._order_after_torch()
         tiles = (C.c_int * self.nsys)()
         st = lib().esp_plan_autotune(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), int(reps), tiles)
-        torch.cuda.current_stream().wait_stream(ext)
+        self._order_torch_after(ext)
         _check(st)
         self.params = [self.get_params(s) for s in range(self.nsys)]
         return list(tiles)
 
     def debug_stage(self, pos, q, stage, out, grid_in=None):
-        import torch
         ext = self._order_after_torch()
         st = lib().esp_debug_stage(self._h, _ptr(pos), _ptr(q), _ptr(grid_in), int(stage), _ptr(out))
-        torch.cuda.current_stream().wait_stream(ext)
+        self._order_torch_after(ext)
+        _check(st)
+
+    def debug_gather(self, pos, q, grid_c, phi=None, F=None):
+        """esp_debug_gather: interpolate the caller's potential grid alone."""
+        ext = self._order_after_torch()
+        st = lib().esp_debug_gather(self._h, _ptr(pos), _ptr(q), _ptr(grid_c), _ptr(phi), _ptr(F))
+        self._order_torch_after(ext)
         _check(st)
 
     def close(self):

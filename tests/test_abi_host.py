@@ -212,3 +212,35 @@ def test_warm_tables_covers_every_grid_and_rejects_bad_tolerances():
     for bad in ([0.0], [1e-14]):
         with pytest.raises(EspError):
             esp_warm_tables(bad, nf_max=16)
+
+
+def test_stream_and_determinism_fields():
+    """esp_params carries the caller's stream (passed through unchanged by
+    the host query) and the determinism flag (1 for FP32 plans, 0 for FP64
+    ones; requiring it of an FP64 plan or passing other values is refused)."""
+    _lib_or_skip()
+    p = esp.esp_plan_query(31.0, 9000, 1e-4)
+    assert p.deterministic == 1 and not p.stream
+    p = esp.esp_plan_query(31.0, 9000, 1e-4, deterministic=1, stream=0x1234)
+    assert p.deterministic == 1 and p.stream == 0x1234
+    assert esp.esp_plan_query(31.0, 9000, 1e-4, precision=64).deterministic == 0
+    with pytest.raises(esp.EspError) as ei:
+        esp.esp_plan_query(31.0, 9000, 1e-4, deterministic=2)
+    assert ei.value.status == -1
+    with pytest.raises(esp.EspError) as ei:
+        esp.esp_plan_query(31.0, 9000, 1e-4, deterministic=1, precision=64)
+    assert ei.value.status == -2
+
+
+def test_plan_entry_points_reject_null_plans():
+    """The plan-level calls added for the boundary (stream selection, batched
+    evaluation, short-range coefficients) return ESP_E_INVALID on a NULL plan
+    without touching a device."""
+    L = _lib_or_skip()
+    import ctypes as C
+    coef = (C.c_double * (2 * esp.ESP_LOCAL_COEF_MAX))()
+    K, d = C.c_int(0), C.c_int(0)
+    assert L.esp_plan_shortrange_coeffs(None, coef, C.byref(K), C.byref(d)) == -1
+    assert L.esp_plan_set_stream(None, None) == -1
+    assert L.esp_batch_longrange(None, None, None, None, None, None) == -1
+    assert L.esp_last_error().decode() != ""

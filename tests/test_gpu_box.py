@@ -15,6 +15,7 @@ import pytest
 import workloads as W
 from oracle.box import ewald_box, five_step_box, local_sum_box
 from oracle.metrics import rel_rms
+from parity import elementwise
 from oracle.split import PSWFSplit
 
 pytestmark = pytest.mark.gpu
@@ -70,6 +71,8 @@ def test_box_against_reference(box, prec, bar_F, bar_E, local):
     eF, ephi, eE = rel_rms(F, F_r), rel_rms(phi, phi_r), abs(E[0] - E_r) / abs(E_r)
     print(f"box {box} prec={prec} local={local}: relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
     assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    elementwise(F, F_r, bar_F, "F")
+    elementwise(phi, phi_r, bar_F, "phi")
     if local:
         _, F_e, E_e = ewald_box(pr, q, box)
         print(f"box {box} prec={prec}: Delta={rel_rms(F, F_e):.2e}")

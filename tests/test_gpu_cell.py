@@ -18,6 +18,7 @@ import workloads as W
 from oracle.cell import (cell_matrix, ewald_cell, five_step_cell, five_step_cell_ik, five_step_classical_cell,
                          local_sum_cell)
 from oracle.metrics import rel_rms
+from parity import elementwise
 from oracle.split import PSWFSplit
 
 pytestmark = pytest.mark.gpu
@@ -82,6 +83,8 @@ def test_cell_against_reference(cell, prec, bar_F, bar_E, local):
     eF, ephi = rel_rms(F, F_r), rel_rms(phi, phi_r)
     print(f"cell {cell} N={len(q)} prec={prec} local={local}: relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
     assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    elementwise(F, F_r, bar_F, "F")
+    elementwise(phi, phi_r, bar_F, "phi")
     if local:
         _, F_e, E_e = ewald_cell(pr, q, cell_matrix(*cell))
         print(f"cell {cell} prec={prec}: Delta={rel_rms(F, F_e):.2e}")
@@ -192,6 +195,8 @@ def test_small_and_non_reduced_cells(cell, n_atoms):
     phi_r, F_r, E_r = reference(pos, q, p, 0)
     print(f"cell {cell} N={n_atoms} n={p.nf}: relF={rel_rms(F, F_r):.2e}")
     assert rel_rms(F, F_r) < 1e-9 and rel_rms(phi, phi_r) < 1e-9
+    elementwise(F, F_r, 1e-9, "F")
+    elementwise(phi, phi_r, 1e-9, "phi")
 
 
 
@@ -214,6 +219,8 @@ def test_ik_forces_in_a_tilted_cell(cell, prec, bar_F):
     _, F_e, _ = ewald_cell(pr, q, H)
     print(f"ik cell {cell} prec={prec}: relF={eF:.2e} relphi={ephi:.2e} Delta={rel_rms(F, F_e):.2e}")
     assert eF < bar_F and ephi < bar_F and rel_rms(F, F_e) < 1e-4
+    elementwise(F, F_r, bar_F, "ik F")
+    elementwise(phi, phi_r, bar_F, "ik phi")
     # the long-range ik forces conserve momentum; the local part does by symmetry
     assert np.abs(F.sum(0)).max() < (1e-10 if prec == 64 else 1e-4) * np.abs(F).max() * len(q)
 
@@ -263,3 +270,5 @@ def test_classical_method_in_a_tilted_cell(cell, prec, bar_F, local):
         msg += f" Delta={rel_rms(F, F_e):.2e}"
     print(msg)
     assert eF < bar_F and ephi < bar_F
+    elementwise(F, F_r, bar_F, "F")
+    elementwise(phi, phi_r, bar_F, "phi")

@@ -13,6 +13,7 @@ import workloads as W
 from oracle.classical import five_step_classical
 from oracle.ewald import ewald
 from oracle.metrics import rel_rms
+from parity import elementwise
 from oracle.split import GaussianSplit
 from oracle.spectral import local_sum
 
@@ -57,6 +58,8 @@ def check(plan, pos, q, local, bar_F, bar_E):
     print(f"classical N={len(q)} n={p.nf} P={p.P} alpha={p.c:.3f} local={local} prec={plan.precision}: "
           f"relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
     assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    elementwise(F, F_r, bar_F, "F")
+    elementwise(phi, phi_r, bar_F, "phi")
     return phi, F, E
 
 

@@ -6,13 +6,15 @@ Workload: 256 water-like boxes at 1 g/cm^3, atom counts log-uniform in
 sizes). Every system is compared with the reference five-step method (exact
 window, matrix DFT) at the library's parameters: relative RMS force error
 below 1e-4 and relative energy error below 1e-5, the bars of the single
-system tests."""
+system tests, and no particle's force or potential off by more than
+10 x 1e-4 of the system's RMS value."""
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle.fivestep import five_step
 from oracle.metrics import rel_rms
+from parity import elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +47,8 @@ def ensemble_results():
     tiles = plan.autotune(pos, q, phi, F, reps=2)
     E2 = plan.longrange(pos, q, phi, F)
     torch.cuda.synchronize()
-    res.update(tiles=tiles, E_tuned=E2, F_tuned=F.cpu().double().numpy(), params_tuned=list(plan.params))
+    res.update(tiles=tiles, E_tuned=E2, F_tuned=F.cpu().double().numpy(), phi_tuned=phi.cpu().double().numpy(),
+               params_tuned=list(plan.params))
     plan.close()
     return res
 
@@ -71,8 +74,11 @@ def test_ensemble_vs_reference(ensemble_results, chunk):
         p = r["params"][s]
         ref = five_step(pos, q, L, p.nf, p.P, p.c, p.rc, p.c1)
         sl = slice(off[s], off[s + 1])
-        for F, E in ((r["F"], r["E"]), (r["F_tuned"], r["E_tuned"])):
+        for F, phi, E in ((r["F"], r["phi"], r["E"]), (r["F_tuned"], r["phi_tuned"], r["E_tuned"])):
             assert rel_rms(F[sl], ref["F"]) < 1e-4, (s, p.nf, len(q))
+            assert rel_rms(phi[sl], ref["phi"]) < 1e-4, (s, p.nf, len(q))
+            elementwise(F[sl], ref["F"], 1e-4, f"F system {s}")
+            elementwise(phi[sl], ref["phi"], 1e-4, f"phi system {s}")
             assert abs(E[s] - ref["E"]) < 1e-5 * abs(ref["E"]), (s, E[s], ref["E"])
 
 

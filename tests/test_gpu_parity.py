@@ -15,6 +15,7 @@ import workloads as W
 from oracle.ewald import ewald
 from oracle.fivestep import five_step, five_step_ik, dft3, influence, spread
 from oracle.metrics import rel_rms
+from parity import elementwise
 from oracle.split import PSWFSplit
 from oracle.spectral import local_sum
 
@@ -143,6 +144,11 @@ def _check_vs_five_step(plan, pos, q, bar_F, bar_E, sys=0, F_scale=None):
     print(f"N={len(q)} n={plan.params[sys].nf} P={plan.params[sys].P} prec={plan.precision}: "
           f"relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e}")
     assert eF < bar_F and ephi < bar_F and eE < bar_E, (eF, ephi, eE)
+    if F_scale is None:
+        elementwise(F, ref["F"], bar_F, "F")
+    else:
+        assert np.max(np.abs(F - ref["F"])) < 10 * bar_F * F_scale
+    elementwise(phi, ref["phi"], bar_F, "phi")
     # Parseval: k-space energy equals 1/2 sum q phi computed from the outputs
     assert abs(E[sys] - 0.5 * np.dot(q, phi)) < 10 * bar_E * abs(E[sys])
     return phi, F, E
@@ -244,7 +250,7 @@ def test_translation_by_grid_spacing_fp64():
 def test_other_orders_and_sizes(tol, P, n):
     pos, q = W.water_box(700, 20.0, seed=P)
     plan = Plan(20.0, len(q), tol, nf=n, P=P)
-    _check_vs_five_step(plan, pos, q, max(tol, 2e-5), 1e-5)
+    _check_vs_five_step(plan, pos, q, tol, 1e-5)
     plan.close()
 
 
@@ -286,6 +292,8 @@ def test_large_water_served_steps_0_and_99():
     assert eF < 1e-5
     assert abs(r["E_last"] - ref["E"]) < 1e-6 * abs(ref["E"])
     assert rel_rms(phi.astype(np.float64), ref["phi"]) < 1e-5
+    elementwise(F, ref["F"], 1e-5, "F step 99")
+    elementwise(phi, ref["phi"], 1e-5, "phi step 99")
 
 
 def test_batch_matches_single_and_reference():
@@ -301,6 +309,8 @@ def test_batch_matches_single_and_reference():
         sl = slice(off[s], off[s + 1])
         ref = ref_five_step(batch, ps, qs, s)
         assert rel_rms(F[sl], ref["F"]) < 1e-4
+        elementwise(F[sl], ref["F"], 1e-4, f"F system {s}")
+        elementwise(phi[sl], ref["phi"], 1e-4, f"phi system {s}")
         assert abs(E[s] - ref["E"]) < 1e-5 * abs(ref["E"])
         single = Plan(L, len(qs), 1e-4)
         assert single.params[0].nf == batch.params[s].nf
@@ -351,6 +361,8 @@ def test_ik_forces_match_reference(prec, bar_F, bar_E, bar_p):
     net = np.max(np.abs(F.sum(axis=0))) / (len(q) * np.sqrt(np.mean(F ** 2)))
     print(f"ik prec={prec}: relF={eF:.2e} relphi={ephi:.2e} relE={eE:.2e} net={net:.1e}")
     assert eF < bar_F and ephi < bar_F and eE < bar_E
+    elementwise(F, ref["F"], bar_F, "ik F")
+    elementwise(phi, ref["phi"], bar_F, "ik phi")
     assert net < bar_p
     ad = Plan(L, len(q), 1e-4, **kw)
     phi_ad, F_ad, E_ad = run(ad, pos, q)

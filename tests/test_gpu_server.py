@@ -10,6 +10,7 @@ import pytest
 import workloads as W
 from oracle.fivestep import five_step
 from oracle.metrics import rel_rms
+from parity import elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +55,8 @@ def test_served_results_match_reference():
         eF = rel_rms(F.astype(np.float64), ref["F"])
         print(f"served N={len(q)} tol={tol}: relF={eF:.2e} E={r['E_last']:.6g} ref={ref['E']:.6g}")
         assert eF < tol
+        elementwise(F, ref["F"], tol, "served F")
+        elementwise(phi, ref["phi"], tol, "served phi")
         assert abs(r["E_last"] - ref["E"]) < 1e-5 * abs(ref["E"])
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
     srv.close()

@@ -22,6 +22,7 @@ import pytest
 
 import workloads as W
 from oracle.metrics import rel_rms
+from parity import elementwise
 from serving_jobs import limit_threads, positions_at_step, reference
 
 pytestmark = pytest.mark.gpu
@@ -98,6 +99,8 @@ def test_sampled_request_vs_reference(served, tol, band):
         assert eF < tol, (r.rid, nsteps, eF)
         assert eE < 1e-5, (r.rid, nsteps, E, E_ref)
         assert rel_rms(phi.astype(np.float64), phi_ref) < tol
+        elementwise(F, F_ref, tol, f"F request {r.rid}")
+        elementwise(phi, phi_ref, tol, f"phi request {r.rid}")
 
 
 def test_sample_spans_the_stream(served):

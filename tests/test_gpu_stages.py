@@ -1,0 +1,121 @@
+"""Stage-level parity at the workloads' full sizes (FP32, the tile edges the
+batched plans choose): the spread grid b (eq. spread) and the interpolation
+(eq. interp, AD forces) of a given potential grid, each against the CPU
+reference element by element.
+
+  * 9000-atom water box: n = 32, P = 6, bin edges 16 (the batched plans'
+    choice) and 8;
+  * 300,000-atom water box: n = 96, P = 8, bin edge 12.
+
+Bars. Grid: the window polynomials are fitted to within delta = 0.05 tol
+of the window's peak w0 on each piece, so one term q w_x w_y w_z is off by
+at most about 3 delta w0^2 |q|, and b_l by at most 0.15 tol w0^3 A_l with
+A_l the sum of |q_j| over the particles whose window covers point l; every
+grid value is held to that bound (plus 1e-6 max |b| for FP32 rounding).
+Gather: every particle's potential and force within 10 tol of the RMS value
+(the element-wise bar of the end-to-end tests), and the RMS error within
+tol."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.fivestep import five_step, interpolate, window
+from oracle.metrics import rel_rms
+from oracle.pswf import pswf
+from parity import elementwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_09727_amd.esp import Plan  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+CASES = {
+    "water9k": dict(n_mol=3000, L=31.0, seed=2, tol=1e-4, n=32, P=6, tiles=(16, 8)),
+    "water300k": dict(n_mol=W.WATER_300K["n_mol"], L=W.WATER_300K["L"], seed=W.WATER_300K["seed"],
+                      tol=W.WATER_300K["tol"], n=96, P=8, tiles=(12,)),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    c = CASES[request.param]
+    pos, q = W.water_box(c["n_mol"], c["L"], c["seed"])
+    pr = pos.astype(np.float32).astype(np.float64)      # what the device sees
+    plan = Plan(c["L"], len(q), c["tol"])
+    p = plan.params[0]
+    plan.close()
+    assert (p.nf, p.P) == (c["n"], c["P"])
+    ref = five_step(pr, q, c["L"], p.nf, p.P, p.c, p.rc, p.c1)
+    return request.param, c, pos, q, pr, p, ref
+
+
+def _coverage(pr, q, L, n, P, c1):
+    """A_l = sum of |q_j| over the particles whose window covers point l."""
+    u = np.mod(pr, L) * (n / L)
+    psi = pswf(c1)
+    idx = [window(u[:, d], P, n, psi)[0] for d in range(3)]
+    flat = (idx[0][:, :, None, None] * n + idx[1][:, None, :, None]) * n + idx[2][:, None, None, :]
+    w = np.broadcast_to(np.abs(q)[:, None, None, None], flat.shape)
+    return np.bincount(flat.ravel(), weights=w.ravel(), minlength=n ** 3).reshape(n, n, n), float(psi(np.zeros(1))[0])
+
+
+def _tensors(pos, q):
+    return (torch.tensor(pos, dtype=torch.float32, device=DEV), torch.tensor(q, dtype=torch.float32, device=DEV))
+
+
+@pytest.mark.parametrize("degree", [0, 16])
+def test_spread_grid_full_size(case, degree):
+    # degree 0: the plan's default polynomial degree (bar from its fit
+    # tolerance); 16: polynomials exact to FP32, so only FP32 rounding and
+    # the coordinates' storage separate the grids
+    name, c, pos, q, pr, p, ref = case
+    n = p.nf
+    tp, tq = _tensors(pos, q)
+    A, w0 = _coverage(pr, q, c["L"], n, p.P, p.c1)
+    scale = 0.15 * c["tol"] if degree == 0 else 2e-6
+    bound = scale * w0 ** 3 * A + 1e-6 * np.max(np.abs(ref["b"]))
+    for T in c["tiles"]:
+        plan = Plan(c["L"], len(q), c["tol"], tile=T, degree=degree or None)
+        assert plan.params[0].tile == T
+        print(f"{name}: spread, n={n} P={p.P} T={T} degree={plan.params[0].degree}", flush=True)
+        out = torch.empty(n * n * (n + 2), dtype=torch.float32, device=DEV)
+        plan.debug_stage(tp, tq, 1, out)
+        got = out.cpu().double().numpy().reshape(n, n, n + 2)[:, :, :n]
+        plan.close()
+        b = ref["b"]
+        ratio = np.max(np.abs(got - b) / bound)
+        print(f"  grid: max |b - b_ref| / max |b_ref| = {np.max(np.abs(got - b)) / np.max(np.abs(b)):.2e}; "
+              f"largest error over its bound {ratio:.2f}; rel RMS {rel_rms(got, b):.2e}", flush=True)
+        assert ratio <= 1.0
+
+
+def test_gather_full_size(case):
+    name, c, pos, q, pr, p, ref = case
+    n = p.nf
+    tp, tq = _tensors(pos, q)
+    cgrid = np.zeros((n, n, n + 2))
+    cgrid[:, :, :n] = ref["c"]
+    gc = torch.tensor(cgrid.ravel(), dtype=torch.float32, device=DEV)
+    # the interpolation of the FP32-rounded grid the device receives
+    c32 = cgrid[:, :, :n].astype(np.float32).astype(np.float64)
+    ut, grad = interpolate(pr, c["L"], n, p.P, p.c1, c32)
+    phi_ref = ut - q * p.s0
+    F_ref = -q[:, None] * grad
+    for T in c["tiles"]:
+        plan = Plan(c["L"], len(q), c["tol"], tile=T)
+        print(f"{name}: gather, n={n} P={p.P} T={T}", flush=True)
+        phi = torch.empty(len(q), dtype=torch.float32, device=DEV)
+        F = torch.empty((len(q), 3), dtype=torch.float32, device=DEV)
+        plan.debug_gather(tp, tq, gc, phi, F)
+        plan.close()
+        phi_h, F_h = phi.cpu().double().numpy(), F.cpu().double().numpy()
+        eF, ephi = rel_rms(F_h, F_ref), rel_rms(phi_h, phi_ref)
+        print(f"  relF={eF:.2e} relphi={ephi:.2e}", flush=True)
+        assert eF < c["tol"] and ephi < c["tol"]
+        elementwise(F_h, F_ref, c["tol"], "gather F")
+        elementwise(phi_h, phi_ref, c["tol"], "gather phi")
