@@ -374,13 +374,16 @@ typedef struct {
 typedef struct {
     int64_t submitted, admitted, completed, failed, active, waiting, iterations;
     double  particle_steps;   /* sum of N * nsteps over completed requests */
-    double  busy_s;           /* scheduler time spent on steps */
+    double  busy_s;           /* scheduler host time enqueueing steps and handling their
+                                 results (not waiting for the device) */
     double  span_s;           /* first submission to last completion */
     double  p50_latency_s, p99_latency_s, max_latency_s;  /* t_done - t_submit */
     size_t  bytes_in_use, bytes_peak;
     double  build_s;          /* scheduler host time assembling launch sets */
     double  admit_s;          /* scheduler host time admitting (incl. uploads) */
-    double  step_s;           /* enqueue-to-completion time of the steps */
+    double  step_s;           /* enqueue-to-results time of the steps, summed (iterations
+                                 overlap: the next is enqueued before the previous
+                                 one's results are taken) */
 } esp_server_stats;
 
 esp_status esp_server_create(const esp_server_opts* opts, esp_server** out);

@@ -7,6 +7,13 @@
 // every active request with one launch per pipeline phase, applies the
 // per-step drift to the resident positions, and retires requests that have
 // done all their steps (freeing their memory for the next admissions).
+//
+// Iterations overlap: iteration k is enqueued (with the copy of its energies
+// into one of two pinned result tables and an event) before the scheduler
+// waits for iteration k - 1, so admission, launch-set assembly and result
+// handling on the host run while the device computes. A request leaves the
+// active set when its last step is enqueued; its memory and output slot are
+// released when that step's results arrive.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,7 +113,8 @@ struct ServerRequest {
     size_t arena_off = SIZE_MAX;
     int out_slot = -1;
     SystemSlot slot;
-    int steps_done = 0;
+    int steps_done = 0;       // steps whose results arrived
+    int steps_launched = 0;   // steps enqueued
     esp_result res{};
     std::vector<float> phi_out, F_out;  // kept outputs of the last step
 };
@@ -119,7 +127,8 @@ struct esp_server {
     unsigned char* arena_base = nullptr;
     std::unique_ptr<Arena> arena;
     double* d_out = nullptr;            // max_active x kOutDoubles
-    double* h_out = nullptr;            // pinned copy
+    double* h_out[2] = {nullptr, nullptr};  // pinned copies, one per iteration in flight
+    hipEvent_t ev[2] = {nullptr, nullptr};  // completion of the iteration using table k & 1
     std::vector<int> free_out;
     TableStore tables;
     std::mutex tables_mu;
@@ -132,7 +141,8 @@ struct esp_server {
     uint64_t next_release = 1;                              // next id to hand to the scheduler
     std::deque<std::unique_ptr<ServerRequest>> arrivals;   // planned, not yet seen by the scheduler
     std::deque<std::unique_ptr<ServerRequest>> waiting;    // seen, waiting for memory
-    std::vector<std::unique_ptr<ServerRequest>> active;    // scheduler-owned
+    std::vector<std::unique_ptr<ServerRequest>> active;    // scheduler-owned, steps still to enqueue
+    std::vector<std::unique_ptr<ServerRequest>> finishing; // last step enqueued, results pending
     std::deque<esp_result> done;
     std::unordered_map<uint64_t, std::unique_ptr<ServerRequest>> kept;  // finished, outputs kept
     std::vector<double> latencies;
@@ -149,6 +159,16 @@ struct esp_server {
 
     void loop();
     void plan_loop();
+    // One enqueued iteration: the requests it stepped and when.
+    struct Inflight {
+        int64_t k;
+        double t_launch;
+        std::vector<ServerRequest*> reqs;
+    };
+    std::deque<Inflight> inflight;
+    // Wait for the oldest enqueued iteration and take its results (caller
+    // does not hold mu). False after a device error (fatal is set).
+    bool complete_oldest();
     bool admit_locked(ServerRequest* r);
     void retire(ServerRequest* r);
 };
@@ -264,13 +284,55 @@ void esp_server::plan_loop() {
     }
 }
 
+bool esp_server::complete_oldest() {
+    Inflight it = std::move(inflight.front());
+    inflight.pop_front();
+    const hipError_t e = hipEventSynchronize(ev[it.k & 1]);
+    const double t_end = now_s(t0);
+    std::lock_guard<std::mutex> lk(mu);
+    if (e != hipSuccess) {
+        fatal = std::string("device error: ") + hipGetErrorString(e);
+        stop = true;
+        cv_done.notify_all();
+        return false;
+    }
+    step_s += t_end - it.t_launch;
+    const double* table = h_out[it.k & 1];
+    for (ServerRequest* r : it.reqs) {
+        const double* o = table + (size_t)kOutDoubles * r->out_slot;
+        if (r->steps_done == 0) r->res.E_first = o[0];
+        r->res.E_last = o[0];
+        ++r->steps_done;
+        if (r->steps_done == 1 && std::fabs(o[1]) > 1e-6 * o[2]) r->res.status = ESP_E_NOT_NEUTRAL;
+        if (r->steps_done < r->req.nsteps) continue;
+        // the last step's results: release the request
+        retire(r);
+        r->res.t_done = t_end;
+        ++completed;
+        particle_steps += (double)r->req.N * r->req.nsteps;
+        latencies.push_back(r->res.t_done - r->res.t_submit);
+        t_last_done = t_end;
+        done.push_back(r->res);
+        auto f = std::find_if(finishing.begin(), finishing.end(), [&](const auto& p) { return p.get() == r; });
+        if (opts.keep_outputs) kept[r->id] = std::move(*f);
+        finishing.erase(f);
+    }
+    busy_s += now_s(t0) - t_end;  // host time on the results (not the wait)
+    cv_done.notify_all();
+    return true;
+}
+
 void esp_server::loop() {
     (void)hipSetDevice(device);
     bool changed = false;
+    int64_t k = 0;  // iterations enqueued
     for (;;) {
+        bool launch = false;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stop || !arrivals.empty() || !waiting.empty() || !active.empty(); });
+            cv_work.wait(lk, [&] {
+                return stop || !arrivals.empty() || !waiting.empty() || !active.empty() || !inflight.empty();
+            });
             if (stop) return;
             while (!arrivals.empty()) {
                 waiting.push_back(std::move(arrivals.front()));
@@ -283,103 +345,103 @@ void esp_server::loop() {
                 changed = true;
             }
             admit_s += now_s(t0) - ta;
-            if (active.empty()) {
+            if (active.empty() && inflight.empty() && finishing.empty() && !waiting.empty()) {
                 // nothing fits although nothing runs: the head request can never be admitted
-                if (!waiting.empty()) {
-                    auto r = std::move(waiting.front());
-                    waiting.pop_front();
-                    r->res.status = ESP_E_BUSY;
-                    r->res.t_done = now_s(t0);
-                    ++failed;
-                    done.push_back(r->res);
-                    cv_done.notify_all();
-                }
+                auto r = std::move(waiting.front());
+                waiting.pop_front();
+                r->res.status = ESP_E_BUSY;
+                r->res.t_done = now_s(t0);
+                ++failed;
+                done.push_back(r->res);
+                cv_done.notify_all();
                 continue;
             }
+            launch = !active.empty();
         }
-        const double t_iter = now_s(t0);
-        std::string msg;
-        if (changed) {
-            const double tb = now_s(t0);
-            std::vector<SystemSlot> slots;
-            slots.reserve(active.size());
-            for (auto& r : active) slots.push_back(r->slot);
-            if (ls.build(slots, 32, stream, msg) != ESP_OK) {
+        if (launch) {
+            const double t_iter = now_s(t0);
+            std::string msg;
+            if (changed) {
+                const double tb = now_s(t0);
+                std::vector<SystemSlot> slots;
+                slots.reserve(active.size());
+                for (auto& r : active) slots.push_back(r->slot);
+                if (ls.build(slots, 32, stream, msg) != ESP_OK) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    fatal = msg;
+                    stop = true;
+                    cv_done.notify_all();
+                    return;
+                }
+                changed = false;
+                build_s += now_s(t0) - tb;
+            }
+            const Launch& L = ls.launch();
+            // one step of every active request
+            hipError_t e = hipSuccess;
+            for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) e = launch_prepare(L, ph);
+            if (e == hipSuccess) e = launch_local(L);
+            for (const Group& G : ls.groups())
+                if (e == hipSuccess) e = launch_spread(L, G);
+            for (int pass = 0; pass < 3; ++pass)
+                for (const FftGroup& G : ls.fft_groups())
+                    if (e == hipSuccess) e = launch_fft(L, G, pass, 0);
+            for (const Group& G : ls.groups())
+                if (e == hipSuccess) e = launch_gather(L, G);
+            if (e == hipSuccess) e = launch_finalize(L, nullptr);
+            // drift for the next step of requests that continue
+            bool any_drift = false;
+            for (size_t s = 0; s < active.size(); ++s) {
+                ServerRequest* r = active[s].get();
+                const int step =
+                    (r->steps_launched + 1 < r->req.nsteps && r->req.drift > 0) ? r->steps_launched + 1 : 0;
+                ls.set_step((int)s, step);
+                any_drift |= step > 0;
+            }
+            if (e == hipSuccess && any_drift) {
+                if (ls.upload_descriptors(msg) != ESP_OK) e = hipErrorUnknown;
+                if (e == hipSuccess) e = launch_drift(L);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h_out[k & 1], d_out, sizeof(double) * kOutDoubles * opts.max_active,
+                                   hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[k & 1], stream);
+            if (e != hipSuccess) {
                 std::lock_guard<std::mutex> lk(mu);
-                fatal = msg;
+                fatal = std::string("device error: ") + hipGetErrorString(e);
                 stop = true;
                 cv_done.notify_all();
                 return;
             }
-            changed = false;
-            build_s += now_s(t0) - tb;
-        }
-        const double ts = now_s(t0);
-        const Launch& L = ls.launch();
-        // one step of every active request
-        hipError_t e = hipSuccess;
-        for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) e = launch_prepare(L, ph);
-        if (e == hipSuccess) e = launch_local(L);
-        for (const Group& G : ls.groups())
-            if (e == hipSuccess) e = launch_spread(L, G);
-        for (int pass = 0; pass < 3; ++pass)
-            for (const FftGroup& G : ls.fft_groups())
-                if (e == hipSuccess) e = launch_fft(L, G, pass, 0);
-        for (const Group& G : ls.groups())
-            if (e == hipSuccess) e = launch_gather(L, G);
-        if (e == hipSuccess) e = launch_finalize(L, nullptr);
-        // drift for the next step of requests that continue
-        bool any_drift = false;
-        for (size_t s = 0; s < active.size(); ++s) {
-            ServerRequest* r = active[s].get();
-            const int step = (r->steps_done + 1 < r->req.nsteps && r->req.drift > 0) ? r->steps_done + 1 : 0;
-            ls.set_step((int)s, step);
-            any_drift |= step > 0;
-        }
-        if (e == hipSuccess && any_drift) {
-            if (ls.upload_descriptors(msg) != ESP_OK) e = hipErrorUnknown;
-            if (e == hipSuccess) e = launch_drift(L);
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h_out, d_out, sizeof(double) * kOutDoubles * opts.max_active, hipMemcpyDeviceToHost,
-                               stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) {
-            std::lock_guard<std::mutex> lk(mu);
-            fatal = std::string("device error: ") + hipGetErrorString(e);
-            stop = true;
-            cv_done.notify_all();
-            return;
-        }
-        const double t_end = now_s(t0);
-        std::lock_guard<std::mutex> lk(mu);
-        busy_s += t_end - t_iter;
-        step_s += t_end - ts;
-        ++iterations;
-        std::vector<std::unique_ptr<ServerRequest>> still;
-        for (auto& rp : active) {
-            ServerRequest* r = rp.get();
-            const double* o = h_out + (size_t)kOutDoubles * r->out_slot;
-            if (r->steps_done == 0) r->res.E_first = o[0];
-            r->res.E_last = o[0];
-            ++r->steps_done;
-            if (r->steps_done == 1 && std::fabs(o[1]) > 1e-6 * o[2]) r->res.status = ESP_E_NOT_NEUTRAL;
-            if (r->steps_done >= r->req.nsteps) {
-                retire(r);
-                r->res.t_done = t_end;
-                ++completed;
-                particle_steps += (double)r->req.N * r->req.nsteps;
-                latencies.push_back(r->res.t_done - r->res.t_submit);
-                t_last_done = t_end;
-                done.push_back(r->res);
-                if (opts.keep_outputs) kept[r->id] = std::move(rp);
-                changed = true;
-            } else {
-                still.push_back(std::move(rp));
+            Inflight it{k, t_iter, {}};
+            it.reqs.reserve(active.size());
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                std::vector<std::unique_ptr<ServerRequest>> still;
+                for (auto& rp : active) {
+                    it.reqs.push_back(rp.get());
+                    if (++rp->steps_launched >= rp->req.nsteps) {
+                        finishing.push_back(std::move(rp));
+                        changed = true;
+                    } else {
+                        still.push_back(std::move(rp));
+                    }
+                }
+                active.swap(still);
+                ++iterations;
+                busy_s += now_s(t0) - t_iter;
             }
+            inflight.push_back(std::move(it));
+            ++k;
         }
-        active.swap(still);
-        cv_done.notify_all();
+        // take the results of the previous iteration while this one runs (or
+        // of the last one when nothing new was enqueued)
+        if (launch) {
+            while (inflight.size() > 1)
+                if (!complete_oldest()) return;
+        } else if (!inflight.empty()) {
+            if (!complete_oldest()) return;
+        }
     }
 }
 
@@ -402,11 +464,13 @@ esp_status esp_server_create(const esp_server_opts* opts, esp_server** out) {
         return sfail(ESP_E_NOMEM, "cannot allocate the HBM budget");
     }
     s->arena.reset(new Arena(s->opts.hbm_budget_bytes));
-    if (hipMalloc(&s->d_out, sizeof(double) * kOutDoubles * s->opts.max_active) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_out, sizeof(double) * kOutDoubles * s->opts.max_active,
-                      hipHostMallocDefault) != hipSuccess) {
+    for (int b = 0; b < 2; ++b)
+        if (hipHostMalloc((void**)&s->h_out[b], sizeof(double) * kOutDoubles * s->opts.max_active,
+                          hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&s->ev[b], hipEventDisableTiming) != hipSuccess)
+            return sfail(ESP_E_NOMEM, "cannot allocate the result tables");
+    if (hipMalloc(&s->d_out, sizeof(double) * kOutDoubles * s->opts.max_active) != hipSuccess)
         return sfail(ESP_E_NOMEM, "cannot allocate the result table");
-    }
     (void)hipMemset(s->d_out, 0, sizeof(double) * kOutDoubles * s->opts.max_active);
     for (int i = s->opts.max_active - 1; i >= 0; --i) s->free_out.push_back(i);
     esp_server* raw = s.get();
@@ -483,7 +547,7 @@ esp_status esp_server_wait(esp_server* s, double timeout_s) {
     const bool ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] {
         return !s->fatal.empty() ||
                (s->to_plan.empty() && s->planned.empty() && s->arrivals.empty() && s->waiting.empty() &&
-                s->active.empty() && s->planning_n == 0);
+                s->active.empty() && s->finishing.empty() && s->planning_n == 0);
     });
     if (!s->fatal.empty()) return sfail(ESP_E_DEVICE, s->fatal);
     return ok ? ESP_OK : sfail(ESP_E_BUSY, "timed out with requests still queued or running");
@@ -497,7 +561,7 @@ esp_status esp_server_get_stats(esp_server* s, esp_server_stats* st) {
     st->admitted = s->admitted;
     st->completed = s->completed;
     st->failed = s->failed;
-    st->active = (int64_t)s->active.size();
+    st->active = (int64_t)(s->active.size() + s->finishing.size());
     st->waiting = (int64_t)(s->waiting.size() + s->arrivals.size() + s->planned.size() + s->to_plan.size() +
                             s->planning_n);
     st->iterations = s->iterations;
@@ -539,7 +603,10 @@ void esp_server_destroy(esp_server* s) {
     (void)hipStreamSynchronize(s->stream);
     (void)hipFree(s->arena_base);
     (void)hipFree(s->d_out);
-    (void)hipHostFree(s->h_out);
+    for (int b = 0; b < 2; ++b) {
+        if (s->h_out[b]) (void)hipHostFree(s->h_out[b]);
+        if (s->ev[b]) (void)hipEventDestroy(s->ev[b]);
+    }
     (void)hipStreamDestroy(s->stream);
     delete s;
 }
