@@ -237,6 +237,31 @@ esp_status esp_longrange_async(esp_plan* plan, const void* pos, const void* q,
                                void* phi, void* F, double* E_dev);
 esp_status esp_plan_sync(esp_plan* plan);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: work issued while a stream is captured into a HIP graph, tight
+ * serving loops, harnesses that forbid allocation): one evaluation of a single
+ * system, as esp_plan_create_ex followed by esp_longrange and
+ * esp_plan_destroy, with no device allocation. Every buffer of the pipeline
+ * comes from one fixed block of ESP_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends; a system whose buffers do not
+ * fit (the message states the bytes it needs) returns ESP_E_UNSUPPORTED. The
+ * 300,000-atom water box at tol 1e-5 (grid 96, P = 8) needs about 26 MB.
+ * box, N, tol, req: as esp_plan_create_ex (req may be NULL; req->stream is
+ * ignored). pos, q, phi, F: as esp_longrange (device, caller-owned; phi or
+ * F may be NULL). E: HOST, one double, or NULL. stream: the hipStream_t to
+ * run on (NULL: the null stream). The call waits for the stream before it
+ * returns and checks neutrality (ESP_E_NOT_NEUTRAL). Results are those of
+ * esp_longrange on a plan with the same parameters (bin edge: req->tile, or
+ * the default of a single-system plan).
+ * Every call on one GPU uses that GPU's block: calls that overlap in time on
+ * one GPU (from several host threads, or on several streams) race and
+ * corrupt each other's results, so the caller serialises them. The block's
+ * previous contents never matter (every buffer is written before it is
+ * read within a call), so nothing is cleared between calls. */
+#define ESP_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+esp_status esp_longrange_noalloc(const double box[3], int64_t N, double tol, const esp_params* req,
+                                 const void* pos, const void* q, void* phi, void* F, double* E, void* stream);
+
 /* Batched evaluation (Methods, five-step method, applied to many independent
  * systems at once): esp_longrange on a plan made by esp_batch_create. pos, q,
  * phi, F hold the systems' arrays concatenated in system order (device, plan

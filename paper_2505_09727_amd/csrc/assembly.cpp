@@ -57,13 +57,21 @@ esp_status TableStore::get(const esp_params& p, const DeviceClass** out, std::st
     for (int i = 0; i < 5; ++i) {
         auto b = to_prec(*src[i], p.precision);
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(b.size(), 16));
-        if (e != hipSuccess) {
-            msg = std::string("hipMalloc: ") + hipGetErrorString(e);
-            return ESP_E_NOMEM;
+        if (arena_) {
+            q = arena_->take(std::max<size_t>(b.size(), 16));
+            if (!q) {
+                msg = "the fixed scratch block cannot hold the tables";
+                return ESP_E_UNSUPPORTED;
+            }
+        } else {
+            hipError_t e = hipMalloc(&q, std::max<size_t>(b.size(), 16));
+            if (e != hipSuccess) {
+                msg = std::string("hipMalloc: ") + hipGetErrorString(e);
+                return ESP_E_NOMEM;
+            }
+            allocs_.push_back(q);
         }
-        allocs_.push_back(q);
-        e = hipMemcpy(q, b.data(), b.size(), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(q, b.data(), b.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             msg = std::string("hipMemcpy: ") + hipGetErrorString(e);
             return ESP_E_DEVICE;
@@ -209,23 +217,38 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
 }
 
 LaunchSet::~LaunchSet() {
+    if (arena_) return;  // the arena's owner keeps its memory
     void* ps[] = {d_sys_,  d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_,
                   d_cols_, d_bpart_,  d_epart_,  d_lpart_,  d_litems_};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }
 
+esp_status LaunchSet::obtain(void** dev, size_t bytes, std::string& msg) {
+    if (arena_) {
+        *dev = arena_->take(bytes);
+        if (!*dev) {
+            msg = "the fixed scratch block cannot hold the launch lists";
+            return ESP_E_UNSUPPORTED;
+        }
+        return ESP_OK;
+    }
+    if (*dev) (void)hipFree(*dev);
+    *dev = nullptr;
+    hipError_t e = hipMalloc(dev, bytes);
+    if (e != hipSuccess) {
+        msg = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return ESP_E_NOMEM;
+    }
+    return ESP_OK;
+}
+
 template <class T>
 esp_status LaunchSet::put(T** dev, size_t* cap, const std::vector<T>& v, std::string& msg) {
     if (v.size() > *cap || !*dev) {
-        if (*dev) (void)hipFree(*dev);
-        *dev = nullptr;
         const size_t c = std::max<size_t>(v.size() + v.size() / 2, 16);
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(dev), c * sizeof(T));
-        if (e != hipSuccess) {
-            msg = std::string("hipMalloc: ") + hipGetErrorString(e);
-            return ESP_E_NOMEM;
-        }
+        esp_status st = obtain(reinterpret_cast<void**>(dev), c * sizeof(T), msg);
+        if (st != ESP_OK) return st;
         *cap = c;
     }
     if (!v.empty()) {
@@ -272,6 +295,13 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.inv_L = 1.0 / r.L;
         d.inv_Ly = 1.0 / r.Ly;
         d.inv_Lz = 1.0 / r.Lz;
+        d.side[0] = r.L;
+        d.side[1] = r.Ly;
+        d.side[2] = r.Lz;
+        d.nside[0] = (double)r.nf / r.L;
+        d.nside[1] = (double)r.nf / r.Ly;
+        d.nside[2] = (double)r.nf / r.Lz;
+        d.tilt = tilted(r) ? 1 : 0;
         d.lay = r.Ly / r.L;  // h_y / h_x
         d.laz = r.Lz / r.L;
         {
@@ -489,14 +519,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     // partial sums are written before they are read: capacity only
     auto reserve = [&](double** dev, size_t* cap, size_t need) {
         if (need <= *cap && *dev) return ESP_OK;
-        if (*dev) (void)hipFree(*dev);
-        *dev = nullptr;
         const size_t c = std::max<size_t>(need + need / 2, 16);
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(dev), c * sizeof(double));
-        if (e != hipSuccess) {
-            msg = std::string("hipMalloc: ") + hipGetErrorString(e);
-            return ESP_E_NOMEM;
-        }
+        esp_status st = obtain(reinterpret_cast<void**>(dev), c * sizeof(double), msg);
+        if (st != ESP_OK) return st;
         *cap = c;
         return ESP_OK;
     };

@@ -16,6 +16,20 @@
 
 namespace esp {
 
+// Device memory handed out from one block the caller owns (no allocation):
+// 256-byte aligned pieces, in order, until the block is used up.
+struct FixedBlock {
+    unsigned char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    void* take(size_t bytes) {
+        const size_t o = (used + 255) & ~size_t(255);
+        if (o > cap || bytes > cap - o) return nullptr;
+        used = o + bytes;
+        return base + o;
+    }
+};
+
 // Device copy of one table class (owned by a TableStore).
 struct DeviceClass {
     const ClassTables* host = nullptr;
@@ -32,8 +46,11 @@ class TableStore {
     ~TableStore();
     // Device tables for resolved params (uploads on first use).
     esp_status get(const esp_params& p, const DeviceClass** out, std::string& msg);
+    // Take device memory from `a` instead of allocating it (before any get).
+    void set_arena(FixedBlock* a) { arena_ = a; }
 
   private:
+    FixedBlock* arena_ = nullptr;
     std::map<std::pair<const ClassTables*, int>, DeviceClass> dev_;
     std::vector<std::shared_ptr<const ClassTables>> keep_;
     std::vector<void*> allocs_;
@@ -106,6 +123,8 @@ class LaunchSet {
     const Launch& launch() const { return L_; }
     // Stream of later launches and uploads.
     void set_stream(hipStream_t stream) { L_.stream = stream; }
+    // Take device memory from `a` instead of allocating it (before build).
+    void set_arena(FixedBlock* a) { arena_ = a; }
     const std::vector<Group>& groups() const { return groups_; }
     const std::vector<FftGroup>& fft_groups() const { return fgroups_; }
     int nsys() const { return (int)hsys_.size(); }
@@ -114,6 +133,9 @@ class LaunchSet {
   private:
     template <class T>
     esp_status put(T** dev, size_t* cap, const std::vector<T>& v, std::string& msg);
+    // Device memory of `bytes` for a launch-set array (allocated, or from the arena).
+    esp_status obtain(void** dev, size_t bytes, std::string& msg);
+    FixedBlock* arena_ = nullptr;
     Launch L_{};
     std::vector<Group> groups_;
     std::vector<FftGroup> fgroups_;

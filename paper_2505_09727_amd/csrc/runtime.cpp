@@ -67,13 +67,18 @@ struct esp_plan {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     double* g_E = nullptr;
+    // device memory carved from the library's fixed scratch block instead of
+    // allocated (esp_longrange_noalloc): nothing to free
+    bool fixed_mem = false;
 
     ~esp_plan() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (stream) (void)hipStreamSynchronize(stream);
-        if (scratch) (void)hipFree(scratch);
-        if (d_out) (void)hipFree(d_out);
+        if (!fixed_mem) {
+            if (scratch) (void)hipFree(scratch);
+            if (d_out) (void)hipFree(d_out);
+        }
         if (h_out) (void)hipHostFree(h_out);
         if (own) (void)hipStreamDestroy(own);
     }
@@ -646,3 +651,99 @@ const char* esp_phase_name(int phase) { return (phase >= 0 && phase < kNumPhases
 void esp_plan_destroy(esp_plan* plan) { delete plan; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One long-range evaluation without allocating device memory. Every buffer
+// of the pipeline (sorted particles, bins, grids, tiles, tables, launch
+// lists, partial sums, the per-system results) is carved from `scratch`, a
+// fixed block in device memory that each GPU holds for the life of the
+// process. Host code reaches it only through the device address
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in); that address is looked up once per device, on the
+// first call there.
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[ESP_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;  // device ordinal -> address of its scratch
+
+esp_status scratch_of_current_device(unsigned char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(ESP_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch block");
+        it = g_scratch_ptr.emplace(dev, static_cast<unsigned char*>(ptr)).first;
+    }
+    *out = it->second;
+    return ESP_OK;
+}
+
+}  // namespace
+
+extern "C" esp_status esp_longrange_noalloc(const double box[3], int64_t N, double tol, const esp_params* req,
+                                            const void* pos, const void* q, void* phi, void* F, double* E,
+                                            void* stream) {
+    try {
+        if (!box || !pos || !q) return fail(ESP_E_INVALID, "NULL argument");
+        esp_params rq = with_box(box, req);
+        std::unique_ptr<esp_plan> holder(new (std::nothrow) esp_plan());
+        esp_plan* p = holder.get();
+        if (!p) return fail(ESP_E_NOMEM, "host allocation failed");
+        p->fixed_mem = true;
+        HIP_TRY(hipGetDevice(&p->device));
+        p->nsys = 1;
+        p->prm.resize(1);
+        p->Ns.assign(1, N);
+        p->part_off.assign(1, 0);
+        std::string msg;
+        esp_status st = resolve_params(box[0], N, tol, &rq, &p->prm[0], msg);
+        if (st != ESP_OK) return fail(st, msg);
+        esp_params& r = p->prm[0];
+        r.tile = choose_tile(r.nf, req ? req->tile : 0, 512);
+        p->prec = r.precision;
+        p->stream = static_cast<hipStream_t>(stream);
+        r.stream = stream;
+        unsigned char* base = nullptr;
+        if ((st = scratch_of_current_device(&base)) != ESP_OK) return st;
+        FixedBlock arena{base, (size_t)ESP_NOALLOC_SCRATCH_BYTES, 0};
+        const size_t need = scratch_bytes(r, N);
+        p->d_out = static_cast<double*>(arena.take(sizeof(double) * kOutDoubles));
+        p->scratch = static_cast<unsigned char*>(arena.take(need));
+        if (!p->d_out || !p->scratch)
+            return fail(ESP_E_UNSUPPORTED, "this system needs " + std::to_string(need) +
+                                               " bytes of scratch; the no-allocation entry point holds " +
+                                               std::to_string((size_t)ESP_NOALLOC_SCRATCH_BYTES));
+        p->tables.set_arena(&arena);
+        p->ls.set_arena(&arena);
+        p->slots.resize(1);
+        p->p3host.resize(1);
+        SystemSlot& sl = p->slots[0];
+        sl.prm = r;
+        sl.N = N;
+        if ((st = p->tables.get(sl.prm, &sl.cls, msg)) != ESP_OK) return fail(st, msg);
+        sl.scr = carve_scratch(p->scratch, sl.prm, N);
+        sl.scr.out = p->d_out;
+        if (sl.scr.p3) {
+            box_influence(sl.prm, *sl.cls->host, p->p3host[0]);
+            const std::vector<unsigned char> b = to_prec(p->p3host[0], sl.prm.precision);
+            HIP_TRY(hipMemcpy(sl.scr.p3, b.data(), b.size(), hipMemcpyHostToDevice));
+        }
+        if ((st = p->ls.build(p->slots, p->prec, p->stream, msg)) != ESP_OK) return fail(st, msg);
+        if ((st = bind_io(p, pos, q, phi, F)) != ESP_OK) return st;
+        if ((st = enqueue(p, nullptr, 0, nullptr)) != ESP_OK) return st;
+        double out[kOutDoubles];
+        HIP_TRY(hipMemcpyAsync(out, p->d_out, sizeof(out), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        if (E) *E = out[0];
+        if (std::fabs(out[1]) > 1e-6 * out[2])
+            return fail(ESP_E_NOT_NEUTRAL, "the system is not charge neutral (sum q = " + std::to_string(out[1]) + ")");
+        return ESP_OK;
+    } catch (const std::exception& e) {
+        return fail(ESP_E_INVALID, e.what());
+    }
+}

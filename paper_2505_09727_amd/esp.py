@@ -97,6 +97,8 @@ _SIGS = {
     "esp_longrange": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(C.c_double)]),
     "esp_longrange_async": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esp_plan_sync": (C.c_int, [_vp]),
+    "esp_longrange_noalloc": (C.c_int, [_P(C.c_double), C.c_int64, C.c_double, _P(esp_params), _vp, _vp, _vp, _vp,
+                                        _P(C.c_double), _vp]),
     "esp_plan_set_graph": (C.c_int, [_vp, C.c_int]),
     "esp_plan_autotune": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_int)]),
     "esp_plan_destroy": (None, [_vp]),
@@ -216,6 +218,18 @@ def esp_warm_tables(tols, nf_max: int = 144, threads: int = 0) -> None:
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
+
+def esp_longrange_noalloc(box, pos, q, phi=None, F=None, tol=1e-4, stream=None, **req):
+    """One evaluation with no device allocation (esp_longrange_noalloc) on
+    torch tensors; runs on `stream` (a torch stream, default torch's current
+    one) and returns the energy."""
+    import torch
+    st = torch.cuda.current_stream() if stream is None else stream
+    b = (C.c_double * 3)(*box) if np.ndim(box) else _box(float(box))
+    E = C.c_double(0.0)
+    _check(lib().esp_longrange_noalloc(b, int(q.shape[0]), float(tol), C.byref(_req(**req)), _ptr(pos), _ptr(q),
+                                       _ptr(phi), _ptr(F), C.byref(E), C.c_void_p(_stream_handle(st))))
+    return E.value
 
 
 class Plan:
