@@ -218,7 +218,7 @@ SysScratch carve_scratch(unsigned char* base, const esp_params& p, int64_t N) {
 
 LaunchSet::~LaunchSet() {
     if (arena_) return;  // the arena's owner keeps its memory
-    void* ps[] = {d_sys_,  d_pitems_, d_titems_, d_planes_, d_fsys_, d_bsys_,
+    void* ps[] = {d_sys_,  d_pitems_, d_titems_, d_xitems_, d_planes_, d_fsys_, d_bsys_,
                   d_cols_, d_bpart_,  d_epart_,  d_lpart_,  d_litems_};
     for (void* p : ps)
         if (p) (void)hipFree(p);
@@ -268,6 +268,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     hsys_.assign(nsys, SysDesc{});
     pitems_.clear();
     titems_.clear();
+    xitems_.clear();
     planes_.clear();
     cols_.clear();
     groups_.clear();
@@ -275,6 +276,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     fsys_.clear();
     bsys_.clear();
     litems_.clear();
+    // bin work items by window width: one spread / gather launch per P (a
+    // launch per further key, say tile edge, would serialise launches whose
+    // tails leave the chip idle)
     std::vector<std::vector<int2>> titems_by_P(13);
     int nb_max = 1, nb_small_max = 1, n_eligible = 0;
     bool any_ik = false, any_local = false;
@@ -401,9 +405,10 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         }
     }
     // FFT work items grouped by (grid size, path): one launch per group and
-    // pass. Systems that ask for the one-block transform and whose half
-    // spectrum fits in LDS take it; their energy partial goes to one slot
-    // after the x-column items.
+    // pass, largest grids first (the plan runs the groups concurrently, the
+    // first on its own stream). Systems that ask for the one-block transform
+    // and whose half spectrum fits in LDS take it; their energy partial goes
+    // to one slot after the x-column items.
     std::map<std::pair<int, int>, std::vector<int>> by_n;
     for (int s = 0; s < nsys; ++s) {
         const int n = hsys_[s].n;
@@ -414,7 +419,8 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     }
     const int C = fft_x_columns(prec);
     std::vector<int> fused_sys;
-    for (const auto& kv : by_n) {
+    for (auto git = by_n.rbegin(); git != by_n.rend(); ++git) {
+        const auto& kv = *git;
         const int n = kv.first.first, hs = n / 2 + 1;
         FftGroup fg{};
         fg.n = n;
@@ -447,24 +453,50 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         d.ncol = 1;
     }
     for (int P = 4; P <= 12; ++P) {
-        if (titems_by_P[P].empty()) continue;
+        const std::vector<int2>& items = titems_by_P[P];
+        if (items.empty()) continue;
         Group g;
         g.P = P;
-        g.off = (int)titems_.size();
-        g.count = (int)titems_by_P[P].size();
         int E = 0;
-        for (const int2& it : titems_by_P[P]) E = std::max(E, hsys_[it.x].E);
-        // 64-bit accumulators (fixed point or double) / the potential tile,
-        // then the window coefficients and their derivatives (2 x P x 17
-        // reals at most: degree <= 16)
-        const int coef_bytes = 2 * 12 * 17 * 8;
-        g.lds_spread = E * E * E * 8 + coef_bytes;
-        g.lds_gather = ((E * E * E * rb + 15) & ~15) + coef_bytes;
-        if (g.lds_spread > kMaxLds) {
+        for (const int2& it : items) E = std::max(E, hsys_[it.x].E);
+        // XCD order: whole systems to the XCD with the least work so far,
+        // largest first (work ~ particles plus 40 per bin for its tile), so
+        // that the XCDs finish together and a system's bins share one L2
+        std::vector<int> sys_of;  // the group's systems, in order
+        for (const int2& it : items)
+            if (sys_of.empty() || sys_of.back() != it.x) sys_of.push_back(it.x);
+        auto work = [&](int s) {
+            const SysDesc& d = hsys_[s];
+            return (double)d.N + 40.0 * d.tiles1 * d.tiles1 * d.tiles1;
+        };
+        std::stable_sort(sys_of.begin(), sys_of.end(), [&](int a, int b) { return work(a) > work(b); });
+        std::vector<std::vector<int2>> lane(kXcds);
+        std::vector<double> load(kXcds, 0.0);
+        for (int s : sys_of) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += work(s);
+            const int nb = hsys_[s].tiles1 * hsys_[s].tiles1 * hsys_[s].tiles1;
+            for (int t = 0; t < nb; ++t) lane[x].push_back(make_int2(s, t));
+        }
+        size_t per = 0;
+        for (const auto& l : lane) per = std::max(per, l.size());
+        g.off = (int)xitems_.size();
+        g.count = (int)(per * kXcds);
+        for (auto& l : lane) {
+            l.resize(per, make_int2(-1, -1));
+            xitems_.insert(xitems_.end(), l.begin(), l.end());
+        }
+        // spread: the accumulators (32-bit fixed point for FP32 windows up
+        // to P = 6, else 64-bit fixed point or double), then the window
+        // coefficients; gather: the potential tile, the coefficients and
+        // their derivatives, the tile's E^2 row offsets
+        g.lds_spread = E * E * E * (prec == 32 && P <= 6 ? 4 : 8) + kCoefBytes;
+        g.lds_gather = ((E * E * E * rb + 15) & ~15) + kCoefBytes + E * E * 4;
+        if (g.lds_spread > kMaxLds || g.lds_gather > kMaxLds) {
             msg = "bin tile (T+P)^3 exceeds LDS; reduce tile";
             return ESP_E_UNSUPPORTED;
         }
-        titems_.insert(titems_.end(), titems_by_P[P].begin(), titems_by_P[P].end());
+        titems_.insert(titems_.end(), items.begin(), items.end());
         groups_.push_back(g);
     }
     L_.prec = prec;
@@ -511,6 +543,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     if ((st = put(&d_sys_, &cap_sys_, hsys_, msg)) != ESP_OK) return st;
     if ((st = put(&d_pitems_, &cap_pitems_, pitems_, msg)) != ESP_OK) return st;
     if ((st = put(&d_titems_, &cap_titems_, titems_, msg)) != ESP_OK) return st;
+    if ((st = put(&d_xitems_, &cap_xitems_, xitems_, msg)) != ESP_OK) return st;
     if ((st = put(&d_planes_, &cap_planes_, planes_, msg)) != ESP_OK) return st;
     if ((st = put(&d_cols_, &cap_cols_, cols_, msg)) != ESP_OK) return st;
     if ((st = put(&d_fsys_, &cap_fsys_, fsys_, msg)) != ESP_OK) return st;
@@ -531,6 +564,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.sys = d_sys_;
     L_.pitems = d_pitems_;
     L_.titems = d_titems_;
+    L_.xitems = d_xitems_;
     L_.planes = d_planes_;
     L_.cols = d_cols_;
     L_.fsys = d_fsys_;

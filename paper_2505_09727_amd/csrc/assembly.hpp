@@ -140,14 +140,14 @@ class LaunchSet {
     std::vector<Group> groups_;
     std::vector<FftGroup> fgroups_;
     std::vector<SysDesc> hsys_;
-    std::vector<int2> pitems_, titems_, planes_, fsys_, bsys_, litems_;
+    std::vector<int2> pitems_, titems_, xitems_, planes_, fsys_, bsys_, litems_;
     std::vector<int4> cols_;
     SysDesc* d_sys_ = nullptr;
-    int2 *d_pitems_ = nullptr, *d_titems_ = nullptr, *d_planes_ = nullptr, *d_fsys_ = nullptr, *d_bsys_ = nullptr,
+    int2 *d_pitems_ = nullptr, *d_titems_ = nullptr, *d_xitems_ = nullptr, *d_planes_ = nullptr, *d_fsys_ = nullptr, *d_bsys_ = nullptr,
          *d_litems_ = nullptr;
     int4* d_cols_ = nullptr;
     double *d_bpart_ = nullptr, *d_epart_ = nullptr, *d_lpart_ = nullptr;
-    size_t cap_sys_ = 0, cap_pitems_ = 0, cap_titems_ = 0, cap_planes_ = 0, cap_fsys_ = 0, cap_bsys_ = 0, cap_cols_ = 0,
+    size_t cap_sys_ = 0, cap_pitems_ = 0, cap_titems_ = 0, cap_xitems_ = 0, cap_planes_ = 0, cap_fsys_ = 0, cap_bsys_ = 0, cap_cols_ = 0,
            cap_bpart_ = 0, cap_epart_ = 0, cap_lpart_ = 0, cap_litems_ = 0;
 };
 

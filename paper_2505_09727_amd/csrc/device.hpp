@@ -108,6 +108,10 @@ constexpr int kSmallMinSystems = 64;  // one-block binning pays only with this m
 constexpr int kSmallAlwaysN = 4096;   // or for systems this small (one launch instead of five)
 constexpr int kParticleChunk = 1024;  // particles per chunk work item
 constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
+constexpr int kXcds = 8;              // accelerator complex dies (one L2 each) of the chip
+// LDS bytes of a spread / gather block's window coefficients and their
+// derivatives: 2 x P x 17 reals at most (P <= 12, degree <= 16, 8-byte reals)
+constexpr int kCoefBytes = 2 * 12 * 17 * 8;
 constexpr int kOutDoubles = 8;
 constexpr int kLocalCoefStride = 17;       // padded coefficients per local polynomial (degree <= 16)
 constexpr int kLocalThreads = 256;          // threads of a local-part block

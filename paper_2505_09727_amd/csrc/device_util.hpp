@@ -13,6 +13,29 @@ template <> struct Vec4<double> { using type = double4; };
 
 template <typename R> struct cplx { R x, y; };
 
+// Global-memory views of the descriptors' pointers (which are generic):
+// accesses through them compile to global_* instructions, which count only on
+// the vector-memory counter, where flat_* accesses count on the LDS counter
+// too, so that every wait for an LDS result would also wait for them.
+template <typename T> __device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+// Element k of a global array of 4-vectors.
+template <typename R>
+__device__ __forceinline__ typename Vec4<R>::type gload4(const void* p, long long k) {
+    typedef R e4 __attribute__((ext_vector_type(4)));
+    const e4 x = gptr(static_cast<const e4*>(p))[k];
+    typename Vec4<R>::type v;
+    v.x = x.x;
+    v.y = x.y;
+    v.z = x.z;
+    v.w = x.w;
+    return v;
+}
+
 // FFT arithmetic is kept free of fused multiply-adds, so every butterfly
 // rounds the same way whatever code the compiler schedules around it.
 #pragma clang fp contract(off)

@@ -115,50 +115,58 @@ template <typename R, int N> constexpr int x_threads() {
 
 // Assemble grid plane x from the spread's bin tiles (the halo fold): every
 // point sums the tile entries that cover it, at most 3 per axis (a tile spans
-// E = T + P - 1 + (P odd) <= T + 12 points and T >= 8). The loads of PG points
-// per thread are all issued before any is summed. The result goes to LDS in
-// pair-row order: rows 2r and 2r+1 are the real and imaginary parts of
-// complex row r, rows N + 1 complex values apart (conflict-free z stages).
+// E = T + P - 1 + (P odd) <= T + 12 points and T >= 8), over x, then y, then z
+// entries. The first floor(BD / N) N threads each own one column z, whose
+// entries they look up once, and walk the rows y = tid / N, + floor(BD / N),
+// ...; a row's y entries are common to the lanes on that row. The result goes
+// to LDS in pair-row order: rows 2r and 2r+1 are the real and imaginary parts
+// of complex row r, rows N + 1 complex values apart (conflict-free z stages).
 template <typename R, int N, int BD>
 __device__ __forceinline__ void fold_plane(R* __restrict__ bufr, const R* __restrict__ tiles, const SysDesc& S,
                                            const CoverTab* __restrict__ tab, const CoverTab& cx) {
-    constexpr int NP = N * N, PG = 4;
+    static_assert(BD >= N, "one thread per column at least");
+    constexpr int RS = BD / N;
     const int t1 = S.tiles1, E = S.E, EE = E * E, E3 = EE * E;
-    for (int p0 = 0; p0 < NP; p0 += PG * BD) {
-        R acc[PG];
+    const int r0 = (int)threadIdx.x / N, z = (int)threadIdx.x - r0 * N;
+    if (r0 >= RS) return;
+    const auto tg = gptr(tiles);
+    const CoverTab cz = tab[z];
+    int zo[3];
 #pragma unroll
-        for (int q = 0; q < PG; ++q) acc[q] = R(0);
+    for (int c = 0; c < 3; ++c) zo[c] = c < cz.cnt ? cz.bin[c] * E3 + cz.off[c] : 0;
+    // two rows per step, the loads of both issued before any is summed
+    for (int y0 = r0; y0 < N; y0 += 2 * RS) {
+        int yo[2][3], ycnt[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int y = y0 + u * RS;
+            const CoverTab cy = tab[y < N ? y : 0];
+            ycnt[u] = y < N ? cy.cnt : 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) yo[u][b] = b < cy.cnt ? cy.bin[b] * t1 * E3 + cy.off[b] * E : 0;
+        }
+        R acc[2] = {R(0), R(0)};
         for (int a = 0; a < cx.cnt; ++a) {
-            const R* ta = tiles + cx.bin[a] * t1 * t1 * E3 + cx.off[a] * EE;
-            R v[PG][3][3];
+            const int xo = cx.bin[a] * t1 * t1 * E3 + cx.off[a] * EE;
+            R v[2][3][3];
 #pragma unroll
-            for (int q = 0; q < PG; ++q) {
-                const int idx = p0 + q * BD + (int)threadIdx.x;
-                const bool ok = (NP % (PG * BD) == 0) || idx < NP;
-                const int y = ok ? idx / N : 0, z = ok ? idx - (idx / N) * N : 0;
-                const CoverTab cy = tab[y], cz = tab[z];
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        v[q][b][c] = (ok && b < cy.cnt && c < cz.cnt)
-                                         ? ta[(cy.bin[b] * t1 + cz.bin[c]) * E3 + cy.off[b] * E + cz.off[c]]
-                                         : R(0);
-            }
+                        v[u][b][c] = (b < ycnt[u] && c < cz.cnt) ? tg[(unsigned)(xo + yo[u][b] + zo[c])] : R(0);
 #pragma unroll
-            for (int q = 0; q < PG; ++q)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[q] += v[q][b][c];
+                    for (int c = 0; c < 3; ++c) acc[u] += v[u][b][c];
         }
 #pragma unroll
-        for (int q = 0; q < PG; ++q) {
-            const int idx = p0 + q * BD + (int)threadIdx.x;
-            if ((NP % (PG * BD) == 0) || idx < NP) {
-                const int y = idx / N, z = idx - y * N;
-                bufr[2 * ((y >> 1) * (N + 1) + z) + (y & 1)] = acc[q];
-            }
+        for (int u = 0; u < 2; ++u) {
+            const int y = y0 + u * RS;
+            if (y < N) bufr[2 * ((y >> 1) * (N + 1) + z) + (y & 1)] = acc[u];
         }
     }
 }

@@ -273,15 +273,11 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
 // holds the j-th staged particle of every class that has one, in class order.
 // Any order within a bin gives the same results; a bin whose largest class
 // exceeds kDealRounds keeps the staged order.
-// Threads per spread / gather block (one block per bin).
-#ifndef ESP_SPREAD_THREADS
-#define ESP_SPREAD_THREADS 512
-#endif
-#ifndef ESP_GATHER_THREADS
-#define ESP_GATHER_THREADS 512
-#endif
-constexpr int kSpreadThreads = ESP_SPREAD_THREADS;
-constexpr int kGatherThreads = ESP_GATHER_THREADS;
+// Threads per spread / gather block (one block per bin). Waves past a bin's
+// last particle exit their particle loop at once, so a fixed block costs
+// little for small bins.
+constexpr int kSpreadThreads = 512;
+constexpr int kGatherThreads = 512;
 
 constexpr int kDealRounds = 1024;
 constexpr int kDealRegs = 8;  // staged particles per thread held in registers
@@ -511,6 +507,15 @@ __device__ __forceinline__ int wrap_near(int g, int n) {
     return g >= n ? g - n : g;
 }
 
+// The bin of this block in a spread / gather launch over a group's XCD-ordered
+// list of kXcds runs of `per` entries. Blocks go to the chip's XCDs round
+// robin (block b to XCD b mod kXcds), so XCD x takes run x, which holds whole
+// systems: the neighbouring bins of a system share that XCD's L2, which then
+// serves the halos their tiles have in common. (-1, -1) marks padding.
+__device__ __forceinline__ int2 xcd_item(const int2* __restrict__ items, int per) {
+    return items[(int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds)];
+}
+
 // Spread (eq. spread): one block per bin of T^3 grid cells. The block
 // accumulates its particles' P^3 windows into an LDS tile of E^3 points
 // (E = T + P - 1 + (P odd)) and stores the whole tile, halo included, to the
@@ -518,33 +523,44 @@ __device__ __forceinline__ int wrap_near(int g, int n) {
 // bins are summed when the forward FFT loads its planes (fold_point), so no
 // global atomics are needed.
 //
-// LDS accumulator: FP32 systems accumulate in 64-bit fixed point (ds_add_u64;
-// LDS float atomics are ~20x slower than 64-bit integer ones on gfx950, and
-// integer sums are order-independent, so the spread is deterministic). Each
-// contribution q w_x w_y w_z is scaled by the system's 2^F and converted to
-// an int32 (an error of at most one unit 2^-F per term); the tile is converted
-// back to float when stored. FP64 systems
-// accumulate with ds_add_f64.
-template <typename R> struct SpreadAcc {
+// LDS accumulator. FP32 systems accumulate in fixed point (LDS float atomics
+// are ~40x slower than integer ones on gfx950, and integer sums are
+// order-independent, so the spread is deterministic):
+//   * windows up to P = 6 (tol >= 1e-4): 32-bit (ds_add_u32, about 1.45x the
+//     rate of 64-bit adds, and half the LDS, so twice the blocks per CU).
+//     A bin of `count` particles takes the scale 2^F / 2^ceil(log2 count):
+//     no point can then collect more than 2^30 in magnitude, and each term,
+//     rounded to the nearest unit, is kept to about 2^-20 of the largest
+//     single term (a few 1e-7 of the grid values, below FP32 rounding of the
+//     later stages times the tolerance);
+//   * wider windows (tol < 1e-4): 64-bit (ds_add_u64) with the system's scale
+//     2^F, every term below 2^30 and truncated toward zero (a bias below one
+//     unit, ~1e-9 of the largest term).
+// The tile goes back to float when stored. FP64 systems accumulate with
+// ds_add_f64.
+template <typename R, int P> struct SpreadAcc {
     using type = R;
 };
-template <> struct SpreadAcc<float> {
-    using type = unsigned long long;
+template <int P> struct SpreadAcc<float, P> {
+    using type = typename std::conditional<(P <= 6), unsigned, unsigned long long>::type;
 };
 
 template <typename R, int P>
-__global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
-    using A = typename SpreadAcc<R>::type;
+__global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                           int per) {
+    using A = typename SpreadAcc<R, P>::type;
     constexpr bool kFixed = !std::is_floating_point<A>::value;
+    constexpr bool kNarrow = sizeof(A) == 4 && kFixed;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
-    const int2 wi = items[blockIdx.x];
+    const int2 wi = xcd_item(items, per);
+    if (wi.x < 0) return;
     const SysDesc& S = sys[wi.x];
     const int t = wi.y;
     const int lo = -((P - 1) / 2);
     const int E = S.E, E3 = E * E * E;
     const int beg = S.bin_start[t], end = S.bin_start[t + 1];
-    R* out = reinterpret_cast<R*>(S.tiles) + (long long)t * E3;
+    const auto out = gptr(reinterpret_cast<R*>(S.tiles) + (long long)t * E3);
     if (beg == end) {  // uniform over the block
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R(0);
         return;
@@ -554,14 +570,16 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
     for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
     __syncthreads();
     const int deg = S.degree;
-    const R scale = kFixed ? R(S.out[4]) : R(1);
-    const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
+    // 32-bit: the system's scale over the bin's count rounded up to a power of two
+    const R scale = !kFixed ? R(1)
+                  : kNarrow ? R(ldexp(S.out[4], -(32 - __clz((unsigned)(end - beg - 1)))))
+                            : R(S.out[4]);
     // each thread's next particle is loaded while the current one is spread
     typename Vec4<R>::type vn{};
-    if (beg + (int)threadIdx.x < end) vn = sorted[beg + threadIdx.x];
+    if (beg + (int)threadIdx.x < end) vn = gload4<R>(S.sorted, beg + threadIdx.x);
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = vn;
-        if (k + (int)blockDim.x < end) vn = sorted[k + blockDim.x];
+        if (k + (int)blockDim.x < end) vn = gload4<R>(S.sorted, k + blockDim.x);
         R w[3][P];
         int l0[3];
         windows3<R, P>(v.x, v.y, v.z, ct, deg, w, l0);
@@ -584,7 +602,9 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
                 A* row = lds + ((bx + a) * E + (by + b)) * E + bz;
 #pragma unroll
                 for (int c = 0; c < P; ++c) {
-                    if constexpr (kFixed)
+                    if constexpr (kNarrow)
+                        atomicAdd(row + c, (A)__float2int_rn(qab * w[2][c]));  // two's complement
+                    else if constexpr (kFixed)
                         atomicAdd(row + c, (A)(hi | (unsigned)(int)(qab * w[2][c] + shift)));
                     else
                         atomicAdd(row + c, qab * w[2][c]);
@@ -593,7 +613,10 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
         }
     }
     __syncthreads();
-    if constexpr (kFixed) {
+    if constexpr (kNarrow) {
+        const R inv = R(1) / scale;
+        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((double)(int)lds[i] * (double)inv);
+    } else if constexpr (kFixed) {
         const R inv = R(1) / scale;
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((double)(long long)lds[i] * (double)inv);
     } else {
@@ -620,27 +643,37 @@ __global__ void __launch_bounds__(256) k_fold(const SysDesc* __restrict__ sys, c
 }
 
 // The E^3 window tile of a bin (origin ox, oy, oz, periodic) from a grid
-// stored n x n x (n + 2): 32-lane groups walk the E^2 rows of the tile, lane
-// c < E loads element c of a row (E <= 28).
+// stored n x n x (n + 2) (E <= 28): element r E + c of the tile, row
+// r = a E + b, is grid point (ox + a, oy + b, oz + c) mod n. The E^2 row
+// offsets go to `rows` (LDS) first. Then the first floor(blockDim / E) E
+// threads each own one column c = tid mod E, whose periodic z offset they
+// compute once, and walk the rows r = tid / E, + floor(blockDim / E), ...,
+// four loads in flight. Starts and ends with a block barrier.
 template <typename R>
-__device__ __forceinline__ void load_tile(R* __restrict__ lds, const R* __restrict__ g, int n, int E, int ox, int oy,
-                                          int oz) {
-    const int rl = n + 2;
-    const int c = threadIdx.x & 31;
-    const int gz = wrap_near(oz + c, n);
-    const int rstep = blockDim.x >> 5;
-    int r = threadIdx.x >> 5, a = r / E, b = r - a * E;
-    for (; r < E * E; r += rstep) {
-        if (c < E) {
-            const int gx = wrap_near(ox + a, n), gy = wrap_near(oy + b, n);
-            lds[r * E + c] = g[((long long)gx * n + gy) * rl + gz];
-        }
-        b += rstep;
-        while (b >= E) {
-            b -= E;
-            ++a;
-        }
+__device__ __forceinline__ void load_tile(R* __restrict__ lds, int* __restrict__ rows, const R* __restrict__ g, int n,
+                                          int E, int ox, int oy, int oz) {
+    const int rl = n + 2, E2 = E * E;
+    for (int r = threadIdx.x; r < E2; r += blockDim.x) {
+        const int a = r / E, b = r - a * E;
+        rows[r] = (wrap_near(ox + a, n) * n + wrap_near(oy + b, n)) * rl;
     }
+    __syncthreads();
+    const int rstep = blockDim.x / E;
+    const int r0 = threadIdx.x / E, c = threadIdx.x - r0 * E;
+    if (r0 < rstep) {
+        const unsigned zoff = (unsigned)wrap_near(oz + c, n);
+        const auto gg = gptr(g);
+        int r = r0;
+        for (; r + 3 * rstep < E2; r += 4 * rstep) {
+            R v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = gg[(unsigned)rows[r + u * rstep] + zoff];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) lds[(r + u * rstep) * E + c] = v[u];
+        }
+        for (; r < E2; r += rstep) lds[r * E + c] = gg[(unsigned)rows[r] + zoff];
+    }
+    __syncthreads();
 }
 
 // Gather with ik forces (Methods, force paragraph): four passes over the
@@ -651,8 +684,8 @@ __device__ __forceinline__ void load_tile(R* __restrict__ lds, const R* __restri
 // fractional coordinates and F = -q H^-T g, accumulated over the passes (H^-1
 // upper triangular: pass d adds to components d and beyond).
 template <typename R, int P>
-__device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __restrict__ ct, int ox, int oy, int oz,
-                          int beg, int end) {
+__device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, int* __restrict__ rows, const R* __restrict__ ct,
+                          int ox, int oy, int oz, int beg, int end) {
     const int n = S.n, E = S.E, deg = S.degree;
     const long long G = (long long)n * n * (n + 2);
     const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
@@ -668,8 +701,7 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __rest
         const R* src = pass == 0 ? reinterpret_cast<const R*>(S.grid)
                                  : reinterpret_cast<const R*>(S.grad) + (pass - 1) * G;
         __syncthreads();
-        load_tile<R>(lds, src, n, E, ox, oy, oz);
-        __syncthreads();
+        load_tile<R>(lds, rows, src, n, E, ox, oy, oz);
         for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
             const typename Vec4<R>::type v = sorted[k];
             R w[3][P];
@@ -713,10 +745,12 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, const R* __rest
 // Gather (eq. interp) with analytic window derivatives (AD forces):
 // phi_i = u~_i - q_i S(0), F_i = -q_i (n/L) grad_u u~_i, written in caller order.
 template <typename R, int P>
-__global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items) {
+__global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                                           int per) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* lds = reinterpret_cast<R*>(smem_raw);
-    const int2 wi = items[blockIdx.x];
+    const int2 wi = xcd_item(items, per);
+    if (wi.x < 0) return;
     const SysDesc& S = sys[wi.x];
     const int t = wi.y, T = S.T, t1 = S.tiles1, n = S.n;
     int tx, ty, tz;
@@ -726,25 +760,42 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     const int ox = tx * T + lo, oy = ty * T + lo, oz = tz * T + lo;
     const int beg = S.bin_start[t], end = S.bin_start[t + 1];
     if (beg == end) return;
+    // LDS: the tile, the window coefficients and their derivatives, the
+    // tile's row offsets
     R* ct = reinterpret_cast<R*>(smem_raw + (((size_t)E3 * sizeof(R) + 15) & ~size_t(15)));
     R* ctd = ct + 17 * P;
+    int* rows = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(ct) + kCoefBytes);
     stage_coef<R, P>(ct, ctd, reinterpret_cast<const R*>(S.poly), S.degree);
     if (S.ik) {  // uniform over the block
-        gather_ik<R, P>(S, lds, ct, ox, oy, oz, beg, end);
+        gather_ik<R, P>(S, lds, rows, ct, ox, oy, oz, beg, end);
         return;
     }
-    load_tile<R>(lds, reinterpret_cast<const R*>(S.grid), n, E, ox, oy, oz);
-    __syncthreads();
+    // each thread's first particle and its caller index load during the
+    // tile's load, the next ones while the current particle is gathered
+    using V = typename Vec4<R>::type;
+    const int BD = blockDim.x;
+    int k = beg + threadIdx.x;
+    V vn{};
+    int on = 0;
+    if (k < end) {
+        vn = gload4<R>(S.sorted, k);
+        on = gptr(S.perm)[k];
+    }
+    load_tile<R>(lds, rows, reinterpret_cast<const R*>(S.grid), n, E, ox, oy, oz);
     const int deg = S.degree;
     const R scx = R(S.n) * R(S.inv_L), scy = R(S.n) * R(S.inv_Ly), scz = R(S.n) * R(S.inv_Lz);
     // grad_r = n H^-T grad_u: the off-diagonal terms of a triclinic cell (0 otherwise)
     const R sxy = R(S.n) * R(S.ixy), sxz = R(S.n) * R(S.ixz), syz = R(S.n) * R(S.iyz);
     const R s0 = R(S.s0);
-    const typename Vec4<R>::type* sorted = reinterpret_cast<const typename Vec4<R>::type*>(S.sorted);
-    R* phi = reinterpret_cast<R*>(S.phi);
-    R* F = reinterpret_cast<R*>(S.F);
-    for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
-        const typename Vec4<R>::type v = sorted[k];
+    const auto phi = gptr(reinterpret_cast<R*>(S.phi));
+    const auto F = gptr(reinterpret_cast<R*>(S.F));
+    for (; k < end; k += BD) {
+        const V v = vn;
+        const int o = on;
+        if (k + BD < end) {
+            vn = gload4<R>(S.sorted, k + BD);
+            on = gptr(S.perm)[k + BD];
+        }
         R w[3][P], dw[3][P];
         int l0[3];
         windows3_d<R, P>(v.x, v.y, v.z, ct, ctd, deg, w, dw, l0);
@@ -780,9 +831,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
             gys += sdy * wx[a];
             gzs += sdz * wx[a];
         }
-        const int o = S.perm[k];
-        typename Vec4<R>::type l = {0, 0, 0, 0};  // local part (k_local)
-        if (S.local) l = reinterpret_cast<const typename Vec4<R>::type*>(S.loc)[k];
+        V l = {0, 0, 0, 0};  // local part (k_local)
+        if (S.local) l = gload4<R>(S.loc, k);
         if (phi) phi[o] = u - v.w * s0 + l.x;
         if (F) {
             F[3LL * o + 0] = -v.w * scx * gxs + l.y;
@@ -1084,7 +1134,7 @@ template <typename R, int P>
 static hipError_t spread_p(const Launch& L, const Group& G) {
     hipError_t e = allow_lds(k_spread<R, P>, G.lds_spread);
     if (e != hipSuccess) return e;
-    k_spread<R, P><<<G.count, kSpreadThreads, G.lds_spread, L.stream>>>(L.sys, L.titems + G.off);
+    k_spread<R, P><<<G.count, kSpreadThreads, G.lds_spread, L.stream>>>(L.sys, L.xitems + G.off, G.count / kXcds);
     return hipGetLastError();
 }
 
@@ -1092,7 +1142,7 @@ template <typename R, int P>
 static hipError_t gather_p(const Launch& L, const Group& G) {
     hipError_t e = allow_lds(k_gather<R, P>, G.lds_gather);
     if (e != hipSuccess) return e;
-    k_gather<R, P><<<G.count, kGatherThreads, G.lds_gather, L.stream>>>(L.sys, L.titems + G.off);
+    k_gather<R, P><<<G.count, kGatherThreads, G.lds_gather, L.stream>>>(L.sys, L.xitems + G.off, G.count / kXcds);
     return hipGetLastError();
 }
 

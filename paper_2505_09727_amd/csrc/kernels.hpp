@@ -9,10 +9,10 @@ namespace esp {
 // Systems sharing one window width P: one spread and one gather launch.
 struct Group {
     int P;
-    int off;         // first bin work item of the group
-    int count;       // bin work items
-    int lds_spread;  // LDS bytes per spread block, E^3 64-bit accumulators
-    int lds_gather;  // LDS bytes per gather block, E^3 reals
+    int off;         // first entry of the group in the XCD-ordered bin list
+    int count;       // its entries: kXcds runs of count / kXcds, padding (-1, -1) included
+    int lds_spread;  // LDS bytes per spread block: E^3 accumulators, coefficients
+    int lds_gather;  // LDS bytes per gather block: E^3 reals, coefficients, E^2 row offsets
 };
 
 // One launch set: the device descriptor table of the active systems, the
@@ -27,6 +27,7 @@ struct Launch {
     int n_pitems;
     const int2* titems;   // bins, grouped by P
     int n_titems;
+    const int2* xitems;   // the same bins per group in XCD order, for the spread and the gather
     const int2* planes;   // (sys, x), grouped by grid size
     int n_planes;
     const int4* cols;     // (sys, first column, columns, 0), grouped by grid size

@@ -55,6 +55,12 @@ struct esp_plan {
     double* d_out = nullptr;   // kOutDoubles per system, contiguous
     hipStream_t stream = nullptr;  // where work is enqueued: the caller's or `own`
     hipStream_t own = nullptr;     // created by the plan when the caller gave none
+    // FFT groups (grid sizes) after the first run on side streams, forked
+    // from and joined back into `stream` with events, so that the groups'
+    // passes overlap on the device (in a captured graph: parallel branches)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t fork = nullptr;
     double* h_out = nullptr;   // pinned copy of d_out
     // caller buffers the descriptors currently point to
     const void* io_pos = nullptr;
@@ -80,6 +86,12 @@ struct esp_plan {
             if (d_out) (void)hipFree(d_out);
         }
         if (h_out) (void)hipHostFree(h_out);
+        for (hipStream_t s : side) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        for (hipEvent_t e : side_done) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
         if (own) (void)hipStreamDestroy(own);
     }
 };
@@ -135,6 +147,17 @@ esp_status assemble(esp_plan* p) {
     std::string msg;
     esp_status st = p->ls.build(p->slots, p->prec, p->stream, msg);
     if (st != ESP_OK) return fail(st, msg);
+    // side streams for the FFT groups after the first
+    const size_t nside = p->ls.fft_groups().size() > 1 ? p->ls.fft_groups().size() - 1 : 0;
+    if (nside && !p->fork) HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+    while (p->side.size() < nside) {
+        hipStream_t s = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        p->side.push_back(s);
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->side_done.push_back(e);
+    }
     HIP_TRY(hipStreamSynchronize(p->stream));
     return ESP_OK;
 }
@@ -268,6 +291,25 @@ esp_status enqueue(esp_plan* p, double* E_dev, int upto, const void* grid_in) {
             HIP_TRY(launch_fold(p->ls.launch()));
             return ESP_OK;
         }
+    }
+    const std::vector<FftGroup>& fg = p->ls.fft_groups();
+    if (!grid_in && upto == 0 && fg.size() > 1 && p->side.size() + 1 >= fg.size()) {
+        // the grid-size groups' three passes each, concurrently: group g
+        // (largest work first, as assembled) on side stream g - 1
+        HIP_TRY(hipEventRecord(p->fork, p->stream));
+        for (size_t g = 1; g < fg.size(); ++g) HIP_TRY(hipStreamWaitEvent(p->side[g - 1], p->fork, 0));
+        for (size_t g = 0; g < fg.size(); ++g) {
+            Launch Lg = p->ls.launch();
+            Lg.stream = g == 0 ? p->stream : p->side[g - 1];
+            for (int pass = 0; pass < 3; ++pass) HIP_TRY(launch_fft(Lg, fg[g], pass, 0, pass == 2 ? E_dev : nullptr));
+        }
+        for (size_t g = 1; g < fg.size(); ++g) {
+            HIP_TRY(hipEventRecord(p->side_done[g - 1], p->side[g - 1]));
+            HIP_TRY(hipStreamWaitEvent(p->stream, p->side_done[g - 1], 0));
+        }
+        for (int ph = kGather; ph <= kFinalize; ++ph)
+            if ((s = run_phase(p, ph, E_dev, 0)) != ESP_OK) return s;
+        return ESP_OK;
     }
     const int xmode = upto == 2 ? 1 : upto == 3 ? 2 : 0;
     if ((s = run_phase(p, kFftZY, E_dev, (grid_in ? 3 : 0) | (xmode << 2))) != ESP_OK) return s;

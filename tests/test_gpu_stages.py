@@ -11,7 +11,9 @@ Bars. Grid: the window polynomials are fitted to within delta = 0.05 tol
 of the window's peak w0 on each piece, so one term q w_x w_y w_z is off by
 at most about 3 delta w0^2 |q|, and b_l by at most 0.15 tol w0^3 A_l with
 A_l the sum of |q_j| over the particles whose window covers point l; every
-grid value is held to that bound (plus 1e-6 max |b| for FP32 rounding).
+grid value is held to that bound, plus half the fixed-point unit of each
+covering particle's bin (32-bit accumulation, P <= 6), plus 1e-6 max |b| for
+FP32 rounding.
 Gather: every particle's potential and force within 10 tol of the RMS value
 (the element-wise bar of the end-to-end tests), and the RMS error within
 tol."""
@@ -64,6 +66,29 @@ def _coverage(pr, q, L, n, P, c1):
     return np.bincount(flat.ravel(), weights=w.ravel(), minlength=n ** 3).reshape(n, n, n), float(psi(np.zeros(1))[0])
 
 
+def _quantum(pr, q, L, n, P, c1, T, w0):
+    """Bound of the 32-bit fixed-point accumulation of windows up to P = 6:
+    every term is rounded to the unit of its bin, 2^ceil(log2 count) times
+    the system's unit 2^(ceil(log2(max|q| w0^3)) - 30) (w0^3 the window
+    polynomials' peak cubed, here the PSWF window's; the fitted polynomials'
+    peak is within 0.05 tol of it), so point l is off by at most half a unit
+    per covering particle."""
+    if P > 6:
+        return 0.0
+    u = np.mod(pr, L) * (n / L)
+    t1 = n // T
+    cell = np.minimum(np.floor(u).astype(np.int64), n - 1) // T
+    b = (cell[:, 0] * t1 + cell[:, 1]) * t1 + cell[:, 2]
+    count = np.bincount(b, minlength=t1 ** 3)[b]
+    # the fitted peak may exceed w0^3 by a hair: one more power of two covers it
+    unit = 2.0 ** (np.ceil(np.log2(count)) + np.ceil(np.log2(np.max(np.abs(q)) * w0 ** 3)) + 1 - 30)
+    psi = pswf(c1)
+    idx = [window(u[:, d], P, n, psi)[0] for d in range(3)]
+    flat = (idx[0][:, :, None, None] * n + idx[1][:, None, :, None]) * n + idx[2][:, None, None, :]
+    w = np.broadcast_to(0.5 * unit[:, None, None, None], flat.shape)
+    return np.bincount(flat.ravel(), weights=w.ravel(), minlength=n ** 3).reshape(n, n, n)
+
+
 def _tensors(pos, q):
     return (torch.tensor(pos, dtype=torch.float32, device=DEV), torch.tensor(q, dtype=torch.float32, device=DEV))
 
@@ -78,8 +103,9 @@ def test_spread_grid_full_size(case, degree):
     tp, tq = _tensors(pos, q)
     A, w0 = _coverage(pr, q, c["L"], n, p.P, p.c1)
     scale = 0.15 * c["tol"] if degree == 0 else 2e-6
-    bound = scale * w0 ** 3 * A + 1e-6 * np.max(np.abs(ref["b"]))
     for T in c["tiles"]:
+        bound = (scale * w0 ** 3 * A + _quantum(pr, q, c["L"], n, p.P, p.c1, T, w0)
+                 + 1e-6 * np.max(np.abs(ref["b"])))
         plan = Plan(c["L"], len(q), c["tol"], tile=T, degree=degree or None)
         assert plan.params[0].tile == T
         print(f"{name}: spread, n={n} P={p.P} T={T} degree={plan.params[0].degree}", flush=True)
