@@ -393,10 +393,23 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     // small enough that one launch beats the chunked path's five (the
     // particle order within a bin, which is all the path changes, affects no
     // result)
+    // A block's binning time grows with its system's size, so with many
+    // systems a system above three times the median size of the candidates (and
+    // above kSmallAlwaysN) takes the chunked path, which runs beside the
+    // one-block launch, instead of finishing long after the other blocks.
+    int n_split = kSmallMaxN;
+    if (n_eligible >= kSmallMinSystems) {
+        std::vector<int> ns;
+        for (const SysDesc& d : hsys_)
+            if (d.small) ns.push_back(d.N);
+        std::nth_element(ns.begin(), ns.begin() + ns.size() / 2, ns.end());
+        n_split = std::max(kSmallAlwaysN, 3 * ns[ns.size() / 2]);
+    }
     for (int s = 0; s < nsys; ++s) {
         SysDesc& d = hsys_[s];
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
         if (n_eligible < kSmallMinSystems && d.N > kSmallAlwaysN) d.small = 0;
+        if (d.N > n_split) d.small = 0;
         if (d.small) {
             bsys_.push_back(make_int2(s, 0));
             nb_small_max = std::max(nb_small_max, nb);

@@ -1092,15 +1092,24 @@ static hipError_t allow_lds(K kernel, int bytes) {
 }
 
 template <typename R>
-static hipError_t prepare_t(const Launch& L, int phase) {
+static hipError_t bin_small_t(const Launch& L) {
+    if (L.n_small == 0) return hipSuccess;
+    hipError_t e = allow_lds(k_bin_small<R>, L.small_lds);
+    if (e != hipSuccess) return e;
+    k_bin_small<R><<<L.n_small, 1024, L.small_lds, L.stream>>>(L.sys, L.bsys, L.bpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_small(const Launch& L) {
+    return L.prec == 64 ? bin_small_t<double>(L) : bin_small_t<float>(L);
+}
+
+template <typename R>
+static hipError_t prepare_t(const Launch& L, int phase, bool with_small) {
     hipError_t e;
     switch (phase) {
         case 0:
-            if (L.n_small > 0) {
-                if ((e = allow_lds(k_bin_small<R>, L.small_lds)) != hipSuccess) return e;
-                k_bin_small<R><<<L.n_small, 1024, L.small_lds, L.stream>>>(L.sys, L.bsys, L.bpart);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-            }
+            if (with_small && (e = bin_small_t<R>(L)) != hipSuccess) return e;
             if (L.n_large == 0) break;
             if ((e = allow_lds(k_hist<R>, L.hist_lds)) != hipSuccess) return e;
             k_hist<R><<<L.n_pitems, kChunkThreads, L.hist_lds, L.stream>>>(L.sys, L.pitems, L.bpart);
@@ -1126,8 +1135,8 @@ static hipError_t prepare_t(const Launch& L, int phase) {
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Launch& L, int phase) {
-    return L.prec == 64 ? prepare_t<double>(L, phase) : prepare_t<float>(L, phase);
+hipError_t launch_prepare(const Launch& L, int phase, bool with_small) {
+    return L.prec == 64 ? prepare_t<double>(L, phase, with_small) : prepare_t<float>(L, phase, with_small);
 }
 
 template <typename R, int P>

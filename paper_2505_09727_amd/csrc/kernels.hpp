@@ -87,8 +87,11 @@ inline int fft_fused_lds(int n, int prec) {
 }
 
 // Preparation phases: 0 per-chunk bin histograms, 1 scan, 2 scatter into
-// bin order and deal each bin into LDS bank classes.
-hipError_t launch_prepare(const Launch& L, int phase);
+// bin order and deal each bin into LDS bank classes. Phase 0 also bins the
+// systems binned by one block (k_bin_small) unless with_small is false, in
+// which case launch_bin_small does that, say on another stream.
+hipError_t launch_prepare(const Launch& L, int phase, bool with_small = true);
+hipError_t launch_bin_small(const Launch& L);
 hipError_t launch_spread(const Launch& L, const Group& G);
 // Diagnostics: fold the spread tiles into the real grid.
 hipError_t launch_fold(const Launch& L);

@@ -147,8 +147,11 @@ esp_status assemble(esp_plan* p) {
     std::string msg;
     esp_status st = p->ls.build(p->slots, p->prec, p->stream, msg);
     if (st != ESP_OK) return fail(st, msg);
-    // side streams for the FFT groups after the first
-    const size_t nside = p->ls.fft_groups().size() > 1 ? p->ls.fft_groups().size() - 1 : 0;
+    // side streams: one per FFT group after the first, and one for the
+    // one-block binning when the chunked binning runs beside it
+    const Launch& L = p->ls.launch();
+    const size_t nside = std::max<size_t>(p->ls.fft_groups().size() > 1 ? p->ls.fft_groups().size() - 1 : 0,
+                                          L.n_small > 0 && L.n_large > 0 ? 1 : 0);
     if (nside && !p->fork) HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
     while (p->side.size() < nside) {
         hipStream_t s = nullptr;
@@ -285,7 +288,22 @@ esp_status enqueue(esp_plan* p, double* E_dev, int upto, const void* grid_in) {
                                (size_t)r.nf * r.nf * (r.nf + 2) * (p->prec == 64 ? 8 : 4), hipMemcpyDeviceToDevice,
                                p->stream));
     } else {
-        for (int ph = kHist; ph <= kSpread; ++ph)
+        const Launch& L = p->ls.launch();
+        int ph = kHist;
+        if (L.n_small > 0 && L.n_large > 0 && !p->side.empty()) {
+            // the one-block binning of the small systems on a side stream,
+            // beside the chunked binning of the others
+            HIP_TRY(hipEventRecord(p->fork, p->stream));
+            HIP_TRY(hipStreamWaitEvent(p->side[0], p->fork, 0));
+            Launch Ls = L;
+            Ls.stream = p->side[0];
+            HIP_TRY(launch_bin_small(Ls));
+            HIP_TRY(hipEventRecord(p->side_done[0], p->side[0]));
+            for (int q = 0; q < 3; ++q) HIP_TRY(launch_prepare(L, q, false));
+            HIP_TRY(hipStreamWaitEvent(p->stream, p->side_done[0], 0));
+            ph = kLocal;
+        }
+        for (; ph <= kSpread; ++ph)
             if ((s = run_phase(p, ph, E_dev, 0)) != ESP_OK) return s;
         if (upto == 1) {
             HIP_TRY(launch_fold(p->ls.launch()));
