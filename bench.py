@@ -586,6 +586,7 @@ def ensemble_headline(args, seed=4):
     default_tiles = Counter(p.tile for p in plan.params)
     grids = sorted({p.nf for p in plan.params})
     plan.set_graph(not args.no_graph)
+    _time_on(st, plan, pos, q, phi, F, 3)  # capture and first replays, untimed
     ms_default = _time_on(st, plan, pos, q, phi, F, 20)
     t0 = time.perf_counter()
     tiles = plan.autotune(pos, q, phi, F, reps=3)

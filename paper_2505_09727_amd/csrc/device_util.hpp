@@ -23,6 +23,21 @@ template <typename T> __device__ __forceinline__ const __attribute__((address_sp
 template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
+// Element k of a global array of complex values, loaded / stored.
+template <typename R>
+__device__ __forceinline__ cplx<R> gload_c(const cplx<R>* p, long long k) {
+    typedef R e2 __attribute__((ext_vector_type(2)));
+    const e2 v = gptr(reinterpret_cast<const e2*>(p))[k];
+    return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void gstore_c(cplx<R>* p, long long k, cplx<R> v) {
+    typedef R e2 __attribute__((ext_vector_type(2)));
+    e2 w;
+    w.x = v.x;
+    w.y = v.y;
+    gptr(reinterpret_cast<e2*>(p))[k] = w;
+}
 // Element k of a global array of 4-vectors.
 template <typename R>
 __device__ __forceinline__ typename Vec4<R>::type gload4(const void* p, long long k) {
@@ -204,11 +219,10 @@ struct CoverTab {
 };
 
 __device__ __forceinline__ void build_cover(CoverTab* tab, const SysDesc& S, int lo) {
-    for (int g = threadIdx.x; g < S.n; g += blockDim.x) {
-        CoverTab c;
-        c.cnt = covering(g, lo, S.T, S.tiles1, S.n, S.E, c.bin, c.off);
-        tab[g] = c;
-    }
+    // written in place (a private CoverTab indexed at run time would live in
+    // scratch memory)
+    for (int g = threadIdx.x; g < S.n; g += blockDim.x)
+        tab[g].cnt = covering(g, lo, S.T, S.tiles1, S.n, S.E, tab[g].bin, tab[g].off);
 }
 
 // b_l for one grid point, summed over every bin tile that covers it.

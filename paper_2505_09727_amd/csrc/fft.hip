@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __
     } else {
         for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
             const int r = idx / N, z = idx - r * N;
-            buf[r * (N + 1) + z] = {plane[(2 * r) * RL + z], plane[(2 * r + 1) * RL + z]};
+            buf[r * (N + 1) + z] = {gptr(plane)[(2 * r) * RL + z], gptr(plane)[(2 * r + 1) * RL + z]};
         }
     }
     __syncthreads();
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_fwd_zy(const SysDesc* __
     }
     fft_ct<R, N, 1, HS, 1, HS, BD, true, +1>(buf, tw);
     cplx<R>* gp = reinterpret_cast<cplx<R>*>(plane);
-    for (int idx = threadIdx.x; idx < N * HS; idx += BD) gp[idx] = buf[idx];
+    for (int idx = threadIdx.x; idx < N * HS; idx += BD) gstore_c(gp, idx, buf[idx]);
 }
 
 // Spectral derivative factor of one axis for index k of an n-point
@@ -248,7 +248,7 @@ __device__ __forceinline__ void inv_yz_plane(cplx<R>* __restrict__ buf, const cp
     constexpr int HS = N / 2 + 1, RL = N + 2, HALF = N / 2;
     const cplx<R>* gp = reinterpret_cast<const cplx<R>*>(src);
     for (int idx = threadIdx.x; idx < N * HS; idx += BD) {
-        cplx<R> v = gp[idx];
+        cplx<R> v = gload_c(gp, idx);
         if (deriv >= 2) {
             const int ky = idx / HS, kz = idx - ky * HS;
             const R d = deriv == 2 ? ik_factor<R, N>(ky, inv_L) : ik_factor<R, N>(kz, inv_L);
@@ -291,8 +291,8 @@ __device__ __forceinline__ void inv_yz_plane(cplx<R>* __restrict__ buf, const cp
     for (int idx = threadIdx.x; idx < HALF * N; idx += BD) {
         const int r = idx / N, z = idx - r * N;
         const cplx<R> v = buf[r * (N + 1) + z];
-        dst[(2 * r) * RL + z] = v.x;
-        dst[(2 * r + 1) * RL + z] = v.y;
+        gptr(dst)[(2 * r) * RL + z] = v.x;
+        gptr(dst)[(2 * r + 1) * RL + z] = v.y;
     }
 }
 
@@ -363,15 +363,15 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
     cplx<R>* gp = reinterpret_cast<cplx<R>*>(S.grid) + c0;
     for (int idx = threadIdx.x; idx < N * C; idx += BD) {
         const int x = idx / C, l = idx - x * C;
-        buf[idx] = l < cnt ? gp[(long long)x * ROW + l] : cplx<R>{R(0), R(0)};
+        buf[idx] = l < cnt ? gload_c(gp, (long long)x * ROW + l) : cplx<R>{R(0), R(0)};
     }
     __syncthreads();
     fft_ct<R, N, 1, C, 1, C, BD, true, +1>(buf, tw);
     double e = 0.0;
     if (mode != 1) {
-        const R* TS = reinterpret_cast<const R*>(S.TS);
-        const R* Tp = reinterpret_cast<const R*>(S.Tphi);
-        const R* p3 = reinterpret_cast<const R*>(S.p3);  // non-cubic box: the whole table
+        const auto TS = gptr(reinterpret_cast<const R*>(S.TS));
+        const auto Tp = gptr(reinterpret_cast<const R*>(S.Tphi));
+        const auto p3 = gptr(reinterpret_cast<const R*>(S.p3));  // non-cubic box: the whole table
         const R ps = R(S.pscale);
         for (int idx = threadIdx.x; idx < N * C; idx += BD) {
             const int x = idx / C, l = idx - x * C;
@@ -398,13 +398,13 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
     }
     for (int idx = threadIdx.x; idx < N * C; idx += BD) {
         const int x = idx / C, l = idx - x * C;
-        if (l < cnt) gp[(long long)x * ROW + l] = buf[idx];
+        if (l < cnt) gstore_c(gp, (long long)x * ROW + l, buf[idx]);
     }
     if (ik) {
         cplx<R>* gx = reinterpret_cast<cplx<R>*>(S.grad) + c0;
         for (int idx = threadIdx.x; idx < N * C; idx += BD) {
             const int x = idx / C, l = idx - x * C;
-            if (l < cnt) gx[(long long)x * ROW + l] = bufx[idx];
+            if (l < cnt) gstore_c(gx, (long long)x * ROW + l, bufx[idx]);
         }
     }
     const double tot = block_sum(e, red);
