@@ -418,8 +418,8 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         }
     }
     // FFT work items grouped by (grid size, path): one launch per group and
-    // pass, largest grids first (the plan runs the groups concurrently, the
-    // first on its own stream). Systems that ask for the one-block transform
+    // pass, largest grids first (dealt to the pipeline lanes in that order).
+    // Systems that ask for the one-block transform
     // and whose half spectrum fits in LDS take it; their energy partial goes
     // to one slot after the x-column items.
     std::map<std::pair<int, int>, std::vector<int>> by_n;
@@ -459,59 +459,87 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
         fg.sys_count = (int)fsys_.size() - fg.sys_off;
         fgroups_.push_back(fg);
     }
+    // lanes: FFT groups, largest grid first, each to the lane with the least
+    // work so far; work = FFT (systems x n^3 log2 n) plus spread and gather
+    // (particles), weighted as measured on MI355X (about 3.1e-6 and 1.0e-4
+    // microseconds per unit)
+    lanes_ = std::max(1, std::min<int>(kLanes, (int)fgroups_.size()));
+    std::vector<int> sys_lane(nsys, 0);
+    {
+        std::vector<double> load(lanes_, 0.0);
+        for (FftGroup& fg : fgroups_) {
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            fg.lane = l;
+            double w = 0.0;
+            const int2* it = fg.fused ? &fsys_[fg.sys_off] : &planes_[fg.plane_off];
+            const int step = fg.fused ? 1 : fg.n;  // a system's planes are consecutive
+            const int cnt = fg.fused ? fg.sys_count : fg.plane_count;
+            for (int k = 0; k < cnt; k += step) {
+                const int s = it[k].x;
+                sys_lane[s] = l;
+                w += 3.1e-6 * std::pow((double)fg.n, 3) * std::log2((double)fg.n) + 1.0e-4 * hsys_[s].N;
+            }
+            load[l] += w;
+        }
+    }
     const int n_eslots = (int)cols_.size() + (int)fused_sys.size();
     for (size_t k = 0; k < fused_sys.size(); ++k) {
         SysDesc& d = hsys_[fused_sys[k]];
         d.col_off = (int)cols_.size() + (int)k;
         d.ncol = 1;
     }
-    for (int P = 4; P <= 12; ++P) {
-        const std::vector<int2>& items = titems_by_P[P];
-        if (items.empty()) continue;
-        Group g;
-        g.P = P;
-        int E = 0;
-        for (const int2& it : items) E = std::max(E, hsys_[it.x].E);
-        // XCD order: whole systems to the XCD with the least work so far,
-        // largest first (work ~ particles plus 40 per bin for its tile), so
-        // that the XCDs finish together and a system's bins share one L2
-        std::vector<int> sys_of;  // the group's systems, in order
-        for (const int2& it : items)
-            if (sys_of.empty() || sys_of.back() != it.x) sys_of.push_back(it.x);
-        auto work = [&](int s) {
-            const SysDesc& d = hsys_[s];
-            return (double)d.N + 40.0 * d.tiles1 * d.tiles1 * d.tiles1;
-        };
-        std::stable_sort(sys_of.begin(), sys_of.end(), [&](int a, int b) { return work(a) > work(b); });
-        std::vector<std::vector<int2>> lane(kXcds);
-        std::vector<double> load(kXcds, 0.0);
-        for (int s : sys_of) {
-            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            load[x] += work(s);
-            const int nb = hsys_[s].tiles1 * hsys_[s].tiles1 * hsys_[s].tiles1;
-            for (int t = 0; t < nb; ++t) lane[x].push_back(make_int2(s, t));
+    for (int lane = 0; lane < lanes_; ++lane) {
+        for (int P = 4; P <= 12; ++P) {
+            std::vector<int2> items;  // the lane's bins of window width P
+            for (const int2& it : titems_by_P[P])
+                if (sys_lane[it.x] == lane) items.push_back(it);
+            if (items.empty()) continue;
+            Group g;
+            g.P = P;
+            g.lane = lane;
+            int E = 0;
+            for (const int2& it : items) E = std::max(E, hsys_[it.x].E);
+            // XCD order: whole systems to the XCD with the least work so far,
+            // largest first (work ~ particles plus 40 per bin for its tile), so
+            // that the XCDs finish together and a system's bins share one L2
+            std::vector<int> sys_of;  // the group's systems, in order
+            for (const int2& it : items)
+                if (sys_of.empty() || sys_of.back() != it.x) sys_of.push_back(it.x);
+            auto work = [&](int s) {
+                const SysDesc& d = hsys_[s];
+                return (double)d.N + 40.0 * d.tiles1 * d.tiles1 * d.tiles1;
+            };
+            std::stable_sort(sys_of.begin(), sys_of.end(), [&](int a, int b) { return work(a) > work(b); });
+            std::vector<std::vector<int2>> runs(kXcds);
+            std::vector<double> load(kXcds, 0.0);
+            for (int s : sys_of) {
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[x] += work(s);
+                const int nb = hsys_[s].tiles1 * hsys_[s].tiles1 * hsys_[s].tiles1;
+                for (int t = 0; t < nb; ++t) runs[x].push_back(make_int2(s, t));
+            }
+            size_t per = 0;
+            for (const auto& r : runs) per = std::max(per, r.size());
+            g.off = (int)xitems_.size();
+            g.count = (int)(per * kXcds);
+            for (auto& r : runs) {
+                r.resize(per, make_int2(-1, -1));
+                xitems_.insert(xitems_.end(), r.begin(), r.end());
+            }
+            // spread: the accumulators (32-bit fixed point for FP32 windows up
+            // to P = 6, else 64-bit fixed point or double), then the window
+            // coefficients; gather: the potential tile, the coefficients and
+            // their derivatives, the tile's E^2 row offsets
+            g.lds_spread = E * E * E * (prec == 32 && P <= 6 ? 4 : 8) + kCoefBytes;
+            g.lds_gather = ((E * E * E * rb + 15) & ~15) + kCoefBytes + E * E * 4;
+            if (g.lds_spread > kMaxLds || g.lds_gather > kMaxLds) {
+                msg = "bin tile (T+P)^3 exceeds LDS; reduce tile";
+                return ESP_E_UNSUPPORTED;
+            }
+            groups_.push_back(g);
         }
-        size_t per = 0;
-        for (const auto& l : lane) per = std::max(per, l.size());
-        g.off = (int)xitems_.size();
-        g.count = (int)(per * kXcds);
-        for (auto& l : lane) {
-            l.resize(per, make_int2(-1, -1));
-            xitems_.insert(xitems_.end(), l.begin(), l.end());
-        }
-        // spread: the accumulators (32-bit fixed point for FP32 windows up
-        // to P = 6, else 64-bit fixed point or double), then the window
-        // coefficients; gather: the potential tile, the coefficients and
-        // their derivatives, the tile's E^2 row offsets
-        g.lds_spread = E * E * E * (prec == 32 && P <= 6 ? 4 : 8) + kCoefBytes;
-        g.lds_gather = ((E * E * E * rb + 15) & ~15) + kCoefBytes + E * E * 4;
-        if (g.lds_spread > kMaxLds || g.lds_gather > kMaxLds) {
-            msg = "bin tile (T+P)^3 exceeds LDS; reduce tile";
-            return ESP_E_UNSUPPORTED;
-        }
-        titems_.insert(titems_.end(), items.begin(), items.end());
-        groups_.push_back(g);
     }
+    for (int P = 4; P <= 12; ++P) titems_.insert(titems_.end(), titems_by_P[P].begin(), titems_by_P[P].end());
     L_.prec = prec;
     L_.nsys = nsys;
     L_.any_local = any_local;

@@ -126,6 +126,11 @@ class LaunchSet {
     // Take device memory from `a` instead of allocating it (before build).
     void set_arena(FixedBlock* a) { arena_ = a; }
     const std::vector<Group>& groups() const { return groups_; }
+    // Pipeline lanes: the FFT grid-size groups, and with them their systems,
+    // are dealt to `lanes()` lanes (largest first, each to the lane with the
+    // least work so far), and a step may run each lane's spread, FFT passes
+    // and gather on a stream of its own. 1 when there is one FFT group.
+    int lanes() const { return lanes_; }
     const std::vector<FftGroup>& fft_groups() const { return fgroups_; }
     int nsys() const { return (int)hsys_.size(); }
     const SysDesc& desc(int s) const { return hsys_[s]; }
@@ -139,6 +144,7 @@ class LaunchSet {
     Launch L_{};
     std::vector<Group> groups_;
     std::vector<FftGroup> fgroups_;
+    int lanes_ = 1;
     std::vector<SysDesc> hsys_;
     std::vector<int2> pitems_, titems_, xitems_, planes_, fsys_, bsys_, litems_;
     std::vector<int4> cols_;
@@ -152,5 +158,9 @@ class LaunchSet {
 };
 
 constexpr int kMaxLds = 160 * 1024;
+// Pipeline lanes of a launch set with several FFT grid-size groups: the
+// plan's stream and two side streams, which (with the binning's side stream
+// reused) fit the 4 hardware queues a process gets by default.
+constexpr int kLanes = 3;
 
 }  // namespace esp

@@ -6,9 +6,11 @@
 
 namespace esp {
 
-// Systems sharing one window width P: one spread and one gather launch.
+// Systems of one lane sharing one window width P: one spread and one gather
+// launch.
 struct Group {
     int P;
+    int lane;        // the pipeline lane of its systems
     int off;         // first entry of the group in the XCD-ordered bin list
     int count;       // its entries: kXcds runs of count / kXcds, padding (-1, -1) included
     int lds_spread;  // LDS bytes per spread block: E^3 accumulators, coefficients
@@ -54,6 +56,7 @@ struct Launch {
 // Systems sharing one grid size n: one launch per FFT pass.
 struct FftGroup {
     int n;
+    int lane;                    // the pipeline lane of its systems
     int fused;                   // 1: one block per system for the whole transform
     int plane_off, plane_count;  // x-plane work items (three-pass path)
     int col_off, col_count;      // x-column chunk work items (three-pass path)

@@ -147,11 +147,10 @@ esp_status assemble(esp_plan* p) {
     std::string msg;
     esp_status st = p->ls.build(p->slots, p->prec, p->stream, msg);
     if (st != ESP_OK) return fail(st, msg);
-    // side streams: one per FFT group after the first, and one for the
+    // side streams: one per pipeline lane after the first, and one for the
     // one-block binning when the chunked binning runs beside it
     const Launch& L = p->ls.launch();
-    const size_t nside = std::max<size_t>(p->ls.fft_groups().size() > 1 ? p->ls.fft_groups().size() - 1 : 0,
-                                          L.n_small > 0 && L.n_large > 0 ? 1 : 0);
+    const size_t nside = std::max<size_t>((size_t)p->ls.lanes() - 1, L.n_small > 0 && L.n_large > 0 ? 1 : 0);
     if (nside && !p->fork) HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
     while (p->side.size() < nside) {
         hipStream_t s = nullptr;
@@ -238,13 +237,6 @@ esp_status bind_io(esp_plan* p, const void* pos, const void* q, void* phi, void*
     return ESP_OK;
 }
 
-// Streams that run the FFT grid-size groups at once in a step. With the
-// plan's stream they make 3 lanes, which with the binning's side stream
-// reused fit the 4 hardware queues a process gets by default; measured on
-// the 256-system ensemble (six grid sizes): 2 lanes 0.416-0.426 ms per step,
-// 3 lanes 0.369, one per group 0.404-0.410.
-constexpr int kFftLanes = 3;
-
 // Pipeline phases (one kernel launch each, or one per window-width group).
 enum Phase { kHist, kScan, kScatter, kLocal, kSpread, kFftZY, kFftX, kFftYZ, kGather, kFinalize, kNumPhases };
 static_assert(kNumPhases == ESP_NUM_PHASES, "esp.h's phase count must match the pipeline");
@@ -310,41 +302,35 @@ esp_status enqueue(esp_plan* p, double* E_dev, int upto, const void* grid_in) {
             HIP_TRY(hipStreamWaitEvent(p->stream, p->side_done[0], 0));
             ph = kLocal;
         }
+        const int lanes = p->ls.lanes();
+        if (upto == 0 && lanes > 1 && (int)p->side.size() >= lanes - 1) {
+            // the pipeline lanes: each runs its systems' spread, FFT passes
+            // and gather on its own stream (lane 0 the plan's, lane l side
+            // stream l - 1), forked after the binning and joined before the
+            // finalisation; launches go in phase order across the lanes
+            for (; ph <= kLocal; ++ph)
+                if ((s = run_phase(p, ph, E_dev, 0)) != ESP_OK) return s;
+            HIP_TRY(hipEventRecord(p->fork, p->stream));
+            for (int l = 1; l < lanes; ++l) HIP_TRY(hipStreamWaitEvent(p->side[l - 1], p->fork, 0));
+            std::vector<Launch> Ll(lanes, L);
+            for (int l = 1; l < lanes; ++l) Ll[l].stream = p->side[l - 1];
+            for (const Group& G : p->ls.groups()) HIP_TRY(launch_spread(Ll[G.lane], G));
+            const std::vector<FftGroup>& fg = p->ls.fft_groups();
+            for (int pass = 0; pass < 3; ++pass)
+                for (const FftGroup& G : fg) HIP_TRY(launch_fft(Ll[G.lane], G, pass, 0, pass == 2 ? E_dev : nullptr));
+            for (const Group& G : p->ls.groups()) HIP_TRY(launch_gather(Ll[G.lane], G));
+            for (int l = 1; l < lanes; ++l) {
+                HIP_TRY(hipEventRecord(p->side_done[l - 1], p->side[l - 1]));
+                HIP_TRY(hipStreamWaitEvent(p->stream, p->side_done[l - 1], 0));
+            }
+            return run_phase(p, kFinalize, E_dev, 0);
+        }
         for (; ph <= kSpread; ++ph)
             if ((s = run_phase(p, ph, E_dev, 0)) != ESP_OK) return s;
         if (upto == 1) {
             HIP_TRY(launch_fold(p->ls.launch()));
             return ESP_OK;
         }
-    }
-    const std::vector<FftGroup>& fg = p->ls.fft_groups();
-    if (!grid_in && upto == 0 && fg.size() > 1 && !p->side.empty()) {
-        // the grid-size groups' passes on kFftLanes streams at once: each
-        // group (largest first, as assembled) to the lane with the least
-        // work so far; lane 0 is the plan's stream, lane l side stream l - 1
-        const int lanes = std::min<int>(std::min<int>(kFftLanes, (int)fg.size()), (int)p->side.size() + 1);
-        std::vector<double> load(lanes, 0.0);
-        std::vector<int> lane_of(fg.size());
-        for (size_t g = 0; g < fg.size(); ++g) {
-            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            lane_of[g] = l;
-            const double n = fg[g].n, systems = fg[g].fused ? fg[g].sys_count : (double)fg[g].plane_count / n;
-            load[l] += systems * n * n * n * std::log2(n);
-        }
-        HIP_TRY(hipEventRecord(p->fork, p->stream));
-        for (int l = 1; l < lanes; ++l) HIP_TRY(hipStreamWaitEvent(p->side[l - 1], p->fork, 0));
-        for (size_t g = 0; g < fg.size(); ++g) {
-            Launch Lg = p->ls.launch();
-            Lg.stream = lane_of[g] == 0 ? p->stream : p->side[lane_of[g] - 1];
-            for (int pass = 0; pass < 3; ++pass) HIP_TRY(launch_fft(Lg, fg[g], pass, 0, pass == 2 ? E_dev : nullptr));
-        }
-        for (int l = 1; l < lanes; ++l) {
-            HIP_TRY(hipEventRecord(p->side_done[l - 1], p->side[l - 1]));
-            HIP_TRY(hipStreamWaitEvent(p->stream, p->side_done[l - 1], 0));
-        }
-        for (int ph = kGather; ph <= kFinalize; ++ph)
-            if ((s = run_phase(p, ph, E_dev, 0)) != ESP_OK) return s;
-        return ESP_OK;
     }
     const int xmode = upto == 2 ? 1 : upto == 3 ? 2 : 0;
     if ((s = run_phase(p, kFftZY, E_dev, (grid_in ? 3 : 0) | (xmode << 2))) != ESP_OK) return s;
