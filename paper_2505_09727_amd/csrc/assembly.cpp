@@ -499,24 +499,38 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             g.lane = lane;
             int E = 0;
             for (const int2& it : items) E = std::max(E, hsys_[it.x].E);
-            // XCD order: whole systems to the XCD with the least work so far,
-            // largest first (work ~ particles plus 40 per bin for its tile), so
-            // that the XCDs finish together and a system's bins share one L2
-            std::vector<int> sys_of;  // the group's systems, in order
-            for (const int2& it : items)
-                if (sys_of.empty() || sys_of.back() != it.x) sys_of.push_back(it.x);
-            auto work = [&](int s) {
-                const SysDesc& d = hsys_[s];
-                return (double)d.N + 40.0 * d.tiles1 * d.tiles1 * d.tiles1;
+            // XCD order: runs of consecutive bins of one system (neighbours,
+            // which share halo rows), at most ceil(bins / (4 kXcds)) long so
+            // that a large system spreads over every XCD, largest first to
+            // the XCD with the least work so far (work ~ particles plus 40
+            // per bin for its tile), so that the XCDs finish together and a
+            // run's halos are fetched once into one L2
+            const int cap = std::max<int>(1, (int)((items.size() + 4 * kXcds - 1) / (4 * kXcds)));
+            struct Piece {
+                int s, t0, nb;
+                double w;
             };
-            std::stable_sort(sys_of.begin(), sys_of.end(), [&](int a, int b) { return work(a) > work(b); });
+            std::vector<Piece> pieces;
+            for (size_t k = 0; k < items.size();) {
+                const int s = items[k].x;
+                size_t e = k;
+                while (e < items.size() && items[e].x == s) ++e;  // the system's bins
+                const SysDesc& d = hsys_[s];
+                const int nb = (int)(e - k);
+                const double per_bin = (double)d.N / nb + 40.0;
+                for (int t0 = 0; t0 < nb; t0 += cap) {
+                    const int m = std::min(cap, nb - t0);
+                    pieces.push_back({s, items[k].y + t0, m, per_bin * m});
+                }
+                k = e;
+            }
+            std::stable_sort(pieces.begin(), pieces.end(), [](const Piece& a, const Piece& b) { return a.w > b.w; });
             std::vector<std::vector<int2>> runs(kXcds);
             std::vector<double> load(kXcds, 0.0);
-            for (int s : sys_of) {
+            for (const Piece& pc : pieces) {
                 const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                load[x] += work(s);
-                const int nb = hsys_[s].tiles1 * hsys_[s].tiles1 * hsys_[s].tiles1;
-                for (int t = 0; t < nb; ++t) runs[x].push_back(make_int2(s, t));
+                load[x] += pc.w;
+                for (int t = 0; t < pc.nb; ++t) runs[x].push_back(make_int2(pc.s, pc.t0 + t));
             }
             size_t per = 0;
             for (const auto& r : runs) per = std::max(per, r.size());
