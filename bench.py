@@ -44,16 +44,18 @@ def _rel_rms(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
-def algorithmic_cost(phase, N, n, P, deg, prec):
+def algorithmic_cost(phase, N, n, P, deg, prec, g=None):
     """Algorithmic HBM bytes and flops of one launch of a phase for one system
-    of N particles on an n^3 grid. FMAs count 2 flops. Window weights are
+    of N particles on an n^3 grid (or, for spread and gather, N particles over
+    g grid points in all). FMAs count 2 flops. Window weights are
     Horner polynomials of degree deg (3 P deg FMAs per particle for the
     values, 3 P (deg - 1) more for the derivatives); the spread forms the P^3
     products by P^2 + P^3 multiplies; the gather contracts the P^3
     neighbourhood for the value and three derivatives in 2 P^3 + 3 P^2 + 4 P
     FMAs. The grid is written (spread) or read (gather) once."""
     rb = 8 if prec == 64 else 4
-    g = n ** 3                       # grid points
+    if g is None:
+        g = n ** 3                   # grid points
     spec = n * n * (n // 2 + 1)      # half-spectrum modes
     if phase == "spread":
         b = N * 4 * rb + g * rb                     # sorted (u, q) in, grid out
@@ -82,6 +84,7 @@ def algorithmic_cost(phase, N, n, P, deg, prec):
 # or 32 lanes of 32-bit reads per clock per CU, over 256 CUs at 2.4 GHz.
 PEAK_LDS_U64_ATOMICS_GOPS = 16 * 256 * 2.4
 PEAK_LDS_F32_READS_GOPS = 32 * 256 * 2.4
+PEAK_LDS_U32_ATOMICS_GOPS = 32 * 256 * 2.4
 
 PHASE_KERNEL = {"hist": "k_hist<float>", "scan": "k_scan", "scatter": "k_scatter<float>",
                 "spread": "k_spread<float, {P}>", "fft_zy": "k_fwd_zy<float, {n}>",
@@ -108,14 +111,16 @@ def measured_traffic(profile, kernel):
     return rec["hbm_bytes_per_dispatch"].get(kernel)
 
 
-def roofline(phase, ms, systems, prec=32, profile=None):
+def roofline(phase, ms, systems, prec=32, profile=None, points=None, blocks=None):
     """Roofline record of one launch of a phase over the systems it covers
     (list of (N, n, P, degree)); algorithmic bytes and flops from
-    algorithmic_cost, ms the measured launch time."""
+    algorithmic_cost, ms the measured launch time. With `points`, systems is
+    one entry (particles of the launch, n of its first system, P, degree) and
+    points the grid points of all its systems (spread and gather)."""
     bytes_launch = flops_launch = 0
     atoms = p3 = 0
     for (N, n, P, deg) in systems:
-        b1, f1 = algorithmic_cost(phase, N, n, P, deg, prec)
+        b1, f1 = algorithmic_cost(phase, N, n, P, deg, prec, g=points)
         bytes_launch += b1
         flops_launch += f1
         atoms += N
@@ -132,15 +137,21 @@ def roofline(phase, ms, systems, prec=32, profile=None):
     P0, n0 = systems[0][2], systems[0][1]
     kname = PHASE_KERNEL.get(phase, phase).format(P=P0, n=n0).replace("float", "double" if prec == 64 else "float")
     r["kernel_symbol"] = kname
-    r["traffic"] = measured_traffic(profile, kname) if profile else None
+    # a kernel launched more than once per step (one launch per pipeline
+    # lane) has its traffic recorded per launch, keyed by its block count
+    r["traffic"] = measured_traffic(profile, kname if blocks is None else f"{kname}#{blocks}") if profile else None
     r["avg_launch_ms"] = ms
     r["algorithmic_bytes_per_launch"] = bytes_launch
     r["algorithmic_flops_per_launch"] = flops_launch
     r["particles_per_launch"] = atoms
     if phase == "spread" and prec == 32:
         ops = p3 / t / 1e9
-        r["lds_u64_atomics"] = dict(achieved_Gops=ops, peak_Gops=PEAK_LDS_U64_ATOMICS_GOPS,
-                                    frac=ops / PEAK_LDS_U64_ATOMICS_GOPS)
+        if P0 <= 6:  # 32-bit fixed-point accumulators
+            r["lds_u32_atomics"] = dict(achieved_Gops=ops, peak_Gops=PEAK_LDS_U32_ATOMICS_GOPS,
+                                        frac=ops / PEAK_LDS_U32_ATOMICS_GOPS)
+        else:
+            r["lds_u64_atomics"] = dict(achieved_Gops=ops, peak_Gops=PEAK_LDS_U64_ATOMICS_GOPS,
+                                        frac=ops / PEAK_LDS_U64_ATOMICS_GOPS)
     if phase == "gather" and prec == 32:
         ops = p3 / t / 1e9
         r["lds_f32_reads"] = dict(achieved_Gops=ops, peak_Gops=PEAK_LDS_F32_READS_GOPS,
@@ -170,6 +181,37 @@ SINGLE_LAUNCH = ("hist", "spread", "gather")
 def dominant_roofline(phases, systems, prec=32, profile=None):
     ph = max(SINGLE_LAUNCH, key=lambda k: phases.get(k, 0.0))
     return roofline(ph, phases[ph], systems, prec, profile)
+
+
+def launch_rooflines(plan, pos, q, phi, F, reps, systems, profile, prec=32):
+    """Per-launch rooflines of the spread and the gather (a plan with several
+    pipeline lanes launches each once per (lane, P)): every launch timed on
+    its own with HIP events (esp_plan_profile_launches). Returns {phase:
+    [record per launch]}; the records carry launches_per_step."""
+    P0, deg0, n0 = systems[0][2], systems[0][3], systems[0][1]
+    out = {}
+    for ph in ("spread", "gather"):
+        ls = plan.profile_launches(pos, q, phi, F, reps, ph)
+        recs = []
+        for k, L in enumerate(ls):
+            r = roofline(ph, L["ms"], [(L["particles"], n0, P0, deg0)], prec, profile, points=L["points"],
+                         blocks=L["blocks"])
+            r["launch"] = k
+            r["launches_per_step"] = len(ls)
+            r["blocks"] = L["blocks"]
+            recs.append(r)
+        out[ph] = recs
+    return out
+
+
+def dominant_launch_roofline(phases, launches):
+    """The roofline record of the dominant kernel: among hist (one launch),
+    spread and gather, the phase with the longest time per step; for spread
+    and gather its longest launch."""
+    ph = max(SINGLE_LAUNCH, key=lambda k: phases.get(k, 0.0))
+    if ph in launches and launches[ph]:
+        return max(launches[ph], key=lambda r: r["avg_launch_ms"])
+    return None
 
 
 def _one_thread():
@@ -614,10 +656,12 @@ def ensemble_headline(args, seed=4):
     F32 = F.cpu().double().numpy()
     phases = profile_phases(plan, pos, q, phi, F, args.profile_reps)
     sysl = [(N, p.nf, p.P, p.degree) for N, p in zip(Ns, plan.params)]
-    roof = dominant_roofline(phases, sysl, 32, "esp_fp32_ensemble256")
-    if roof["kernel"] == "hist":
-        roof["kernel_symbol"] = "k_bin_small<float>"
-    kernels = {ph: roofline(ph, phases[ph], sysl, 32, "esp_fp32_ensemble256") for ph in ("spread", "gather")}
+    kernels = launch_rooflines(plan, pos, q, phi, F, args.profile_reps, sysl, "esp_fp32_ensemble256")
+    roof = dominant_launch_roofline(phases, kernels)
+    if roof is None:
+        roof = dominant_roofline(phases, sysl, 32, "esp_fp32_ensemble256")
+        if roof["kernel"] == "hist":
+            roof["kernel_symbol"] = "k_bin_small<float>"
     prm = list(plan.params)
     plan.close()
     # FP64 plain, one single-system plan after another
@@ -714,11 +758,14 @@ def water9k_run(args):
     F_all = F.cpu().double().numpy()
     phases = profile_phases(plan, pos, q, phi, F, args.profile_reps)
     sysl = [(N, prm.nf, prm.P, prm.degree)] * B
-    roof = dominant_roofline(phases, sysl, 32, "esp_fp32_water9k_b128")
-    if roof["kernel"] == "hist":
-        roof["kernel_symbol"] = "k_bin_small<float>"
-    kernels = {ph: roofline(ph, phases[ph], sysl, 32, "esp_fp32_water9k_b128")
-               for ph in ("spread", "gather", "fft_zy", "fft_x_scale", "fft_yz")}
+    kernels = launch_rooflines(plan, pos, q, phi, F, args.profile_reps, sysl, "esp_fp32_water9k_b128")
+    roof = dominant_launch_roofline(phases, kernels)
+    if roof is None:
+        roof = dominant_roofline(phases, sysl, 32, "esp_fp32_water9k_b128")
+        if roof["kernel"] == "hist":
+            roof["kernel_symbol"] = "k_bin_small<float>"
+    kernels.update({ph: roofline(ph, phases[ph], sysl, 32, "esp_fp32_water9k_b128")
+                    for ph in ("fft_zy", "fft_x_scale", "fft_yz")})
     plan.close()
     torch.cuda.synchronize()
     out["batch128_fp32"] = {"batch": B, "particle_steps_per_s": B * N / (ms / 1e3), "ms_per_step": ms,

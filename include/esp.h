@@ -348,6 +348,20 @@ esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void
 int         esp_num_phases(void);
 const char* esp_phase_name(int phase);
 
+/* Time each launch of the spread or the gather phase (phase = index of
+ * "spread" or "gather" in esp_phase_name): a plan with several pipeline
+ * lanes launches one kernel per (lane, window width) there. Runs the
+ * pipeline `reps` times on the plan's stream, the phase's launches one
+ * after another with a HIP event around each, and writes for launch k <
+ * *count (at most `max`) its mean milliseconds to ms[k], its particle count
+ * to particles[k], the grid points of its systems (sum of n^3) to points[k]
+ * and its workgroup count to blocks[k] (host arrays of `max` entries). Each
+ * timed pass follows an untimed one. ESP_E_INVALID for other phases. Waits
+ * for the stream. */
+esp_status esp_plan_profile_launches(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
+                                     int phase, int max, double* ms, int64_t* particles, int64_t* points,
+                                     int64_t* blocks, int* count);
+
 /* ---- serving: continuous batching of independent long-range solves ----
  *
  * A server owns one HIP stream, one scheduler thread and a device arena of

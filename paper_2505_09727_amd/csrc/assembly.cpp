@@ -482,6 +482,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             load[l] += w;
         }
     }
+    sys_lane_ = sys_lane;
     const int n_eslots = (int)cols_.size() + (int)fused_sys.size();
     for (size_t k = 0; k < fused_sys.size(); ++k) {
         SysDesc& d = hsys_[fused_sys[k]];

@@ -131,6 +131,7 @@ class LaunchSet {
     // least work so far), and a step may run each lane's spread, FFT passes
     // and gather on a stream of its own. 1 when there is one FFT group.
     int lanes() const { return lanes_; }
+    int lane_of(int s) const { return sys_lane_[s]; }
     const std::vector<FftGroup>& fft_groups() const { return fgroups_; }
     int nsys() const { return (int)hsys_.size(); }
     const SysDesc& desc(int s) const { return hsys_[s]; }
@@ -145,6 +146,7 @@ class LaunchSet {
     std::vector<Group> groups_;
     std::vector<FftGroup> fgroups_;
     int lanes_ = 1;
+    std::vector<int> sys_lane_;
     std::vector<SysDesc> hsys_;
     std::vector<int2> pitems_, titems_, xitems_, planes_, fsys_, bsys_, litems_;
     std::vector<int4> cols_;

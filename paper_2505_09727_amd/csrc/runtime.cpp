@@ -707,6 +707,56 @@ esp_status esp_plan_profile(esp_plan* plan, const void* pos, const void* q, void
     return s;
 }
 
+esp_status esp_plan_profile_launches(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
+                                     int phase, int max, double* ms, int64_t* particles, int64_t* points,
+                                     int64_t* blocks, int* count) {
+    if (!plan || !pos || !q || !ms || !particles || !points || !blocks || !count || reps < 1 || max < 0)
+        return fail(ESP_E_INVALID, "bad argument");
+    if (phase != kSpread && phase != kGather) return fail(ESP_E_INVALID, "phase must be spread or gather");
+    esp_status s = bind_io(plan, pos, q, phi, F);
+    if (s != ESP_OK) return s;
+    const std::vector<Group>& gs = plan->ls.groups();
+    const int ng = (int)gs.size();
+    *count = std::min(ng, max);
+    // particles and grid points of each launch: its systems' sums
+    for (int k = 0; k < *count; ++k) {
+        particles[k] = 0;
+        points[k] = 0;
+        blocks[k] = gs[k].count;  // the launch's grid (XCD-ordered list, padding included)
+    }
+    for (int s2 = 0; s2 < plan->nsys; ++s2) {
+        const SysDesc& d = plan->ls.desc(s2);
+        for (int k = 0; k < *count; ++k)
+            if (gs[k].P == d.P && gs[k].lane == plan->ls.lane_of(s2)) {
+                particles[k] += d.N;
+                points[k] += (int64_t)d.n * d.n * d.n;
+            }
+    }
+    const Launch& L = plan->ls.launch();
+    std::vector<hipEvent_t> ev(ng + 1);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    std::vector<double> acc(ng, 0.0);
+    for (int r = 0; r < reps && s == ESP_OK; ++r) {
+        for (int ph = 0; ph < kNumPhases && s == ESP_OK; ++ph) s = run_phase(plan, ph, nullptr, 0);
+        for (int ph = 0; ph < phase && s == ESP_OK; ++ph) s = run_phase(plan, ph, nullptr, 0);
+        HIP_TRY(hipEventRecord(ev[0], plan->stream));
+        for (int k = 0; k < ng; ++k) {
+            HIP_TRY(phase == kSpread ? launch_spread(L, gs[k]) : launch_gather(L, gs[k]));
+            HIP_TRY(hipEventRecord(ev[k + 1], plan->stream));
+        }
+        for (int ph = phase + 1; ph < kNumPhases && s == ESP_OK; ++ph) s = run_phase(plan, ph, nullptr, 0);
+        HIP_TRY(hipEventSynchronize(ev[ng]));
+        for (int k = 0; k < ng; ++k) {
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            acc[k] += t;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < *count; ++k) ms[k] = acc[k] / reps;
+    return s;
+}
+
 int esp_num_phases(void) { return kNumPhases; }
 
 const char* esp_phase_name(int phase) { return (phase >= 0 && phase < kNumPhases) ? kPhaseNames[phase] : ""; }

@@ -106,6 +106,8 @@ _SIGS = {
     "esp_debug_gather": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "esp_plan_profile": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, _P(C.c_double)]),
     "esp_phase_name": (C.c_char_p, [C.c_int]),
+    "esp_plan_profile_launches": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _P(C.c_double),
+                                            _P(C.c_int64), _P(C.c_int64), _P(C.c_int64), _P(C.c_int)]),
     "esp_server_create": (C.c_int, [_P(esp_server_opts), _P(_vp)]),
     "esp_server_submit": (C.c_int, [_vp, _P(esp_request), _P(C.c_uint64)]),
     "esp_server_poll": (C.c_int, [_vp, _P(esp_result), C.c_int, _P(C.c_int)]),
@@ -358,6 +360,20 @@ class Plan:
         st = lib().esp_debug_gather(self._h, _ptr(pos), _ptr(q), _ptr(grid_c), _ptr(phi), _ptr(F))
         self._order_torch_after(ext)
         _check(st)
+
+    def profile_launches(self, pos, q, phi, F, reps: int, phase: str):
+        """esp_plan_profile_launches: mean ms, particles, grid points and
+        workgroups of each launch of the "spread" or "gather" phase."""
+        names = [lib().esp_phase_name(i).decode() for i in range(lib().esp_num_phases())]
+        mx = 64
+        ms, cnt = (C.c_double * mx)(), C.c_int()
+        pa, pt, bl = (C.c_int64 * mx)(), (C.c_int64 * mx)(), (C.c_int64 * mx)()
+        ext = self._order_after_torch()
+        st = lib().esp_plan_profile_launches(self._h, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F), int(reps),
+                                             names.index(phase), mx, ms, pa, pt, bl, C.byref(cnt))
+        self._order_torch_after(ext)
+        _check(st)
+        return [dict(ms=ms[k], particles=pa[k], points=pt[k], blocks=bl[k]) for k in range(cnt.value)]
 
     def close(self):
         if self._h:

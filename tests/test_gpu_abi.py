@@ -90,6 +90,34 @@ def test_batch_longrange_matches_single_systems():
     batch.close()
 
 
+def test_profile_launches_cover_the_phase():
+    """esp_plan_profile_launches: on a batch of three grid sizes (three
+    pipeline lanes) the spread and the gather launch once per lane; the
+    launches' particles and grid points add up to the batch's, every launch
+    takes a positive time, and their sum is within the phase's time plus
+    slack (the per-phase profile runs the same launches back to back)."""
+    sizes = [(300, 14.4, 41), (1000, 20.0, 42), (3000, 31.0, 43)]
+    systems = [W.water_box(n, L, s) for n, L, s in sizes]
+    Ls = [L for _, L, _ in sizes]
+    Ns = [len(q) for _, q in systems]
+    plan = Plan(Ls, Ns, 1e-4)
+    grids = {p.nf for p in plan.params}
+    pos = np.concatenate([p for p, _ in systems])
+    q = np.concatenate([q for _, q in systems])
+    tp, tq, phi, F = _buffers(pos, q)
+    print(f"profile launches: grids {sorted(grids)}", flush=True)
+    for phase in ("spread", "gather"):
+        ls = plan.profile_launches(tp, tq, phi, F, 3, phase)
+        assert len(ls) == min(3, len(grids)), ls
+        assert sum(L["particles"] for L in ls) == sum(Ns)
+        assert sum(L["points"] for L in ls) == sum(p.nf ** 3 for p in plan.params)
+        assert all(L["ms"] > 0 for L in ls)
+        assert all(L["blocks"] > 0 and L["blocks"] % 8 == 0 for L in ls)  # runs of the 8 XCDs
+    with pytest.raises(Exception):
+        plan.profile_launches(tp, tq, phi, F, 1, "fft_x_scale")
+    plan.close()
+
+
 def test_shortrange_coeffs_are_the_split_kernel():
     plan = Plan(31.0, 9000, 1e-4)
     p = plan.params[0]
