@@ -2,6 +2,7 @@
 #include "assembly.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -422,22 +423,25 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     // Systems that ask for the one-block transform
     // and whose half spectrum fits in LDS take it; their energy partial goes
     // to one slot after the x-column items.
-    std::map<std::pair<int, int>, std::vector<int>> by_n;
+    // (ik systems apart: the x pass of AD systems up to n = 64 (FP32) keeps
+    // each column in registers, k_fft_x_reg, 64 columns per block)
+    std::map<std::array<int, 3>, std::vector<int>> by_n;
     for (int s = 0; s < nsys; ++s) {
         const int n = hsys_[s].n;
         const int fused = systems[s].prm.fft_passes == 1 && !hsys_[s].ik && !hsys_[s].p3 &&
                           fft_fused_lds(n, prec) <= kMaxLds;
-        by_n[{n, fused}].push_back(s);
+        by_n[{n, fused, hsys_[s].ik ? 1 : 0}].push_back(s);
         hsys_[s].fin_fft = !fused;  // the plane-pass FFT's last kernel finalizes the energy
     }
-    const int C = fft_x_columns(prec);
     std::vector<int> fused_sys;
     for (auto git = by_n.rbegin(); git != by_n.rend(); ++git) {
         const auto& kv = *git;
-        const int n = kv.first.first, hs = n / 2 + 1;
+        const int n = kv.first[0], hs = n / 2 + 1;
         FftGroup fg{};
         fg.n = n;
-        fg.fused = kv.first.second;
+        fg.fused = kv.first[1];
+        fg.xreg = !fg.fused && !kv.first[2] && fft_x_in_registers(n, prec);
+        const int C = fg.xreg ? kXRegColumns : fft_x_columns(prec);
         fg.plane_off = (int)planes_.size();
         fg.col_off = (int)cols_.size();
         fg.sys_off = (int)fsys_.size();

@@ -411,6 +411,98 @@ __global__ void __launch_bounds__((x_threads<R, N>())) k_fft_x(const SysDesc* __
     if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
 }
 
+// The same Stockham stages on one line held in a thread's registers: element
+// idx of the line is a[idx], and every butterfly, twiddle and store index is
+// that of st_stage with one line of element stride 1, so the results are
+// those of the LDS stages bit for bit.
+template <typename R, int N, int NS, int DIR>
+__device__ __forceinline__ void reg_fft(cplx<R> (&a)[N], const cplx<R>* __restrict__ tw) {
+    if constexpr (NS < N) {
+        constexpr int M = N / NS;
+        constexpr int RAD = M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 3);
+        constexpr int NB = N / RAD;
+        constexpr int SPAN = N / (NS * RAD);
+        cplx<R> b[N];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int jm = j % NS;
+            cplx<R> v[RAD];
+#pragma unroll
+            for (int k = 0; k < RAD; ++k) {
+                cplx<R> x = a[j + k * NB];
+                if constexpr (NS > 1) {
+                    if (k > 0) {
+                        cplx<R> w = tw[k * jm * SPAN];
+                        if constexpr (DIR < 0) w.y = -w.y;
+                        x = cmul(x, w);
+                    }
+                }
+                v[k] = x;
+            }
+            Bfly<R, RAD>::run(v, DIR);
+#pragma unroll
+            for (int k = 0; k < RAD; ++k) b[(j - jm) * RAD + jm + k * NS] = v[k];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) a[i] = b[i];
+        reg_fft<R, N, NS * RAD, DIR>(a, tw);
+    }
+}
+
+// x pass with one column per thread, its N values in registers (no LDS
+// stages, no barriers): forward DFT along x, scaling by p_k with the energy
+// partial, inverse DFT, as k_fft_x and with its arithmetic. One wave per
+// chunk of up to kXRegColumns consecutive flattened (ky, kz) columns; each
+// x-row of the chunk is one contiguous run. Systems with AD forces, FP32
+// grids of 40 to 64 points (fft_x_in_registers).
+template <typename R, int N>
+__global__ void __launch_bounds__(kXRegColumns) k_fft_x_reg(const SysDesc* __restrict__ sys,
+                                                           const int4* __restrict__ items,
+                                                           double* __restrict__ epart, int mode) {
+    constexpr int HS = N / 2 + 1, HALF = N / 2, ROW = N * HS;
+    __shared__ cplx<R> tw[N];
+    __shared__ double red[1];
+    const int4 wi = items[blockIdx.x];
+    const SysDesc& S = sys[wi.x];
+    const int c0 = wi.y, cnt = wi.z, l = threadIdx.x;
+    const cplx<R>* tw_g = reinterpret_cast<const cplx<R>*>(S.tw);
+    for (int i = threadIdx.x; i < N; i += kXRegColumns) tw[i] = tw_g[i];
+    __syncthreads();
+    double e = 0.0;
+    if (l < cnt) {
+        cplx<R>* gp = reinterpret_cast<cplx<R>*>(S.grid) + c0 + l;
+        cplx<R> a[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) a[x] = gload_c(gp, (long long)x * ROW);
+        reg_fft<R, N, 1, +1>(a, tw);
+        if (mode != 1) {
+            const auto TS = gptr(reinterpret_cast<const R*>(S.TS));
+            const auto Tp = gptr(reinterpret_cast<const R*>(S.Tphi));
+            const auto p3 = gptr(reinterpret_cast<const R*>(S.p3));  // non-cubic box: the whole table
+            const R ps = R(S.pscale);
+            const int col = c0 + l;
+            const int ky = col / HS, kz = col - ky * HS;
+            const int my = ky <= HALF ? ky : N - ky;
+            const double wgt = (kz == 0 || kz == HALF) ? 1.0 : 2.0;
+            const R typs = Tp[my] * ps, tkz = Tp[kz];
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+                const int mx = x <= HALF ? x : N - x;
+                // k_fft_x's product, in its order
+                const R p = p3 ? p3[(long long)x * ROW + col] : TS[mx * mx + my * my + kz * kz] * Tp[mx] * typs * tkz;
+                const cplx<R> b = a[x];
+                e += wgt * (double)p * ((double)b.x * (double)b.x + (double)b.y * (double)b.y);
+                a[x] = {b.x * p, b.y * p};
+            }
+            if (mode == 0) reg_fft<R, N, 1, -1>(a, tw);
+        }
+#pragma unroll
+        for (int x = 0; x < N; ++x) gstore_c(gp, (long long)x * ROW, a[x]);
+    }
+    const double tot = block_sum(e, red);
+    if (threadIdx.x == 0) epart[blockIdx.x] = 0.5 * tot;
+}
+
 // ---------------------------------------------------------------------------
 // Whole 3D transform of one system in one block, for grids whose half
 // spectrum fits in LDS (FP32 n <= 32, FP64 n <= 24): halo fold, forward z, y
@@ -665,6 +757,13 @@ static hipError_t fft_n(const Launch& L, const FftGroup& G, int which, int mode,
         k_fwd_zy<R, N><<<G.plane_count, plane_threads<N>(), lds_plane, L.stream>>>(L.sys, L.planes + G.plane_off,
                                                                                    (mode & 3) == 3 ? 0 : 1);
     } else if (which == 1) {
+        if constexpr (sizeof(R) == 4 && N >= 40 && N <= 64) {
+            if (G.xreg) {
+                k_fft_x_reg<R, N><<<G.col_count, kXRegColumns, 0, L.stream>>>(L.sys, L.cols + G.col_off,
+                                                                             L.epart + G.col_off, mode);
+                return hipGetLastError();
+            }
+        }
         const int lds = fft_x_lds(N, L.prec, L.any_ik);
         if ((e = allow_lds(k_fft_x<R, N>, lds)) != hipSuccess) return e;
         k_fft_x<R, N><<<G.col_count, x_threads<R, N>(), lds, L.stream>>>(L.sys, L.cols + G.col_off,

@@ -58,6 +58,7 @@ struct FftGroup {
     int n;
     int lane;                    // the pipeline lane of its systems
     int fused;                   // 1: one block per system for the whole transform
+    int xreg;                    // 1: x pass with one column per thread (k_fft_x_reg)
     int plane_off, plane_count;  // x-plane work items (three-pass path)
     int col_off, col_count;      // x-column chunk work items (three-pass path)
     int sys_off, sys_count;      // system work items (fused path)
@@ -72,6 +73,11 @@ inline bool fft_size_supported(int n) {
 }
 // Columns per x-pass block: 256-byte runs of complex values.
 inline int fft_x_columns(int prec) { return prec == 64 ? 16 : 32; }
+// Grid sizes whose x pass keeps each column in one thread's registers
+// (k_fft_x_reg; systems with AD forces), with its columns per block (one
+// wave): FP32 n in [40, 64]; smaller grids run faster on the LDS stages.
+inline bool fft_x_in_registers(int n, int prec) { return prec == 32 && n >= 40 && n <= 64; }
+constexpr int kXRegColumns = 64;
 // Dynamic LDS bytes of the plane passes (twiddles, one half-spectrum plane,
 // covering tables of the halo fold) and of the x pass.
 inline int fft_plane_lds(int n, int prec) {
