@@ -292,7 +292,9 @@ esp_status esp_plan_shortrange_coeffs(const esp_plan* plan, double* coef, int* n
  * the grid size in [8, 16] whose spread tile and bin histogram fit in the
  * 160 KB LDS) is timed over `reps` full steps on the caller's data (pos, q,
  * phi, F as for esp_longrange_async, device, concatenated in system order)
- * with the other groups held at their current T, and the fastest is kept.
+ * with the other groups held at their current T, in three interleaved
+ * sweeps of the candidates; the candidate with the fastest sweep is kept,
+ * unless the group's current choice is within 2% of it.
  * Where the one-block FFT applies (fft_passes), both FFT paths are timed for
  * every T. The plan is then rebuilt with the choice: its scratch is reallocated and
  * a captured graph is dropped (recaptured on the next graph call). tiles_out

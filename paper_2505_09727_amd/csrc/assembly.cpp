@@ -263,7 +263,7 @@ esp_status LaunchSet::put(T** dev, size_t* cap, const std::vector<T>& v, std::st
 }
 
 esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hipStream_t stream,
-                            std::string& msg) {
+                            std::string& msg, int max_lanes) {
     const int rb = prec == 64 ? 8 : 4;
     const int nsys = (int)systems.size();
     hsys_.assign(nsys, SysDesc{});
@@ -467,7 +467,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     // work so far; work = FFT (systems x n^3 log2 n) plus spread and gather
     // (particles), weighted as measured on MI355X (about 3.1e-6 and 1.0e-4
     // microseconds per unit)
-    lanes_ = std::max(1, std::min<int>(kLanes, (int)fgroups_.size()));
+    lanes_ = std::max(1, std::min<int>(max_lanes, (int)fgroups_.size()));
     std::vector<int> sys_lane(nsys, 0);
     {
         std::vector<double> load(lanes_, 0.0);

@@ -107,13 +107,21 @@ struct SystemSlot {
     float drift = 0.0f;
 };
 
+// Pipeline lanes of a launch set with several FFT grid-size groups: the
+// plan's stream and two side streams, which (with the binning's side stream
+// reused) fit the 4 hardware queues a process gets by default.
+constexpr int kLanes = 3;
+
 // Host and device copies of a launch set.
 class LaunchSet {
   public:
     ~LaunchSet();
     // Build descriptors and work lists for `systems` (same precision) and
     // upload them on `stream`. Device arrays grow as needed.
-    esp_status build(const std::vector<SystemSlot>& systems, int prec, hipStream_t stream, std::string& msg);
+    // max_lanes caps the pipeline lanes (1 for a caller that launches every
+    // group on one stream, as the server does).
+    esp_status build(const std::vector<SystemSlot>& systems, int prec, hipStream_t stream, std::string& msg,
+                     int max_lanes = kLanes);
     // Re-point the particle arrays of system s (no upload).
     void set_io(int s, const void* pos, const void* q, void* phi, void* F);
     // Serving: drift step of system s for the next drift launch (0: none).
@@ -160,9 +168,5 @@ class LaunchSet {
 };
 
 constexpr int kMaxLds = 160 * 1024;
-// Pipeline lanes of a launch set with several FFT grid-size groups: the
-// plan's stream and two side streams, which (with the binning's side stream
-// reused) fit the 4 hardware queues a process gets by default.
-constexpr int kLanes = 3;
 
 }  // namespace esp

@@ -366,7 +366,9 @@ void esp_server::loop() {
                 std::vector<SystemSlot> slots;
                 slots.reserve(active.size());
                 for (auto& r : active) slots.push_back(r->slot);
-                if (ls.build(slots, 32, stream, msg) != ESP_OK) {
+                // one stream: no pipeline lanes (one spread and one gather
+                // launch per window width)
+                if (ls.build(slots, 32, stream, msg, 1) != ESP_OK) {
                     std::lock_guard<std::mutex> lk(mu);
                     fatal = msg;
                     stop = true;
