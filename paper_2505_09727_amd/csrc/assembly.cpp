@@ -397,7 +397,9 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     // A block's binning time grows with its system's size, so with many
     // systems a system above three times the median size of the candidates (and
     // above kSmallAlwaysN) takes the chunked path, which runs beside the
-    // one-block launch, instead of finishing long after the other blocks.
+    // one-block launch, instead of finishing long after the other blocks; in
+    // FP32 so does a system too large to keep its particles in registers
+    // (kSmallKeep), when the chunked path runs anyway.
     int n_split = kSmallMaxN;
     if (n_eligible >= kSmallMinSystems) {
         std::vector<int> ns;
@@ -405,7 +407,10 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             if (d.small) ns.push_back(d.N);
         std::nth_element(ns.begin(), ns.begin() + ns.size() / 2, ns.end());
         n_split = std::max(kSmallAlwaysN, 3 * ns[ns.size() / 2]);
+        const bool chunked = std::any_of(ns.begin(), ns.end(), [&](int N) { return N > n_split; });
+        if (prec == 32 && chunked) n_split = std::min(n_split, std::max(kSmallAlwaysN, kSmallKeep * 1024));
     }
+    int scan_rows_fused = 1;
     for (int s = 0; s < nsys; ++s) {
         SysDesc& d = hsys_[s];
         const int nb = d.tiles1 * d.tiles1 * d.tiles1;
@@ -416,6 +421,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             nb_small_max = std::max(nb_small_max, nb);
         } else {
             nb_max = std::max(nb_max, nb);
+            if (nb > kScanRowsMax || d.npitem > kScanRowsMax) scan_rows_fused = 0;
         }
     }
     // FFT work items grouped by (grid size, path): one launch per group and
@@ -592,6 +598,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
     L_.n_cols = (int)cols_.size();
     L_.hist_lds = nb_max * 4;
     L_.any_ik = any_ik;
+    L_.scan_rows_fused = scan_rows_fused;
     L_.n_small = (int)bsys_.size();
     L_.n_large = nsys - L_.n_small;
     L_.small_lds = (nb_small_max * 32 + 2 * (nb_small_max + 1) + 2 * kSmallRounds) * 4;

@@ -106,7 +106,14 @@ constexpr int kSmallMaxBins = 512;    // ... and bin count are binned by one blo
 constexpr int kSmallRounds = 8192;    // deal rounds a one-block binning can hold
 constexpr int kSmallMinSystems = 64;  // one-block binning pays only with this many systems,
 constexpr int kSmallAlwaysN = 4096;   // or for systems this small (one launch instead of five)
+// FP32 systems up to kSmallKeep x 1024 particles keep each particle's bin
+// coordinates, bin, class and rank in registers from the one-block binning's
+// counting pass to its placing pass, which then computes nothing again and
+// reads no input (9 per thread: the 1024-thread block's 128 registers hold no
+// more without spilling)
+constexpr int kSmallKeep = 9;
 constexpr int kParticleChunk = 1024;  // particles per chunk work item
+constexpr int kScanRowsMax = 64;      // bins and chunks per system for k_scan to scan the rows itself
 constexpr int kChunkThreads = 256;    // threads of a chunk block (4 particles each)
 constexpr int kXcds = 8;              // accelerator complex dies (one L2 each) of the chip
 // LDS bytes of a spread / gather block's window coefficients and their

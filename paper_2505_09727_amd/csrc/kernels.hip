@@ -183,11 +183,42 @@ __global__ void __launch_bounds__(256) k_scan_rows(const SysDesc* __restrict__ s
 // Per system (one block): exclusive scan of the bin totals into the bins'
 // first slots, and the fixed-point scale of the FP32 spread: 2^F with every
 // single term |q w_x w_y w_z| 2^F <= 2^30, so it is exact through int32.
-__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, const double* __restrict__ bpart) {
+// With `rows` (every chunked system has at most kScanRowsMax bins and chunks)
+// the block first does k_scan_rows' work itself, one wave per bin with all of
+// its rows' loads issued first, and keeps the totals in LDS: one launch fewer.
+__global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, const double* __restrict__ bpart,
+                                               int rows) {
     __shared__ int warp_tot[16];
     __shared__ double red[16];
+    __shared__ int tot[kScanRowsMax];
     const SysDesc& S = sys[blockIdx.x];
     if (S.small) return;  // uniform over the block
+    if (rows) {
+        constexpr int RW = kScanRowsMax / 16;  // rows per wave
+        const int nbr = S.tiles1 * S.tiles1 * S.tiles1, np = S.npitem;
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        int v[RW];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int b = wid + 16 * k;
+            v[k] = b < nbr && lane < np ? S.hist[(size_t)b * np + lane] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int b = wid + 16 * k;
+            if (b < nbr) {  // uniform over the wave
+                int x = v[k];
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(x, off, 64);
+                    if (lane >= off) x += y;
+                }
+                if (lane < np) S.hist[(size_t)b * np + lane] = x - v[k];
+                if (lane == 63) tot[b] = x;
+            }
+        }
+        __syncthreads();
+    }
+    auto total = [&](int b) { return rows ? tot[b] : S.bin_start[b]; };
     {
         double qm = 0.0;
         for (int i = threadIdx.x; i < S.npitem; i += blockDim.x) qm = fmax(qm, bpart[4 * (S.pitem_off + i) + 3]);
@@ -203,7 +234,7 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
     const int per = (nb + blockDim.x - 1) / blockDim.x;
     const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
     int run = 0;
-    for (int b = b0; b < b1; ++b) run += S.bin_start[b];
+    for (int b = b0; b < b1; ++b) run += total(b);
     int x = run;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int off = 1; off < 64; off <<= 1) {
@@ -215,7 +246,7 @@ __global__ void __launch_bounds__(1024) k_scan(const SysDesc* __restrict__ sys, 
     int off = x - run;
     for (int w = 0; w < wid; ++w) off += warp_tot[w];
     for (int b = b0; b < b1; ++b) {
-        const int v = S.bin_start[b];
+        const int v = total(b);
         S.bin_start[b] = off;
         off += v;
     }
@@ -928,9 +959,43 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
     for (int i = threadIdx.x; i < nb * 32; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     double sq = 0.0, sa = 0.0, s2 = 0.0, qm = 0.0;
+    constexpr int KK = sizeof(R) == 4 ? kSmallKeep : 1;
+    const bool keep = sizeof(R) == 4 && N <= KK * 1024;  // uniform over the block
+    R kx[KK], ky[KK], kz[KK], kq[KK];
+    int kk[KK];  // rank within (bin, class) << 14 | bin x 32 + class (bins <= 512)
+    if (keep) {
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            const int i = k * 1024 + threadIdx.x;
+            if (i < N) {
+                kx[k] = pos[3 * i + 0];
+                ky[k] = pos[3 * i + 1];
+                kz[k] = pos[3 * i + 2];
+                kq[k] = q[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            const int i = k * 1024 + threadIdx.x;
+            if (i < N) {
+                int c;
+                const BinCoords<R> bc = small_bin_class<R>(S, kx[k], ky[k], kz[k], hp, lo, c);
+                kx[k] = bc.vx;
+                ky[k] = bc.vy;
+                kz[k] = bc.vz;
+                const int bcl = bc.bin * 32 + c;
+                kk[k] = (atomicAdd(&cnt[bcl], 1) << 14) | bcl;
+                const double qq = (double)kq[k];
+                sq += qq;
+                sa += fabs(qq);
+                s2 += qq * qq;
+                qm = fmax(qm, fabs(qq));
+            }
+        }
+    }
     // batches of kSmallBatch particles per thread: every load of a batch is
     // issued before any is used
-    for (int base = 0; base < N; base += kSmallBatch * 1024) {
+    for (int base = 0; !keep && base < N; base += kSmallBatch * 1024) {
         R px[kSmallBatch], py[kSmallBatch], pz[kSmallBatch], pq[kSmallBatch];
 #pragma unroll
         for (int k = 0; k < kSmallBatch; ++k) {
@@ -1040,6 +1105,30 @@ __global__ void __launch_bounds__(1024) k_bin_small(const SysDesc* __restrict__ 
     }
     __syncthreads();
     V* sorted = reinterpret_cast<V*>(S.sorted);
+    if (keep) {
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            const int i = k * 1024 + threadIdx.x;
+            if (i < N) {
+                const int bcl = kk[k] & 16383, r = kk[k] >> 14, b = bcl >> 5, c = bcl & 31;
+                int p = binoff[b];
+                if (deal) {
+                    const int j = rbase[b] + r;
+                    p += rstart[j] + __popc(rmask[j] & ((1u << c) - 1u));
+                } else {
+                    p += cnt[bcl] + r;
+                }
+                V v;
+                v.x = kx[k];
+                v.y = ky[k];
+                v.z = kz[k];
+                v.w = kq[k];
+                sorted[p] = v;
+                S.perm[p] = i;
+            }
+        }
+        return;
+    }
     for (int base = 0; base < N; base += kSmallBatch * 1024) {
         R px[kSmallBatch], py[kSmallBatch], pz[kSmallBatch], pq[kSmallBatch];
         int pr[kSmallBatch];
@@ -1116,11 +1205,11 @@ static hipError_t prepare_t(const Launch& L, int phase, bool with_small) {
             break;
         case 1:
             if (L.n_large == 0) break;
-            if (L.n_titems > 0) {
+            if (L.n_titems > 0 && !L.scan_rows_fused) {
                 k_scan_rows<<<(L.n_titems + 3) / 4, 256, 0, L.stream>>>(L.sys, L.titems, L.n_titems);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             }
-            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.bpart);
+            k_scan<<<L.nsys, 1024, 0, L.stream>>>(L.sys, L.bpart, L.scan_rows_fused);
             break;
         case 2: {
             if (L.n_large == 0) break;

@@ -47,6 +47,7 @@ struct Launch {
     int n_litems;
     double* lpart;        // per local item: local-part energy partial, sum q u^l
     int any_local;        // some system evaluates the local part
+    int scan_rows_fused;  // every chunked system has <= kScanRowsMax bins and chunks: k_scan scans the rows
     int any_fin_kernel;   // some system is finalized by k_finalize (fused FFT), not by k_inv_yz
     int local_cap;        // particles of a bin's halo the local pass stages in LDS
     int local_cells;      // largest halo sub-cell count, (lcs + 2 lR)^3
