@@ -596,18 +596,24 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R(0);
         return;
     }
-    R* ct = reinterpret_cast<R*>(smem_raw + (size_t)E3 * sizeof(A));
-    stage_coef<R, P>(ct, nullptr, reinterpret_cast<const R*>(S.poly), S.degree);
-    for (int i = threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
-    __syncthreads();
-    const int deg = S.degree;
+    // each thread's first particle loads while the tile is cleared, the next
+    // ones while the current one is spread
+    typename Vec4<R>::type vn{};
+    if (beg + (int)threadIdx.x < end) vn = gload4<R>(S.sorted, beg + threadIdx.x);
     // 32-bit: the system's scale over the bin's count rounded up to a power of two
     const R scale = !kFixed ? R(1)
                   : kNarrow ? R(ldexp(S.out[4], -(32 - __clz((unsigned)(end - beg - 1)))))
                             : R(S.out[4]);
-    // each thread's next particle is loaded while the current one is spread
-    typename Vec4<R>::type vn{};
-    if (beg + (int)threadIdx.x < end) vn = gload4<R>(S.sorted, beg + threadIdx.x);
+    R* ct = reinterpret_cast<R*>(smem_raw + (size_t)E3 * sizeof(A));
+    stage_coef<R, P>(ct, nullptr, reinterpret_cast<const R*>(S.poly), S.degree);
+    {
+        // clear the tile 16 bytes at a time, then the tail
+        const int n16 = (int)(((size_t)E3 * sizeof(A)) / 16);
+        for (int i = threadIdx.x; i < n16; i += blockDim.x) reinterpret_cast<uint4*>(lds)[i] = make_uint4(0, 0, 0, 0);
+        for (int i = n16 * (16 / (int)sizeof(A)) + threadIdx.x; i < E3; i += blockDim.x) lds[i] = A(0);
+    }
+    __syncthreads();
+    const int deg = S.degree;
     for (int k = beg + threadIdx.x; k < end; k += blockDim.x) {
         const typename Vec4<R>::type v = vn;
         if (k + (int)blockDim.x < end) vn = gload4<R>(S.sorted, k + blockDim.x);
@@ -645,8 +651,9 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(const SysDesc* __rest
     }
     __syncthreads();
     if constexpr (kNarrow) {
+        // |value| < 2^31 and the scale a power of two: one rounding, as in FP64
         const R inv = R(1) / scale;
-        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((double)(int)lds[i] * (double)inv);
+        for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((int)lds[i]) * inv;
     } else if constexpr (kFixed) {
         const R inv = R(1) / scale;
         for (int i = threadIdx.x; i < E3; i += blockDim.x) out[i] = R((double)(long long)lds[i] * (double)inv);
