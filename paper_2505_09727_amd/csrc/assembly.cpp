@@ -556,7 +556,7 @@ esp_status LaunchSet::build(const std::vector<SystemSlot>& systems, int prec, hi
             // coefficients; gather: the potential tile, the coefficients and
             // their derivatives, the tile's E^2 row offsets
             g.lds_spread = E * E * E * (prec == 32 && P <= 6 ? 4 : 8) + kCoefBytes;
-            g.lds_gather = ((E * E * E * rb + 15) & ~15) + kCoefBytes + E * E * 4;
+            g.lds_gather = ((E * E * E * rb + 15) & ~15) + gather_coef_bytes(P, (int)rb) + E * E * 4;
             if (g.lds_spread > kMaxLds || g.lds_gather > kMaxLds) {
                 msg = "bin tile (T+P)^3 exceeds LDS; reduce tile";
                 return ESP_E_UNSUPPORTED;

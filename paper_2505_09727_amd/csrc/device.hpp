@@ -119,6 +119,9 @@ constexpr int kXcds = 8;              // accelerator complex dies (one L2 each) 
 // LDS bytes of a spread / gather block's window coefficients and their
 // derivatives: 2 x P x 17 reals at most (P <= 12, degree <= 16, 8-byte reals)
 constexpr int kCoefBytes = 2 * 12 * 17 * 8;
+// A gather block's coefficient tables (window and derivative, 17 x P each),
+// 16-byte aligned: the tile row offsets follow them in LDS
+constexpr int gather_coef_bytes(int P, int rb) { return (2 * 17 * P * rb + 15) & ~15; }
 constexpr int kOutDoubles = 8;
 constexpr int kLocalCoefStride = 17;       // padded coefficients per local polynomial (degree <= 16)
 constexpr int kLocalThreads = 256;          // threads of a local-part block

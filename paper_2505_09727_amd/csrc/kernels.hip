@@ -306,9 +306,12 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
 // exceeds kDealRounds keeps the staged order.
 // Threads per spread / gather block (one block per bin). Waves past a bin's
 // last particle exit their particle loop at once, so a fixed block costs
-// little for small bins.
+// little for small bins. The gather's registers (about 120 per thread) allow
+// 16 waves per compute unit: in blocks of 256 threads that is 4 bins at once
+// (the LDS holds 4 FP32 P = 6 tiles), against 2 with blocks of 512 (measured:
+// the ensemble's largest gather launch 48 against 53 us).
 constexpr int kSpreadThreads = 512;
-constexpr int kGatherThreads = 512;
+constexpr int kGatherThreads = 256;
 
 constexpr int kDealRounds = 1024;
 constexpr int kDealRegs = 8;  // staged particles per thread held in registers
@@ -802,7 +805,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __rest
     // tile's row offsets
     R* ct = reinterpret_cast<R*>(smem_raw + (((size_t)E3 * sizeof(R) + 15) & ~size_t(15)));
     R* ctd = ct + 17 * P;
-    int* rows = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(ct) + kCoefBytes);
+    int* rows = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(ct) + gather_coef_bytes(P, (int)sizeof(R)));
     stage_coef<R, P>(ct, ctd, reinterpret_cast<const R*>(S.poly), S.degree);
     if (S.ik) {  // uniform over the block
         gather_ik<R, P>(S, lds, rows, ct, ox, oy, oz, beg, end);
