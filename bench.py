@@ -89,7 +89,9 @@ PEAK_LDS_U32_ATOMICS_GOPS = 32 * 256 * 2.4
 PHASE_KERNEL = {"hist": "k_hist<float>", "scan": "k_scan", "scatter": "k_scatter<float>",
                 "spread": "k_spread<float, {P}>", "fft_zy": "k_fwd_zy<float, {n}>",
                 "fft_x_scale": "k_fft_x<float, {n}>", "fft_yz": "k_inv_yz<float, {n}>",
-                "gather": "k_gather<float, {P}>", "finalize": "k_finalize"}
+                "gather": "k_gather<float, {P}, {BT}>", "finalize": "k_finalize"}
+# threads per gather block: 256 in launches of at least 4 bins per compute unit
+GATHER_MANY_BINS = 4 * 256
 
 
 def measured_traffic(profile, kernel):
@@ -135,7 +137,8 @@ def roofline(phase, ms, systems, prec=32, profile=None, points=None, blocks=None
         r = dict(kernel=phase, bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
                  frac=gbs / PEAK_HBM_GBS, alu_achieved_TFLOPs=tfl)
     P0, n0 = systems[0][2], systems[0][1]
-    kname = PHASE_KERNEL.get(phase, phase).format(P=P0, n=n0).replace("float", "double" if prec == 64 else "float")
+    bt = 256 if (blocks or 0) >= GATHER_MANY_BINS else 512
+    kname = PHASE_KERNEL.get(phase, phase).format(P=P0, n=n0, BT=bt).replace("float", "double" if prec == 64 else "float")
     r["kernel_symbol"] = kname
     # a kernel launched more than once per step (one launch per pipeline
     # lane) has its traffic recorded per launch, keyed by its block count

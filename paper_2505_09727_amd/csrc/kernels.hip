@@ -309,9 +309,13 @@ __global__ void __launch_bounds__(kChunkThreads) k_scatter(const SysDesc* __rest
 // little for small bins. The gather's registers (about 120 per thread) allow
 // 16 waves per compute unit: in blocks of 256 threads that is 4 bins at once
 // (the LDS holds 4 FP32 P = 6 tiles), against 2 with blocks of 512 (measured:
-// the ensemble's largest gather launch 48 against 53 us).
+// the ensemble's largest gather launch 48 against 53 us). A launch of fewer
+// than 4 bins per compute unit keeps 512 threads per bin (the 300,000-atom
+// box's 512 bins: 36 against 46 us with 256).
 constexpr int kSpreadThreads = 512;
-constexpr int kGatherThreads = 256;
+constexpr int kGatherThreadsMany = 256;
+constexpr int kGatherThreadsFew = 512;
+constexpr int kComputeUnits = 256;  // MI355X
 
 constexpr int kDealRounds = 1024;
 constexpr int kDealRegs = 8;  // staged particles per thread held in registers
@@ -725,7 +729,7 @@ __device__ __forceinline__ void load_tile(R* __restrict__ lds, int* __restrict__
 // fractional coordinates and F = -q H^-T g, accumulated over the passes (H^-1
 // upper triangular: pass d adds to components d and beyond).
 template <typename R, int P>
-__device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, int* __restrict__ rows, const R* __restrict__ ct,
+__device__ __forceinline__ void gather_ik(const SysDesc& S, R* __restrict__ lds, int* __restrict__ rows, const R* __restrict__ ct,
                           int ox, int oy, int oz, int beg, int end) {
     const int n = S.n, E = S.E, deg = S.degree;
     const long long G = (long long)n * n * (n + 2);
@@ -785,9 +789,13 @@ __device__ void gather_ik(const SysDesc& S, R* __restrict__ lds, int* __restrict
 
 // Gather (eq. interp) with analytic window derivatives (AD forces):
 // phi_i = u~_i - q_i S(0), F_i = -q_i (n/L) grad_u u~_i, written in caller order.
-template <typename R, int P>
-__global__ void __launch_bounds__(kGatherThreads) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
-                                                           int per) {
+// BT threads per block (see kGatherThreadsMany). FP32 windows of 7 and 8
+// points are held to 128 registers (4 waves per SIMD, two 512-thread blocks
+// per compute unit), which they exceed by a few otherwise; the others keep
+// the compiler's choice (P = 6: 121, and a cap there costs speed).
+template <typename R, int P, int BT>
+__global__ void __launch_bounds__(BT, (sizeof(R) == 4 && P >= 7 && P <= 8) ? 4 : 1) k_gather(const SysDesc* __restrict__ sys, const int2* __restrict__ items,
+                                               int per) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* lds = reinterpret_cast<R*>(smem_raw);
     const int2 wi = xcd_item(items, per);
@@ -1246,12 +1254,18 @@ static hipError_t spread_p(const Launch& L, const Group& G) {
     return hipGetLastError();
 }
 
+template <typename R, int P, int BT>
+static hipError_t gather_bt(const Launch& L, const Group& G) {
+    hipError_t e = allow_lds(k_gather<R, P, BT>, G.lds_gather);
+    if (e != hipSuccess) return e;
+    k_gather<R, P, BT><<<G.count, BT, G.lds_gather, L.stream>>>(L.sys, L.xitems + G.off, G.count / kXcds);
+    return hipGetLastError();
+}
+
 template <typename R, int P>
 static hipError_t gather_p(const Launch& L, const Group& G) {
-    hipError_t e = allow_lds(k_gather<R, P>, G.lds_gather);
-    if (e != hipSuccess) return e;
-    k_gather<R, P><<<G.count, kGatherThreads, G.lds_gather, L.stream>>>(L.sys, L.xitems + G.off, G.count / kXcds);
-    return hipGetLastError();
+    return G.count >= 4 * kComputeUnits ? gather_bt<R, P, kGatherThreadsMany>(L, G)
+                                        : gather_bt<R, P, kGatherThreadsFew>(L, G);
 }
 
 #define ESP_P_SWITCH(FN, R, ...)                        \
