@@ -286,8 +286,8 @@ esp_status esp_batch_longrange(esp_plan* batch, const void* pos, const void* q,
  * The polynomials match L and L' to 1e-12 of their peak. */
 esp_status esp_plan_shortrange_coeffs(const esp_plan* plan, double* coef, int* npieces, int* degree);
 
-/* Autotuner of the bin edge T (spec batching: tile and bin sizes picked
- * by measurement). Systems are grouped by (grid size, window width); for each
+/* Autotuner of the bin edge T (batching: tile and bin sizes picked by
+ * measurement). Systems are grouped by (grid size, window width); for each
  * group, largest total particle count first, every admissible T (divisors of
  * the grid size in [8, 16] whose spread tile and bin histogram fit in the
  * 160 KB LDS) is timed over `reps` full steps on the caller's data (pos, q,
@@ -300,9 +300,11 @@ esp_status esp_plan_shortrange_coeffs(const esp_plan* plan, double* coef, int* n
  * a captured graph is dropped (recaptured on the next graph call). tiles_out
  * (nsys ints, may be NULL) receives the chosen T per system. Blocks until
  * done. Results depend on T only through rounding: the fold of the bins'
- * overlapping tiles into the grid adds in an order set by T (about 1e-6
- * relative in FP32 forces, 1e-15 in FP64); the spread itself sums in fixed
- * point and does not depend on T at all. */
+ * overlapping tiles into the grid adds in an order set by T, and the 32-bit
+ * fixed-point spread (FP32, P <= 6) rounds each term to a unit set by its
+ * bin's particle count (together about 1e-6 relative in FP32 forces, 1e-15 in
+ * FP64). Within a bin the fixed-point sums are exact, so no result depends on
+ * the order of the particles. */
 esp_status esp_plan_autotune(esp_plan* plan, const void* pos, const void* q, void* phi, void* F, int reps,
                              int* tiles_out);
 

@@ -65,8 +65,8 @@ def test_c1_rule_lands_at_the_force_error_minimum(which, request):
     # the error has an interior minimum over [0.9 c, 1.4 c] ...
     i = int(np.argmin(deltas))
     assert 0 < i < len(xs) - 1 and deltas[0] > 3 * deltas[i] and deltas[-1] > 3 * deltas[i]
-    # ... and the E_A argmin sits within 10% of it (measured 2-3%), while the
-    # range the survey once proposed (c1/c = 1.0-1.1) costs 1.5x or more
+    # ... and the E_A argmin sits within 10% of it (measured 2-3%), while a
+    # c1 at or just above c (c1/c = 1.0-1.1) costs 1.2x or more
     assert chosen <= 1.10 * deltas.min(), (prm["c1"] / prm["c"], chosen, xs[i], deltas[i])
     assert min(box.delta(prm, x * prm["c"]) for x in (1.0, 1.05, 1.1)) > 1.2 * chosen
 
